@@ -1,0 +1,307 @@
+"""Seeded synthetic reconstructions (inputs only).
+
+This module produces the *inputs* of the camera-covariance computation:
+cameras, points and the observation index set S (paper, Sec. 3, "Problem
+formulation").  It holds none of the method's arithmetic: no projection, no
+Jacobian, no normal equations.  Camera orientations are built as look-at
+frames and converted to angle-axis with SciPy; visibility uses only camera
+centres and viewing directions.
+
+Both the CPU oracle (through the tests) and the GPU library (through the
+Python binding) consume the same ``Scene`` objects, so neither side generates
+its own inputs.
+
+Camera parameter layout, one row of 9 float64 per camera, in the order the
+paper uses for P_i = {r_i, C_i, c_i, k_i} (Sec. 4.1) extended to two radial
+coefficients:
+
+    r0 r1 r2   angle-axis of the world-to-camera rotation R(r)
+    C0 C1 C2   camera centre in world coordinates
+    f          focal length in pixels
+    k1 k2      radial distortion coefficients
+
+Recipes (all distributions are seeded with numpy's PCG64 ``default_rng``):
+
+* ``tiny_circle``   10 cameras on a circle of radius 10 in the z=0 plane looking
+  at the origin (up = +z); 200 points uniform in a ball of radius 3; every
+  point is seen by 3..6 distinct random cameras; f = 1000*U[0.95,1.05];
+  k1, k2 ~ N(0, 0.1^2).  Z is 90 x 90.
+* ``spiral_slab``   n cameras (default 500) on an Archimedean spiral of three
+  turns at height 8 above the slab [-10,10]^2 x [-2.5,2.5] (radius 2 -> 12,
+  per-axis jitter N(0, 0.2^2)), nadir-looking with a N(0, (2 deg)^2) tilt;
+  m points (default 50 000) uniform in the slab; track length
+  t = 1 + Geometric(p) (mean 6 for p = 0.2, minimum 2, capped at 30), the
+  track's cameras drawn at random from the 2t cameras nearest the point.
+  Z is 9n x 9n (4500 x 4500 by default).
+* ``clustered``     10 clusters of 300 cameras on a ring of radius 40 and
+  500 000 points, Zipf(1.5) track lengths on [2, 30], 2 % of the tracks
+  spanning two adjacent clusters and 5 % of the points placed so far away
+  that their triangulation angle is about 1e-4 rad (near-zero baseline).
+* ``batch_scenes``  256 independent spiral scenes with camera counts
+  log-uniform in [20, 400], 100 points per camera and mean track length 5.
+
+The observed image coordinates (and their 1 px noise) are not generated: a
+first-order covariance does not depend on the residuals (Sec. 3, the normal
+equations), so the library never reads them.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+from scipy.spatial import cKDTree
+from scipy.spatial.transform import Rotation
+
+PRINCIPAL_POINT = (320.0, 240.0)  # 640 x 480 image, fixed, not a parameter
+
+
+@dataclasses.dataclass
+class Scene:
+    """A reconstruction theta = {P, X} with its index set S."""
+
+    cams: np.ndarray       # (n, 9) float64
+    pts: np.ndarray        # (m, 3) float64
+    obs_cam: np.ndarray    # (t,) int32
+    obs_pt: np.ndarray     # (t,) int32
+    obs_info: np.ndarray | None = None  # (t, 3) float64: a, b, c of [[a, b], [b, c]]
+    name: str = ""
+    seed: int = 0
+
+    @property
+    def n_cams(self) -> int:
+        return int(self.cams.shape[0])
+
+    @property
+    def n_pts(self) -> int:
+        return int(self.pts.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_cam.shape[0])
+
+    def subset_points(self, keep: np.ndarray) -> "Scene":
+        """Same cameras, only the points whose mask entry is true."""
+        keep = np.asarray(keep, bool)
+        new_index = -np.ones(self.n_pts, np.int64)
+        new_index[keep] = np.arange(int(keep.sum()))
+        sel = keep[self.obs_pt]
+        info = None if self.obs_info is None else self.obs_info[sel].copy()
+        return Scene(self.cams.copy(), self.pts[keep].copy(),
+                     self.obs_cam[sel].astype(np.int32),
+                     new_index[self.obs_pt[sel]].astype(np.int32), info,
+                     self.name + "-sub", self.seed)
+
+
+# ----------------------------------------------------------------------------
+# helpers (geometry of the synthetic rig only)
+# ----------------------------------------------------------------------------
+
+def _look_at_rotvec(centres: np.ndarray, forward: np.ndarray, up: np.ndarray) -> np.ndarray:
+    """Angle-axis of world-to-camera rotations whose third row is ``forward``."""
+    z = forward / np.linalg.norm(forward, axis=1, keepdims=True)
+    x = np.cross(z, up)
+    bad = np.linalg.norm(x, axis=1) < 1e-9
+    if bad.any():
+        x[bad] = np.cross(z[bad], np.array([1.0, 0.0, 0.0]))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    y = np.cross(z, x)
+    rows = np.stack([x, y, z], axis=1)  # rows are the camera axes in world coords
+    return Rotation.from_matrix(rows).as_rotvec()
+
+
+def _intrinsics(rng: np.random.Generator, n: int) -> np.ndarray:
+    f = 1000.0 * rng.uniform(0.95, 1.05, n)
+    k = rng.normal(0.0, 0.1, (n, 2))
+    return np.column_stack([f, k])
+
+
+def _check_connected(n: int, obs_cam: np.ndarray, obs_pt: np.ndarray) -> None:
+    """Cameras and points must form one connected component (nullity 7)."""
+    m = int(obs_pt.max()) + 1
+    g = coo_matrix((np.ones(obs_cam.size), (obs_cam, n + obs_pt)), shape=(n + m, n + m))
+    ncomp, _ = connected_components(g, directed=False)
+    if ncomp != 1:
+        raise RuntimeError(f"generated scene is not connected ({ncomp} components)")
+
+
+def _finish(rng, cams, pts, tracks, name, seed, with_info) -> Scene:
+    obs_cam = np.concatenate(tracks).astype(np.int32)
+    obs_pt = np.repeat(np.arange(len(tracks)), [len(t) for t in tracks]).astype(np.int32)
+    perm = rng.permutation(obs_cam.size)  # observation order is arbitrary at the boundary
+    obs_cam, obs_pt = obs_cam[perm], obs_pt[perm]
+    _check_connected(cams.shape[0], obs_cam, obs_pt)
+    info = None
+    if with_info:
+        info = random_information(rng, obs_cam.size)
+    return Scene(np.ascontiguousarray(cams, np.float64), np.ascontiguousarray(pts, np.float64),
+                 obs_cam, obs_pt, info, name, seed)
+
+
+def random_information(rng: np.random.Generator, t: int) -> np.ndarray:
+    """Per-observation 2x2 information matrices Sigma_u^-1 (eigenvalues of
+    Sigma_u in [0.5, 2] px^2, random orientation), stored as (a, b, c)."""
+    ang = rng.uniform(0, np.pi, t)
+    ev = rng.uniform(0.5, 2.0, (t, 2))
+    c, s = np.cos(ang), np.sin(ang)
+    # Sigma_u^-1 = R diag(1/ev) R^T
+    l0, l1 = 1.0 / ev[:, 0], 1.0 / ev[:, 1]
+    a = c * c * l0 + s * s * l1
+    b = c * s * (l0 - l1)
+    d = s * s * l0 + c * c * l1
+    return np.column_stack([a, b, d])
+
+
+# ----------------------------------------------------------------------------
+# recipes
+# ----------------------------------------------------------------------------
+
+def tiny_circle(seed: int = 0, n: int = 10, m: int = 200, radius: float = 10.0,
+                ball: float = 3.0, track=(3, 6), with_info: bool = False) -> Scene:
+    """10 cameras on a circle looking at the origin, 200 points in a ball."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(n) / n
+    centres = radius * np.column_stack([np.cos(ang), np.sin(ang), np.zeros(n)])
+    rot = _look_at_rotvec(centres, -centres, np.tile([0.0, 0.0, 1.0], (n, 1)))
+    cams = np.column_stack([rot, centres, _intrinsics(rng, n)])
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = d * (ball * rng.uniform(0, 1, m) ** (1 / 3))[:, None]
+    tracks = [rng.choice(n, size=min(n, int(rng.integers(track[0], track[1] + 1))), replace=False)
+              for _ in range(m)]
+    return _finish(rng, cams, pts, tracks, "tiny_circle", seed, with_info)
+
+
+def _spiral_cameras(rng, n, scale):
+    # Archimedean spiral r = scale*(0.2 + theta/(6 pi)), three turns, cameras at
+    # equal arc-length spacing along it
+    fine = np.linspace(0.0, 6 * np.pi, 20001)
+    r_f = scale * (0.2 + fine / (6 * np.pi))
+    arc = np.concatenate([[0.0], np.cumsum(0.5 * (r_f[1:] + r_f[:-1]) * np.diff(fine))])
+    theta = np.interp(np.linspace(0.0, arc[-1], n), arc, fine)
+    rad = scale * (0.2 + theta / (6 * np.pi))
+    centres = np.column_stack([rad * np.cos(theta), rad * np.sin(theta),
+                               np.full(n, 0.8 * scale)])
+    centres += rng.normal(0.0, 0.02 * scale, (n, 3))
+    tilt = Rotation.from_rotvec(rng.normal(0.0, np.deg2rad(2.0), (n, 3)))
+    forward = tilt.apply(np.array([0.0, 0.0, -1.0]))
+    up = np.column_stack([np.cos(theta), np.sin(theta), np.zeros(n)])  # radial direction
+    rot = _look_at_rotvec(centres, forward, up)
+    return np.column_stack([rot, centres, _intrinsics(rng, n)])
+
+
+def spiral_slab(seed: int = 0, n: int = 500, m: int = 50_000, p_geom: float = 0.2,
+                scale: float = 10.0, with_info: bool = False, max_track: int = 30) -> Scene:
+    """Cameras on a noisy spiral above a slab of points (nadir views).
+
+    With the default ``scale`` of 10 the spiral radius runs 2 -> 12 at height
+    8 and the slab is [-10,10]^2 x [-2.5,2.5].
+    """
+    rng = np.random.default_rng(seed)
+    cams = _spiral_cameras(rng, n, scale)
+    centres = cams[:, 3:6]
+    pts = np.column_stack([rng.uniform(-scale, scale, (m, 2)),
+                           rng.uniform(-0.25 * scale, 0.25 * scale, m)])
+    t = np.minimum(1 + rng.geometric(p_geom, m), min(max_track, n))
+    kmax = int(min(n, 2 * t.max()))
+    tree = cKDTree(centres)
+    _, near = tree.query(pts, k=kmax)
+    near = np.atleast_2d(near)
+    tracks = []
+    for j in range(m):
+        cand = near[j, :min(n, 2 * t[j])]
+        tracks.append(rng.choice(cand, size=t[j], replace=False))
+    return _finish(rng, cams, pts, tracks, f"spiral_slab_n{n}", seed, with_info)
+
+
+def _zipf_lengths(rng, m, s=1.5, lo=2, hi=30):
+    k = np.arange(lo, hi + 1)
+    p = k ** (-s)
+    p /= p.sum()
+    return rng.choice(k, size=m, p=p)
+
+
+def clustered(seed: int = 0, n_clusters: int = 10, per_cluster: int = 300,
+              m: int = 500_000, ring: float = 40.0, frac_cross: float = 0.02,
+              frac_far: float = 0.05, with_info: bool = False) -> Scene:
+    """Clustered groups of cameras with Zipf track lengths and far points."""
+    rng = np.random.default_rng(seed)
+    n = n_clusters * per_cluster
+    ang = 2 * np.pi * np.arange(n_clusters) / n_clusters
+    kc = ring * np.column_stack([np.cos(ang), np.sin(ang), np.zeros(n_clusters)])
+    cl = np.repeat(np.arange(n_clusters), per_cluster)
+    centres = kc[cl] + np.array([0.0, 0.0, 10.0]) + rng.normal(0.0, 3.0, (n, 3))
+    target = kc[cl] + rng.normal(0.0, 1.0, (n, 3))
+    radial = np.column_stack([np.cos(ang[cl]), np.sin(ang[cl]), np.zeros(n)])
+    rot = _look_at_rotvec(centres, target - centres, radial)
+    cams = np.column_stack([rot, centres, _intrinsics(rng, n)])
+    fwd = target - centres
+    fwd /= np.linalg.norm(fwd, axis=1, keepdims=True)
+
+    t = _zipf_lengths(rng, m)
+    kind = rng.uniform(0, 1, m)
+    cross = kind < frac_cross
+    far = (kind >= frac_cross) & (kind < frac_cross + frac_far)
+    home = rng.integers(0, n_clusters, m)
+    pts = kc[home] + np.column_stack([rng.uniform(-6, 6, (m, 2)), rng.uniform(-2, 2, m)])
+    nb = (home + 1) % n_clusters
+    pts[cross] = 0.5 * (kc[home[cross]] + kc[nb[cross]]) + rng.normal(0, 2.0, (int(cross.sum()), 3))
+
+    trees = [cKDTree(centres[cl == c]) for c in range(n_clusters)]
+    base = [np.flatnonzero(cl == c) for c in range(n_clusters)]
+    tracks = [None] * m
+    # local points: 2t nearest cameras of the home cluster
+    for c in range(n_clusters):
+        sel = np.flatnonzero((home == c) & ~cross)
+        if sel.size == 0:
+            continue
+        kmax = int(min(per_cluster, 2 * t[sel].max()))
+        _, near = trees[c].query(pts[sel], k=kmax)
+        near = np.atleast_2d(near)
+        for row, j in enumerate(sel):
+            cand = near[row, :min(per_cluster, 2 * t[j])]
+            tracks[j] = base[c][rng.choice(cand, size=t[j], replace=False)]
+    # cross-cluster tracks: half from each neighbouring cluster
+    for j in np.flatnonzero(cross):
+        a, b = home[j], nb[j]
+        ta = max(1, t[j] // 2)
+        tb = max(1, t[j] - ta)
+        _, na = trees[a].query(pts[j], k=min(per_cluster, 2 * ta))
+        _, nbb = trees[b].query(pts[j], k=min(per_cluster, 2 * tb))
+        na, nbb = np.atleast_1d(na), np.atleast_1d(nbb)
+        tracks[j] = np.concatenate([base[a][rng.choice(na, ta, replace=False)],
+                                    base[b][rng.choice(nbb, tb, replace=False)]])
+    # near-zero-baseline points: pushed far along the mean viewing direction
+    for j in np.flatnonzero(far):
+        cams_j = tracks[j]
+        cc = centres[cams_j].mean(axis=0)
+        d = fwd[cams_j].mean(axis=0)
+        d /= np.linalg.norm(d)
+        spread = np.linalg.norm(centres[cams_j] - cc, axis=1).max() + 1e-3
+        pts[j] = cc + d * spread * 1e4
+    return _finish(rng, cams, pts, tracks, "clustered", seed, with_info)
+
+
+def batch_scenes(seed: int = 1000, count: int = 256, lo: int = 20, hi: int = 400,
+                 pts_per_cam: int = 100, p_geom: float = 0.25) -> list[Scene]:
+    """Independent sub-reconstructions with log-uniform camera counts."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(int)
+    out = []
+    for s, n in enumerate(sizes):
+        scale = 10.0 * math.sqrt(n / 500.0)
+        out.append(spiral_slab(seed + 1 + s, n=int(n), m=int(pts_per_cam * n),
+                               p_geom=p_geom, scale=scale))
+    return out
+
+
+def by_name(name: str, seed: int = 0) -> Scene:
+    if name == "tiny_circle":
+        return tiny_circle(seed)
+    if name == "spiral_slab":
+        return spiral_slab(seed)
+    if name == "clustered":
+        return clustered(seed)
+    raise KeyError(name)
