@@ -1,0 +1,164 @@
+/*
+ * ucov: exact per-camera covariance of a bundle-adjusted reconstruction on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every camera i of a reconstruction, the 9x9
+ * diagonal block of Z^+, the Moore-Penrose inverse of the reduced camera
+ * matrix Z = U - W V^-1 W^T (Polic, Forstner, Pajdla, "Fast and Accurate
+ * Camera Covariance Computation for Large 3D Reconstruction", ECCV 2018:
+ * Sec. 3 for the normal equations and the gauge, Sec. 4.1 for the similarity
+ * nullspace, Sec. 4.2 for the block inversion and the Schur complement).
+ * Z^+ is evaluated as (Z + a Q Q^T)^-1 - Q Q^T / a with Q an orthonormal basis
+ * of the camera rows H_c of the nullspace and a > 0.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every pointer argument is a DEVICE pointer (memory of the context's GPU)
+ *   unless its comment says "host".  The caller owns all inputs and outputs;
+ *   the context owns its workspace, grows it on demand and frees it in
+ *   ucov_destroy.
+ * - Work is enqueued on the context's stream (ucov_set_stream; default: the
+ *   null stream of the device).  Every entry point returns only after its
+ *   work has completed, because it reports device-detected errors.
+ * - Return value: UCOV_OK (0) or a negative UCOV_E* code.  On error the
+ *   outputs are unspecified; ucov_last_error() describes the failure and
+ *   ucov_report.bad_index names the offending observation, point or camera
+ *   where there is one.
+ * - A context may be used by one host thread at a time.
+ * - Matrices are column-major with an explicit leading dimension.
+ *
+ * Scene layout (all float64 unless stated)
+ * ----------------------------------------
+ *   cams[9*i + 0..2]   r_i, angle-axis of the world-to-camera rotation R(r_i)
+ *   cams[9*i + 3..5]   C_i, camera centre
+ *   cams[9*i + 6]      f_i, focal length (pixels)
+ *   cams[9*i + 7..8]   k1_i, k2_i, radial distortion
+ *   pts[3*j + 0..2]    X_j
+ *   obs_cam[o], obs_pt[o]  (int32) camera and point of observation o, any order
+ *   obs_info[3*o+0..2] (a, b, c) of the 2x2 information Sigma_u^-1 =
+ *                      [[a, b], [b, c]]; NULL means identity
+ * The projection is u = f d(rho2) pi + (cx, cy) with pi = x[0:2] / x[2],
+ * x = R(r)(X - C), rho2 = |pi|^2 and d = 1 + k1 rho2 + k2 rho2^2 (Sec. 4.1,
+ * focal length applied after the division); the principal point is a
+ * constant and does not enter the covariance.
+ *
+ * Input rules (violations return UCOV_EINVAL unless noted): n_cams >= 2,
+ * n_pts >= 1, n_obs >= 1; indices in range; finite parameters; positive
+ * definite information blocks; no camera observes a point twice; every
+ * observed point lies in front of its camera (x[2] > 0); every point has at
+ * least two observations (else UCOV_EPOINT).
+ */
+#ifndef UCOV_H
+#define UCOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UCOV_OK       0
+#define UCOV_EINVAL  (-1) /* malformed input */
+#define UCOV_EPOINT  (-2) /* a point block V_j cannot be inverted (bad_index = point) */
+#define UCOV_EGAUGE  (-3) /* Z + aQQ^T is not positive definite: the null space of Z is
+                             not exactly the 7-dimensional similarity gauge (e.g. a
+                             disconnected scene or an unconstrained camera) */
+#define UCOV_ENOCONV (-4) /* refinement did not reach the requested tolerance */
+#define UCOV_EDEVICE (-5) /* HIP runtime failure */
+#define UCOV_ENOMEM  (-6) /* device allocation failed */
+
+/* Precision of the dense inverse (step a4). */
+#define UCOV_FP64     0   /* FP64 Cholesky inverse on FP64 MFMA */
+#define UCOV_FP32_NS  1   /* FP32 MFMA Cholesky inverse + Newton-Schulz with FP64 residuals */
+
+typedef struct ucov_ctx ucov_ctx;
+
+typedef struct {
+  int32_t n_cams;
+  int32_t n_pts;
+  int64_t n_obs;
+  const double *cams;      /* n_cams x 9 */
+  const double *pts;       /* n_pts x 3 */
+  const int32_t *obs_cam;  /* n_obs */
+  const int32_t *obs_pt;   /* n_obs */
+  const double *obs_info;  /* n_obs x 3 or NULL */
+} ucov_scene;
+
+typedef struct {
+  int32_t precision;  /* UCOV_FP64 or UCOV_FP32_NS */
+  int32_t max_iter;   /* Newton-Schulz iterations allowed (UCOV_FP32_NS); 0 = default 6 */
+  double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-12 */
+  double alpha;       /* gauge weight a; 0 = balanced automatic choice */
+} ucov_options;
+
+typedef struct {
+  double alpha;        /* gauge weight used */
+  int32_t bad_index;   /* offending observation / point / camera, -1 if none */
+  int32_t ns_iters;    /* Newton-Schulz iterations performed */
+  double ns_residual;  /* final |I - A X|_F / sqrt(N) (mixed precision only) */
+  int64_t n_pairs;     /* (observation, observation) pairs in the Schur scatter */
+  /* stage times in milliseconds, measured with HIP events on the stream */
+  float ms_structure;  /* index sorting and pair binning */
+  float ms_schur;      /* Jacobians, point blocks, Z assembly (steps a1, a2) */
+  float ms_gauge;      /* nullspace, orthonormalisation, scaling (step a3) */
+  float ms_inverse;    /* dense factorisation and inversion (step a4) */
+  float ms_extract;    /* covariance block extraction (step a4) */
+} ucov_report;
+
+/* Create a context on HIP device `device`.  Returns UCOV_EDEVICE if the
+ * device cannot be selected. */
+int ucov_create(ucov_ctx **ctx, int device);
+
+/* Use `stream` (a hipStream_t; NULL = null stream) for subsequent calls. */
+int ucov_set_stream(ucov_ctx *ctx, void *stream);
+
+/* Release the context and its workspace. */
+void ucov_destroy(ucov_ctx *ctx);
+
+/* Per-camera covariance blocks, the whole hot path (steps a1-a4).
+ * cov_out: n_cams x 81 float64, block i row-major at cov_out + 81*i; it is
+ * the diagonal block of Z^+ for the parameters (r, C, f, k1, k2) of camera i.
+ * opt may be NULL (defaults); rep may be NULL. */
+int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
+                           const ucov_options *opt, double *cov_out,
+                           ucov_report *rep);
+
+/* Step a1 alone: per-observation Jacobian blocks of the projection (Sec. 4.1),
+ * in the caller's observation order, unweighted by obs_info.
+ * jp: n_obs x 18 (2x9 row-major per observation, columns r, C, f, k1, k2);
+ * jx: n_obs x 6 (2x3 row-major per observation). */
+int ucov_jacobians(ucov_ctx *ctx, const ucov_scene *scene, double *jp, double *jx);
+
+/* Steps a1-a2: the reduced camera matrix Z = U - W V^-1 W^T (Sec. 4.2,
+ * Schur complement of the point block), written densely (both triangles)
+ * into z, an N x N column-major matrix with leading dimension ldz >= N,
+ * N = 9 n_cams. */
+int ucov_reduced_camera_matrix(ucov_ctx *ctx, const ucov_scene *scene,
+                               double *z, int64_t ldz, ucov_report *rep);
+
+/* Step a3: the camera rows H_c of the similarity nullspace (Sec. 4.1,
+ * column order translation, rotation, scale; rotation block from
+ * J_r H_r = B) and an orthonormal basis Q of their span.
+ * hc, q: N x 7 column-major with leading dimension N (either may be NULL). */
+int ucov_gauge_basis(ucov_ctx *ctx, const ucov_scene *scene, double *hc, double *q);
+
+/* Step a4 alone: diagonal 9x9 blocks of Z^+ = (Z + a QQ^T)^-1 - QQ^T/a for a
+ * caller-supplied symmetric positive semi-definite z (N x N, column-major,
+ * leading dimension ldz, only the lower triangle is read) whose null space is
+ * spanned by the orthonormal columns of q (N x 7, leading dimension N).
+ * N must be a multiple of 9.  alpha <= 0 selects the balanced weight.
+ * cov_out: (N/9) x 81 as in ucov_camera_covariance. */
+int ucov_pinv_blocks(ucov_ctx *ctx, int64_t n, const double *z, int64_t ldz,
+                     const double *q, const ucov_options *opt, double *cov_out,
+                     ucov_report *rep);
+
+/* Text for an error code; description of the last failure on this context. */
+const char *ucov_strerror(int code);
+const char *ucov_last_error(const ucov_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UCOV_H */

@@ -1,0 +1,226 @@
+"""ctypes binding of the ucov C-ABI (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``lib/libucov.so``; this module
+only passes device pointers of torch tensors and the current HIP stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libucov.so")
+
+OK, EINVAL, EPOINT, EGAUGE, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {EINVAL: "EINVAL", EPOINT: "EPOINT", EGAUGE: "EGAUGE", ENOCONV: "ENOCONV",
+               EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
+FP64, FP32_NS = 0, 1
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n_cams", ctypes.c_int32), ("n_pts", ctypes.c_int32), ("n_obs", ctypes.c_int64),
+                ("cams", ctypes.c_void_p), ("pts", ctypes.c_void_p),
+                ("obs_cam", ctypes.c_void_p), ("obs_pt", ctypes.c_void_p),
+                ("obs_info", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("bad_index", ctypes.c_int32),
+                ("ns_iters", ctypes.c_int32), ("ns_residual", ctypes.c_double),
+                ("n_pairs", ctypes.c_int64),
+                ("ms_structure", ctypes.c_float), ("ms_schur", ctypes.c_float),
+                ("ms_gauge", ctypes.c_float), ("ms_inverse", ctypes.c_float),
+                ("ms_extract", ctypes.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covariance",
+           "ucov_jacobians", "ucov_reduced_camera_matrix", "ucov_gauge_basis",
+           "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"ucov HIP library not built: {path} is missing "
+                          "(run __graft_entry__.build() or python paper_1808_02414_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ucov_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int]),
+        "ucov_set_stream": (ctypes.c_int, [P, P]),
+        "ucov_destroy": (None, [P]),
+        "ucov_camera_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), ctypes.POINTER(Options),
+                                                  P, ctypes.POINTER(Report)]),
+        "ucov_jacobians": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
+        "ucov_reduced_camera_matrix": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, I64,
+                                                      ctypes.POINTER(Report)]),
+        "ucov_gauge_basis": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
+        "ucov_pinv_blocks": (ctypes.c_int, [P, I64, P, I64, P, ctypes.POINTER(Options), P,
+                                            ctypes.POINTER(Report)]),
+        "ucov_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "ucov_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    del I32, D
+    _lib = lib
+    return lib
+
+
+class UcovError(RuntimeError):
+    def __init__(self, code: int, message: str, index: int = -1):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {message}")
+        self.code = code
+        self.kind = ERROR_NAMES.get(code, str(code))
+        self.index = index
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("ucov needs a GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+class DeviceScene:
+    """A reconstruction resident in device memory (torch tensors)."""
+
+    def __init__(self, cams, pts, obs_cam, obs_pt, obs_info=None):
+        self.cams, self.pts, self.obs_cam, self.obs_pt, self.obs_info = cams, pts, obs_cam, obs_pt, obs_info
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda:0"):
+        torch = _torch()
+
+        def t(a, dt):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+
+        info = None if scene.obs_info is None else t(scene.obs_info, torch.float64)
+        return cls(t(scene.cams, torch.float64), t(scene.pts, torch.float64),
+                   t(scene.obs_cam, torch.int32), t(scene.obs_pt, torch.int32), info)
+
+    @property
+    def n_cams(self):
+        return int(self.cams.shape[0])
+
+    def struct(self) -> Scene:
+        for a in (self.cams, self.pts, self.obs_cam, self.obs_pt):
+            assert a.is_cuda and a.is_contiguous()
+        return Scene(self.cams.shape[0], self.pts.shape[0], self.obs_cam.shape[0],
+                     self.cams.data_ptr(), self.pts.data_ptr(), self.obs_cam.data_ptr(),
+                     self.obs_pt.data_ptr(),
+                     None if self.obs_info is None else self.obs_info.data_ptr())
+
+
+class Context:
+    """One ucov context on one device; calls use torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.torch = _torch()
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = self.lib.ucov_create(ctypes.byref(h), device)
+        if rc != OK:
+            raise UcovError(rc, "ucov_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ucov_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.ucov_set_stream(self.h, ctypes.c_void_p(s))
+
+    def _check(self, rc, rep=None):
+        if rc != OK:
+            msg = self.lib.ucov_last_error(self.h).decode()
+            raise UcovError(rc, msg, rep.bad_index if rep is not None else -1)
+
+    def camera_covariance(self, scene: DeviceScene, precision=FP64, alpha=0.0, tol=0.0,
+                          max_iter=0, out=None):
+        """(n, 9, 9) float64 covariance blocks on the device, and the report."""
+        torch = self.torch
+        n = scene.n_cams
+        if out is None:
+            out = torch.empty((n, 9, 9), dtype=torch.float64, device=scene.cams.device)
+        opt = Options(precision, max_iter, tol, alpha)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        rc = self.lib.ucov_camera_covariance(self.h, ctypes.byref(sc), ctypes.byref(opt),
+                                             out.data_ptr(), ctypes.byref(rep))
+        self._check(rc, rep)
+        return out, rep.as_dict()
+
+    def jacobians(self, scene: DeviceScene):
+        torch = self.torch
+        t = scene.obs_cam.shape[0]
+        jp = torch.empty((t, 2, 9), dtype=torch.float64, device=scene.cams.device)
+        jx = torch.empty((t, 2, 3), dtype=torch.float64, device=scene.cams.device)
+        self._stream()
+        sc = scene.struct()
+        self._check(self.lib.ucov_jacobians(self.h, ctypes.byref(sc), jp.data_ptr(), jx.data_ptr()))
+        return jp, jx
+
+    def reduced_camera_matrix(self, scene: DeviceScene):
+        torch = self.torch
+        N = 9 * scene.n_cams
+        z = torch.empty((N, N), dtype=torch.float64, device=scene.cams.device)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        self._check(self.lib.ucov_reduced_camera_matrix(self.h, ctypes.byref(sc), z.data_ptr(), N,
+                                                        ctypes.byref(rep)), rep)
+        return z.T, rep.as_dict()  # column-major storage
+
+    def gauge_basis(self, scene: DeviceScene):
+        torch = self.torch
+        N = 9 * scene.n_cams
+        hc = torch.empty((7, N), dtype=torch.float64, device=scene.cams.device)
+        q = torch.empty((7, N), dtype=torch.float64, device=scene.cams.device)
+        self._stream()
+        sc = scene.struct()
+        self._check(self.lib.ucov_gauge_basis(self.h, ctypes.byref(sc), hc.data_ptr(), q.data_ptr()))
+        return hc.T, q.T
+
+    def pinv_blocks(self, z, q, alpha=0.0, precision=FP64):
+        """Diagonal 9x9 blocks of Z^+ for a symmetric z (N, N) with null space
+        spanned by the orthonormal columns of q (N, 7)."""
+        torch = self.torch
+        N = z.shape[0]
+        zc = z.contiguous()  # symmetric: row-major storage is its own column-major form
+        qc = q.T.contiguous()
+        out = torch.empty((N // 9, 9, 9), dtype=torch.float64, device=z.device)
+        opt = Options(precision, 0, 0.0, alpha)
+        rep = Report()
+        self._stream()
+        self._check(self.lib.ucov_pinv_blocks(self.h, N, zc.data_ptr(), N, qc.data_ptr(),
+                                              ctypes.byref(opt), out.data_ptr(), ctypes.byref(rep)), rep)
+        return out, rep.as_dict()

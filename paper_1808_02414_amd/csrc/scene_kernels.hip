@@ -1,0 +1,890 @@
+// Scene stage of the camera covariance (steps a1-a3):
+//   * observations grouped by point (counting sort on device),
+//   * per-observation projection Jacobians (paper Sec. 4.1, projection),
+//   * per-point 3x3 blocks V_j and their FP64 inverses (Sec. 4.2, A_p),
+//   * camera-pair binning of the Schur-complement terms and their reduction
+//     into Z = U - W V^-1 W^T (Sec. 4.2, Schur complement),
+//   * the camera rows of the similarity nullspace with the rotation block
+//     from J_r H_r = B (Sec. 4.1) and its Cholesky-QR2 orthonormalisation,
+//   * Jacobi scaling of Z + a QQ^T (Sec. 4.2, conditioning).
+#include "ucov_internal.h"
+#include "../../include/ucov.h"
+
+namespace ucov {
+
+namespace {
+
+constexpr int kBlk = 256;
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+__device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
+
+// ---------------------------------------------------------------------------
+// fills and an exclusive scan of int32 counts into int64 offsets
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int64_t wave_incl_scan(int64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of the per-thread totals; returns the thread's
+// exclusive prefix and writes the block total into *total.
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t *total) {
+  __shared__ int64_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    int64_t w = lane < kScanThreads / 64 ? wsum[lane] : 0;
+    int64_t wi = wave_incl_scan(w);
+    if (lane < kScanThreads / 64) wsum[lane] = wi - w;
+    if (lane == kScanThreads / 64 - 1) *total = wi;
+  }
+  __syncthreads();
+  int64_t r = inc - v + wsum[wid];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t *in, int64_t *out,
+                                                            int64_t len, int64_t *sums) {
+  __shared__ int64_t total;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < len) ? (int64_t)in[base + k] : 0;
+    s += v[k];
+  }
+  int64_t pre = block_excl_scan(s, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < len) out[base + k] = pre;
+    pre += v[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the tile sums, total at sums[ntiles]
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t *sums, int64_t ntiles) {
+  __shared__ int64_t total;
+  int64_t carry = 0;
+  for (int64_t b = 0; b < ntiles; b += kScanThreads) {
+    int64_t i = b + threadIdx.x;
+    int64_t v = i < ntiles ? sums[i] : 0;
+    int64_t pre = block_excl_scan(v, &total);
+    if (i < ntiles) sums[i] = carry + pre;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[ntiles] = carry;
+}
+
+__global__ void k_scan_add(int64_t *out, int64_t len, const int64_t *sums, int64_t ntiles) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) out[i] += sums[i / kScanTile];
+  if (i == 0) out[len] = sums[ntiles];
+}
+
+// ---------------------------------------------------------------------------
+// observations grouped by point
+// ---------------------------------------------------------------------------
+__global__ void k_count_points(SceneDev sc, int32_t *cnt_p, DevStatus *ds) {
+  int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= sc.t) return;
+  int c = sc.oc[o], j = sc.op[o];
+  if (c < 0 || c >= sc.n || j < 0 || j >= sc.m) {
+    report_error(ds, UCOV_EINVAL, (int)o);
+    return;
+  }
+  atomicAdd(&cnt_p[j], 1);
+}
+
+__global__ void k_fill_slots(SceneDev sc, const int64_t *ptr_p, int32_t *cur_p,
+                             int32_t *slot_obs) {
+  int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= sc.t) return;
+  int c = sc.oc[o], j = sc.op[o];
+  if (c < 0 || c >= sc.n || j < 0 || j >= sc.m) return;
+  int64_t pos = ptr_p[j] + atomicAdd(&cur_p[j], 1);
+  slot_obs[pos] = (int32_t)o;
+}
+
+// One thread per point: order its observations by camera, reject duplicate
+// cameras and points with fewer than two observations.
+__global__ void k_sort_points(SceneDev sc, const int64_t *ptr_p, int32_t *slot_obs,
+                              int32_t *slot_cam, int32_t *slot_pt, DevStatus *ds) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sc.m) return;
+  int64_t p0 = ptr_p[j], p1 = ptr_p[j + 1];
+  if (p1 - p0 < 2) {
+    report_error(ds, UCOV_EPOINT, j);
+  }
+  // insertion sort of the (small) segment by camera id
+  for (int64_t a = p0 + 1; a < p1; ++a) {
+    int32_t o = slot_obs[a];
+    int32_t c = sc.oc[o];
+    int64_t b = a - 1;
+    while (b >= p0 && sc.oc[slot_obs[b]] > c) {
+      slot_obs[b + 1] = slot_obs[b];
+      --b;
+    }
+    slot_obs[b + 1] = o;
+  }
+  int32_t prev = -1;
+  for (int64_t a = p0; a < p1; ++a) {
+    int32_t c = sc.oc[slot_obs[a]];
+    if (c == prev) report_error(ds, UCOV_EINVAL, slot_obs[a]);
+    prev = c;
+    slot_cam[a] = c;
+    slot_pt[a] = j;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step a1: projection Jacobians (hand-derived, FP64)
+// ---------------------------------------------------------------------------
+struct Jac {
+  double jp[2][9];
+  double jx[2][3];
+  double x[3];
+};
+
+// u = f d pi + c0, pi = x[0:2]/x[2], x = R(r)(X - C), d = 1 + k1 rho2 + k2 rho2^2.
+//   du/dpi  = f (d I + 2 (k1 + 2 k2 rho2) pi pi^T)
+//   dpi/dx  = [[1, 0, -pi0], [0, 1, -pi1]] / x2
+//   dx/dX   = R,  dx/dC = -R,  dx/dr = -[x]x J_l(r)
+// with J_l(r) = I + (1 - cos t)/t^2 [r]x + (t - sin t)/t^3 [r]x^2 the left
+// Jacobian of SO(3), and du/df = d pi, du/dk1 = f rho2 pi, du/dk2 = f rho2^2 pi.
+__device__ inline void projection_jacobian(const double *cam, const double *X, Jac &J) {
+  const double r0 = cam[0], r1 = cam[1], r2 = cam[2];
+  const double t2 = r0 * r0 + r1 * r1 + r2 * r2;
+  double a, b, c;  // sin t / t, (1 - cos t)/t^2, (t - sin t)/t^3
+  if (t2 < 1e-4) {
+    // Taylor series in t^2 (truncation below 1e-20 for t < 0.01)
+    a = 1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 + t2 / 362880)));
+    b = 0.5 + t2 * (-1.0 / 24 + t2 * (1.0 / 720 + t2 * (-1.0 / 40320 + t2 / 3628800)));
+    c = 1.0 / 6 + t2 * (-1.0 / 120 + t2 * (1.0 / 5040 + t2 * (-1.0 / 362880 + t2 / 39916800)));
+  } else {
+    const double t = sqrt(t2);
+    double s, co, sh, chh;
+    sincos(t, &s, &co);
+    sincos(0.5 * t, &sh, &chh);
+    a = s / t;
+    b = 2.0 * sh * sh / t2;  // (1 - cos t) / t^2 without cancellation
+    c = (t - s) / (t2 * t);
+  }
+  // K = [r]x, R = I + a K + b K^2
+  const double K[3][3] = {{0, -r2, r1}, {r2, 0, -r0}, {-r1, r0, 0}};
+  double K2[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      K2[i][j] = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+  double R[3][3], Jl[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double id = (i == j) ? 1.0 : 0.0;
+      R[i][j] = id + a * K[i][j] + b * K2[i][j];
+      Jl[i][j] = id + b * K[i][j] + c * K2[i][j];
+    }
+  const double v0 = X[0] - cam[3], v1 = X[1] - cam[4], v2 = X[2] - cam[5];
+  double x[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x[i] = R[i][0] * v0 + R[i][1] * v1 + R[i][2] * v2;
+  J.x[0] = x[0];
+  J.x[1] = x[1];
+  J.x[2] = x[2];
+  const double iz = 1.0 / x[2];
+  const double p0 = x[0] * iz, p1 = x[1] * iz;
+  const double rho2 = p0 * p0 + p1 * p1;
+  const double f = cam[6], k1 = cam[7], k2 = cam[8];
+  const double d = 1.0 + k1 * rho2 + k2 * rho2 * rho2;
+  const double e = 2.0 * (k1 + 2.0 * k2 * rho2);
+  // du/dpi (symmetric 2x2)
+  const double D00 = f * (d + e * p0 * p0), D01 = f * e * p0 * p1, D11 = f * (d + e * p1 * p1);
+  // G = du/dx = du/dpi * dpi/dx (2x3)
+  double G[2][3];
+  G[0][0] = D00 * iz;
+  G[0][1] = D01 * iz;
+  G[0][2] = -(D00 * p0 + D01 * p1) * iz;
+  G[1][0] = D01 * iz;
+  G[1][1] = D11 * iz;
+  G[1][2] = -(D01 * p0 + D11 * p1) * iz;
+  // dx/dr = -[x]x Jl
+  const double Xs[3][3] = {{0, -x[2], x[1]}, {x[2], 0, -x[0]}, {-x[1], x[0], 0}};
+  double DR[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      DR[i][j] = -(Xs[i][0] * Jl[0][j] + Xs[i][1] * Jl[1][j] + Xs[i][2] * Jl[2][j]);
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double gr = G[p][0] * DR[0][j] + G[p][1] * DR[1][j] + G[p][2] * DR[2][j];
+      const double gx = G[p][0] * R[0][j] + G[p][1] * R[1][j] + G[p][2] * R[2][j];
+      J.jp[p][j] = gr;
+      J.jp[p][3 + j] = -gx;
+      J.jx[p][j] = gx;
+    }
+  }
+  J.jp[0][6] = d * p0;
+  J.jp[1][6] = d * p1;
+  J.jp[0][7] = f * rho2 * p0;
+  J.jp[1][7] = f * rho2 * p1;
+  J.jp[0][8] = f * rho2 * rho2 * p0;
+  J.jp[1][8] = f * rho2 * rho2 * p1;
+}
+
+__device__ inline bool finite9(const double *v, int k) {
+  for (int i = 0; i < k; ++i)
+    if (!isfinite(v[i])) return false;
+  return true;
+}
+
+// One thread per slot: Jacobians, whitened by the upper Cholesky factor L of
+// the information block (L^T L = Sigma_u^-1), written into the slot record.
+// Only the first ptr_p[m] slots are filled (observations with out-of-range
+// indices are never placed), so every slot loop is bounded by that count.
+__global__ void k_jacobians(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_obs,
+                            const int32_t *slot_cam, const int32_t *slot_pt, double *rec,
+                            double *jp_out, double *jx_out, DevStatus *ds) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ptr_p[sc.m]) return;
+  const int32_t o = slot_obs[s];
+  const int i = slot_cam[s], j = slot_pt[s];
+  double cam[9], X[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cam[k] = sc.cams[9 * (int64_t)i + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) X[k] = sc.pts[3 * (int64_t)j + k];
+  if (!finite9(cam, 9) || !finite9(X, 3)) {
+    report_error(ds, UCOV_EINVAL, o);
+    return;
+  }
+  double l00 = 1.0, l01 = 0.0, l11 = 1.0;
+  if (sc.info) {
+    const double ia = sc.info[3 * (int64_t)o], ib = sc.info[3 * (int64_t)o + 1],
+                 ic = sc.info[3 * (int64_t)o + 2];
+    if (!(ia > 0.0) || !(ia * ic - ib * ib > 0.0) || !isfinite(ia + ib + ic)) {
+      report_error(ds, UCOV_EINVAL, o);
+      return;
+    }
+    l00 = sqrt(ia);
+    l01 = ib / l00;
+    l11 = sqrt(ic - l01 * l01);
+  }
+  Jac J;
+  projection_jacobian(cam, X, J);
+  if (!(J.x[2] > 0.0)) {
+    report_error(ds, UCOV_EINVAL, o);
+    return;
+  }
+  if (jp_out) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) jp_out[18 * (int64_t)o + 9 * p + k] = J.jp[p][k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) jx_out[6 * (int64_t)o + 3 * p + k] = J.jx[p][k];
+    }
+  }
+  double *r = rec + s * kRec;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    r[kRecJP + k] = l00 * J.jp[0][k] + l01 * J.jp[1][k];
+    r[kRecJP + 9 + k] = l11 * J.jp[1][k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[kRecJX + k] = l00 * J.jx[0][k] + l01 * J.jx[1][k];
+    r[kRecJX + 3 + k] = l11 * J.jx[1][k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step a2 (points): V_j = sum J_X^T J_X, FP64 Cholesky inverse, Y = J_X V^-1
+// ---------------------------------------------------------------------------
+// A point block is rejected when its Cholesky factor does not exist or its
+// smallest squared pivot is at most 1e-14 times its trace.
+__global__ void k_point_blocks(SceneDev sc, const int64_t *ptr_p, double *rec, DevStatus *ds) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sc.m) return;
+  const int64_t p0 = ptr_p[j], p1 = ptr_p[j + 1];
+  if (p1 - p0 < 2) return;
+  double v00 = 0, v01 = 0, v02 = 0, v11 = 0, v12 = 0, v22 = 0;
+  for (int64_t s = p0; s < p1; ++s) {
+    const double *x = rec + s * kRec + kRecJX;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const double a = x[3 * p], b = x[3 * p + 1], c = x[3 * p + 2];
+      v00 += a * a;
+      v01 += a * b;
+      v02 += a * c;
+      v11 += b * b;
+      v12 += b * c;
+      v22 += c * c;
+    }
+  }
+  const double tr = v00 + v11 + v22;
+  const double thr = 1e-14 * tr;
+  // V = L L^T
+  const double d0 = v00;
+  if (!(d0 > thr)) {
+    report_error(ds, UCOV_EPOINT, j);
+    return;
+  }
+  const double L00 = sqrt(d0);
+  const double L10 = v01 / L00, L20 = v02 / L00;
+  const double d1 = v11 - L10 * L10;
+  if (!(d1 > thr)) {
+    report_error(ds, UCOV_EPOINT, j);
+    return;
+  }
+  const double L11 = sqrt(d1);
+  const double L21 = (v12 - L20 * L10) / L11;
+  const double d2 = v22 - L20 * L20 - L21 * L21;
+  if (!(d2 > thr)) {
+    report_error(ds, UCOV_EPOINT, j);
+    return;
+  }
+  const double L22 = sqrt(d2);
+  // M = L^-1 (lower)
+  const double M00 = 1.0 / L00, M11 = 1.0 / L11, M22 = 1.0 / L22;
+  const double M10 = -L10 * M00 * M11;
+  const double M21 = -L21 * M11 * M22;
+  const double M20 = -(L20 * M00 + L21 * M10) * M22;
+  // V^-1 = M^T M
+  const double w00 = M00 * M00 + M10 * M10 + M20 * M20;
+  const double w01 = M10 * M11 + M20 * M21;
+  const double w02 = M20 * M22;
+  const double w11 = M11 * M11 + M21 * M21;
+  const double w12 = M21 * M22;
+  const double w22 = M22 * M22;
+  for (int64_t s = p0; s < p1; ++s) {
+    double *r = rec + s * kRec;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const double a = r[kRecJX + 3 * p], b = r[kRecJX + 3 * p + 1], c = r[kRecJX + 3 * p + 2];
+      r[kRecY + 3 * p + 0] = a * w00 + b * w01 + c * w02;
+      r[kRecY + 3 * p + 1] = a * w01 + b * w11 + c * w12;
+      r[kRecY + 3 * p + 2] = a * w02 + b * w12 + c * w22;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// camera-pair bins: every ordered pair (a, b) of observations of one point
+// with cam(a) >= cam(b) contributes to block Z(cam a, cam b)
+// ---------------------------------------------------------------------------
+__global__ void k_pair_count(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
+                             const int32_t *slot_pt, int32_t *bin_cnt) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ptr_p[sc.m]) return;
+  const int64_t p0 = ptr_p[slot_pt[a]];
+  const int64_t base = tri(slot_cam[a]);
+  for (int64_t b = p0; b <= a; ++b) atomicAdd(&bin_cnt[base + slot_cam[b]], 1);
+}
+
+__global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
+                            const int32_t *slot_pt, const int64_t *bin_ptr, int32_t *bin_cur,
+                            int2 *pairs) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ptr_p[sc.m]) return;
+  const int64_t p0 = ptr_p[slot_pt[a]];
+  const int64_t base = tri(slot_cam[a]);
+  for (int64_t b = p0; b <= a; ++b) {
+    const int64_t bin = base + slot_cam[b];
+    const int64_t pos = bin_ptr[bin] + atomicAdd(&bin_cur[bin], 1);
+    pairs[pos] = make_int2((int)a, (int)b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per camera: diagonal block Z_ii and the rotation rows of the nullspace
+// ---------------------------------------------------------------------------
+constexpr int kDiagVals = 45 + 6 + 9;  // Z_ii upper triangle, J_r^T J_r, J_r^T B
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Z_ii = sum over the observations a of camera i of J_P^T (I - Y J_X^T) J_P
+// (whitened), i.e. U_i minus the point-eliminated terms.  The rotation
+// nullspace block solves J_r H_r = B in least squares over the camera's
+// observation rows, B = -J_X [X_j - C_i]x (the known rows of H in the rotation
+// columns are [C_i]x for the centre and [X_j]x for the points, and J_C = -J_X).
+__global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t *bin_ptr,
+                                                    const int2 *pairs, const double *rec,
+                                                    const int32_t *slot_pt, double *zdiag,
+                                                    double *hc, DevStatus *ds) {
+  const int i = blockIdx.x;
+  const int64_t bin = tri(i) + i;
+  const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
+  double acc[kDiagVals];
+#pragma unroll
+  for (int k = 0; k < kDiagVals; ++k) acc[k] = 0.0;
+  const double C0 = sc.cams[9 * (int64_t)i + 3], C1 = sc.cams[9 * (int64_t)i + 4],
+               C2 = sc.cams[9 * (int64_t)i + 5];
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int a = pairs[e].x;
+    const double *r = rec + (int64_t)a * kRec;
+    double jp[2][9], jx[2][3], y[2][3];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) jp[p][k] = r[kRecJP + 9 * p + k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        jx[p][k] = r[kRecJX + 3 * p + k];
+        y[p][k] = r[kRecY + 3 * p + k];
+      }
+    }
+    // M = I - Y J_X^T (2x2, symmetric)
+    double M[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        M[p][q] = (p == q ? 1.0 : 0.0) - (y[p][0] * jx[q][0] + y[p][1] * jx[q][1] + y[p][2] * jx[q][2]);
+    double T[2][9];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) T[p][k] = M[p][0] * jp[0][k] + M[p][1] * jp[1][k];
+    int idx = 0;
+#pragma unroll
+    for (int rr = 0; rr < 9; ++rr)
+#pragma unroll
+      for (int cc = rr; cc < 9; ++cc) acc[idx++] += jp[0][rr] * T[0][cc] + jp[1][rr] * T[1][cc];
+    // rotation nullspace normal equations
+    const int j = slot_pt[a];
+    const double v0 = sc.pts[3 * (int64_t)j] - C0, v1 = sc.pts[3 * (int64_t)j + 1] - C1,
+                 v2 = sc.pts[3 * (int64_t)j + 2] - C2;
+    double B[2][3];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      // -(jx [v]x): row p of jx times [v]x, negated
+      B[p][0] = -(jx[p][1] * v2 - jx[p][2] * v1);
+      B[p][1] = -(jx[p][2] * v0 - jx[p][0] * v2);
+      B[p][2] = -(jx[p][0] * v1 - jx[p][1] * v0);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int cc = rr; cc < 3; ++cc) acc[idx++] += jp[0][rr] * jp[0][cc] + jp[1][rr] * jp[1][cc];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[idx++] += jp[0][rr] * B[0][cc] + jp[1][rr] * B[1][cc];
+  }
+  __shared__ double part[4][kDiagVals];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kDiagVals; ++k) {
+    double v = wave_sum(acc[k]);
+    if (lane == 0) part[wid][k] = v;
+  }
+  __syncthreads();
+  __shared__ double tot[kDiagVals];
+  if (threadIdx.x < kDiagVals) {
+    const int k = threadIdx.x;
+    tot[k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+  }
+  __syncthreads();
+  // diagonal block, full 9x9 row-major
+  if (threadIdx.x < 81) {
+    const int rr = threadIdx.x / 9, cc = threadIdx.x % 9;
+    const int a = rr < cc ? rr : cc, b = rr < cc ? cc : rr;
+    const int idx = a * 9 - a * (a - 1) / 2 + (b - a);
+    zdiag[81 * (int64_t)i + threadIdx.x] = tot[idx];
+  }
+  if (threadIdx.x == 0) {
+    if (e1 == e0) report_error(ds, UCOV_EGAUGE, i);
+    const double *N = tot + 45;  // 00 01 02 11 12 22
+    const double *R = tot + 51;  // row-major 3x3
+    const double n00 = N[0], n01 = N[1], n02 = N[2], n11 = N[3], n12 = N[4], n22 = N[5];
+    // Cholesky of the 3x3 normal matrix, pivots checked against its trace
+    const double thr = 1e-14 * (n00 + n11 + n22);
+    double L00 = 0, L10 = 0, L20 = 0, L11 = 0, L21 = 0, L22 = 0;
+    bool ok = n00 > thr;
+    if (ok) {
+      L00 = sqrt(n00);
+      L10 = n01 / L00;
+      L20 = n02 / L00;
+      const double d1 = n11 - L10 * L10;
+      ok = d1 > thr;
+      if (ok) {
+        L11 = sqrt(d1);
+        L21 = (n12 - L20 * L10) / L11;
+        const double d2 = n22 - L20 * L20 - L21 * L21;
+        ok = d2 > thr;
+        if (ok) L22 = sqrt(d2);
+      }
+    }
+    if (!ok) report_error(ds, UCOV_EGAUGE, i);
+    const int64_t Nn = 9 * (int64_t)sc.n;
+    const int64_t row0 = 9 * (int64_t)i;
+    for (int cc = 0; cc < 3; ++cc) {
+      // solve L L^T h = R[:, cc]
+      double h0 = 0, h1 = 0, h2 = 0;
+      if (ok) {
+        const double y0 = R[0 * 3 + cc] / L00;
+        const double y1 = (R[1 * 3 + cc] - L10 * y0) / L11;
+        const double y2 = (R[2 * 3 + cc] - L20 * y0 - L21 * y1) / L22;
+        h2 = y2 / L22;
+        h1 = (y1 - L21 * h2) / L11;
+        h0 = (y0 - L10 * h1 - L20 * h2) / L00;
+      }
+      hc[(3 + cc) * Nn + row0 + 0] = h0;
+      hc[(3 + cc) * Nn + row0 + 1] = h1;
+      hc[(3 + cc) * Nn + row0 + 2] = h2;
+    }
+    // rotation rows, translation and scale columns: zero
+    for (int rr = 0; rr < 3; ++rr) {
+      for (int cc = 0; cc < 3; ++cc) hc[cc * Nn + row0 + rr] = 0.0;
+      hc[6 * Nn + row0 + rr] = 0.0;
+    }
+    // centre rows: [I | [C]x | C]
+    const double Cv[3] = {C0, C1, C2};
+    const double Cx[3][3] = {{0, -C2, C1}, {C2, 0, -C0}, {-C1, C0, 0}};
+    for (int rr = 0; rr < 3; ++rr) {
+      for (int cc = 0; cc < 3; ++cc) {
+        hc[cc * Nn + row0 + 3 + rr] = rr == cc ? 1.0 : 0.0;
+        hc[(3 + cc) * Nn + row0 + 3 + rr] = Cx[rr][cc];
+      }
+      hc[6 * Nn + row0 + 3 + rr] = Cv[rr];
+    }
+    // intrinsics rows: zero
+    for (int rr = 6; rr < 9; ++rr)
+      for (int cc = 0; cc < 7; ++cc) hc[cc * Nn + row0 + rr] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step a3: Cholesky-QR2 orthonormalisation, gauge weight, Jacobi scaling
+// ---------------------------------------------------------------------------
+constexpr int kGaugeThreads = 1024;
+
+__device__ inline double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < kGaugeThreads / 64; ++k) s += red[k];
+  return s;
+}
+
+// Gram matrix G = A^T A of an N x 7 column-major matrix, then R = chol(G)
+// (G = R^T R) and A <- A R^-1, written into out.  Returns false if G is not
+// positive definite.
+__device__ bool cholqr_pass(int64_t N, const double *A, double *out, double *red,
+                            double *Gs, double *Ri) {
+  double g[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) g[k] = 0.0;
+  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
+    double row[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) row[c] = A[c * N + p];
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a)
+#pragma unroll
+      for (int b = a; b < 7; ++b) g[idx++] += row[a] * row[b];
+  }
+  for (int k = 0; k < 28; ++k) {
+    double v = block_sum(g[k], red);
+    if (threadIdx.x == 0) Gs[k] = v;
+  }
+  __syncthreads();
+  __shared__ int okflag;
+  if (threadIdx.x == 0) {
+    double G[7][7], L[7][7];
+    int idx = 0;
+    for (int a = 0; a < 7; ++a)
+      for (int b = a; b < 7; ++b) {
+        G[a][b] = Gs[idx];
+        G[b][a] = Gs[idx];
+        ++idx;
+      }
+    bool ok = true;
+    for (int a = 0; a < 7; ++a)
+      for (int b = 0; b < 7; ++b) L[a][b] = 0.0;
+    for (int j = 0; j < 7 && ok; ++j) {
+      double d = G[j][j];
+      for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+      if (!(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      L[j][j] = sqrt(d);
+      for (int r = j + 1; r < 7; ++r) {
+        double v = G[r][j];
+        for (int k = 0; k < j; ++k) v -= L[r][k] * L[j][k];
+        L[r][j] = v / L[j][j];
+      }
+    }
+    // R = L^T (upper); Ri = R^-1 = (L^-1)^T
+    double Li[7][7];
+    for (int a = 0; a < 7; ++a)
+      for (int b = 0; b < 7; ++b) Li[a][b] = 0.0;
+    if (ok) {
+      for (int c = 0; c < 7; ++c) {
+        for (int r = c; r < 7; ++r) {
+          double v = (r == c) ? 1.0 : 0.0;
+          for (int k = c; k < r; ++k) v -= L[r][k] * Li[k][c];
+          Li[r][c] = v / L[r][r];
+        }
+      }
+    }
+    for (int a = 0; a < 7; ++a)
+      for (int b = 0; b < 7; ++b) Ri[a * 7 + b] = Li[b][a];
+    okflag = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!okflag) return false;
+  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
+    double row[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) row[c] = A[c * N + p];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) v += row[k] * Ri[k * 7 + c];
+      out[c * N + p] = v;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double *hc,
+                                                        double *q, const double *zdiag,
+                                                        const double *zdense, int64_t ldz,
+                                                        double user_alpha, double *s,
+                                                        double *alpha_out, DevStatus *ds) {
+  __shared__ double red[kGaugeThreads / 64];
+  __shared__ double Gs[28];
+  __shared__ double Ri[49];
+  if (hc) {
+    if (!cholqr_pass(N, hc, q, red, Gs, Ri) || !cholqr_pass(N, q, q, red, Gs, Ri)) {
+      if (threadIdx.x == 0) report_error(ds, UCOV_EGAUGE, -1);
+      return;
+    }
+  }
+  // a = 7 / sum_p sum_k Q_pk^2 / Z_pp unless given
+  double part = 0.0;
+  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
+    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[p * ldz + p];
+    double qq = 0.0;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) qq += q[c * N + p] * q[c * N + p];
+    part += qq / zpp;
+  }
+  const double tot = block_sum(part, red);
+  const double a = user_alpha > 0.0 ? user_alpha : 7.0 / tot;
+  if (threadIdx.x == 0) *alpha_out = a;
+  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
+    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[p * ldz + p];
+    double qq = 0.0;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) qq += q[c * N + p] * q[c * N + p];
+    const double dA = zpp + a * qq;
+    if (!(dA > 0.0) || !isfinite(dA)) {
+      report_error(ds, UCOV_EGAUGE, (int)(p / 9));
+      s[p] = 0.0;
+    } else {
+      s[p] = 1.0 / sqrt(dA);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1), one workgroup per
+// block column k; wave w handles the row blocks i = k + w, k + w + 4, ...
+// Lane l holds elements e = l and e = 64 + l (l < 17) of the 9x9 block,
+// element e at row e % 9 and column e / 9.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_assemble(SceneDev sc, const int64_t *bin_ptr,
+                                                 const int2 *pairs, const double *rec,
+                                                 const double *zdiag, const double *q,
+                                                 const double *s, const double *alpha,
+                                                 int mode, double *out, int64_t ld) {
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t N = 9 * (int64_t)sc.n;
+  const int e0 = lane, e1 = 64 + lane;
+  const bool has1 = lane < 17;
+  const int r0 = e0 % 9, c0 = e0 / 9, r1 = e1 % 9, c1 = e1 / 9;
+  const double a = mode ? *alpha : 0.0;
+  for (int i = k + wid; i < sc.n; i += 4) {
+    double z0, z1;
+    if (i == k) {
+      z0 = zdiag[81 * (int64_t)k + 9 * r0 + c0];
+      z1 = has1 ? zdiag[81 * (int64_t)k + 9 * r1 + c1] : 0.0;
+    } else {
+      z0 = 0.0;
+      z1 = 0.0;
+      const int64_t bin = tri(i) + k;
+      const int64_t b0 = bin_ptr[bin], b1 = bin_ptr[bin + 1];
+      for (int64_t e = b0; e < b1; ++e) {
+        const int2 pr = pairs[e];
+        const double *ra = rec + (int64_t)pr.x * kRec;
+        const double *rb = rec + (int64_t)pr.y * kRec;
+        // K = Y_a J_X,b^T (2x2)
+        double K[2][2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int qq = 0; qq < 2; ++qq)
+            K[p][qq] = ra[kRecY + 3 * p] * rb[kRecJX + 3 * qq] +
+                       ra[kRecY + 3 * p + 1] * rb[kRecJX + 3 * qq + 1] +
+                       ra[kRecY + 3 * p + 2] * rb[kRecJX + 3 * qq + 2];
+        {
+          const double pa0 = ra[kRecJP + r0], pa1 = ra[kRecJP + 9 + r0];
+          const double pb0 = rb[kRecJP + c0], pb1 = rb[kRecJP + 9 + c0];
+          z0 -= pa0 * (K[0][0] * pb0 + K[0][1] * pb1) + pa1 * (K[1][0] * pb0 + K[1][1] * pb1);
+        }
+        if (has1) {
+          const double pa0 = ra[kRecJP + r1], pa1 = ra[kRecJP + 9 + r1];
+          const double pb0 = rb[kRecJP + c1], pb1 = rb[kRecJP + 9 + c1];
+          z1 -= pa0 * (K[0][0] * pb0 + K[0][1] * pb1) + pa1 * (K[1][0] * pb0 + K[1][1] * pb1);
+        }
+      }
+    }
+    const int64_t row0 = 9 * (int64_t)i, col0 = 9 * (int64_t)k;
+    if (mode == 0) {
+      out[(col0 + c0) * ld + row0 + r0] = z0;
+      if (i != k) out[(row0 + r0) * ld + col0 + c0] = z0;
+      if (has1) {
+        out[(col0 + c1) * ld + row0 + r1] = z1;
+        if (i != k) out[(row0 + r1) * ld + col0 + c1] = z1;
+      }
+    } else {
+      {
+        const int64_t pr = row0 + r0, pc = col0 + c0;
+        double g = 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) g += q[c * N + pr] * q[c * N + pc];
+        out[pc * ld + pr] = s[pr] * (z0 + a * g) * s[pc];
+      }
+      if (has1) {
+        const int64_t pr = row0 + r1, pc = col0 + c1;
+        double g = 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) g += q[c * N + pr] * q[c * N + pc];
+        out[pc * ld + pr] = s[pr] * (z1 + a * g) * s[pc];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, st, p, v, n);
+}
+void fill_f64(double *p, double v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, st, p, v, n);
+}
+
+void exclusive_scan(const int32_t *in, int64_t *out, int64_t len, int64_t *tmp,
+                    hipStream_t st) {
+  const int64_t ntiles = (len + kScanTile - 1) / kScanTile;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, in,
+                       out, len, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, tmp, ntiles);
+  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(len + 1, kBlk)), dim3(kBlk), 0, st, out, len,
+                     tmp, ntiles);
+}
+
+void launch_count_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_points, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.cnt_p, ds);
+}
+
+void launch_group_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_slots, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.cur_p, w.slot_obs);
+  hipLaunchKernelGGL(k_sort_points, dim3(blocks_for(sc.m, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.slot_obs, w.slot_cam, w.slot_pt, ds);
+}
+
+void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *jx_out,
+                      DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobians, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.slot_obs, w.slot_cam, w.slot_pt, w.rec, jp_out, jx_out, ds);
+}
+
+void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_point_blocks, dim3(blocks_for(sc.m, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.rec, ds);
+}
+
+void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_count, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_cnt);
+}
+
+void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_fill, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
+                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_ptr, w.bin_cur, w.pairs);
+}
+
+void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_camera_diag, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs,
+                     w.rec, w.slot_pt, w.zdiag, w.hc, ds);
+}
+
+void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
+                  const double *zdense, int64_t ldz, double user_alpha, double *s,
+                  double *alpha, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_gauge, dim3(1), dim3(kGaugeThreads), 0, st, N, hc, q, zdiag, zdense,
+                     ldz, user_alpha, s, alpha, ds);
+}
+
+void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs, w.rec,
+                     w.zdiag, w.q, w.s, w.alpha, mode, out, ld);
+}
+
+}  // namespace ucov

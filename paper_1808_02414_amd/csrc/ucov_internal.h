@@ -1,0 +1,103 @@
+// Internal declarations shared by the ucov HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ucov {
+
+// First device-detected error of a call.  Kernels record it with
+// report_error(); the host reads it back after the stream has drained.
+struct DevStatus {
+  int code;   // 0 or a negative UCOV_E* code
+  int index;  // offending observation / point / camera
+};
+
+__device__ inline void report_error(DevStatus *st, int code, int index) {
+  if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->index, index);
+}
+
+// Tile edge of the dense factorisation; every dense dimension is padded to it.
+constexpr int kTile = 64;
+
+// Per-slot record (observations grouped by point, cameras ascending within
+// a point), 32 doubles = 256 bytes:
+//   [0..17]  whitened J_P (2x9 row-major)
+//   [18..23] whitened J_X (2x3 row-major)
+//   [24..29] Y = J_X V^-1 (2x3 row-major), the point-eliminated coupling
+constexpr int kRec = 32;
+constexpr int kRecJP = 0;
+constexpr int kRecJX = 18;
+constexpr int kRecY = 24;
+
+// ---- scene stage (scene_kernels.hip) ---------------------------------------
+struct SceneDev {
+  int n, m;
+  int64_t t;
+  const double *cams, *pts, *info;
+  const int32_t *oc, *op;
+};
+
+struct SceneWork {
+  // observations grouped by point
+  int32_t *cnt_p;     // m
+  int64_t *ptr_p;     // m + 1
+  int32_t *cur_p;     // m
+  int32_t *slot_obs;  // t: observation id of each slot
+  int32_t *slot_cam;  // t
+  int32_t *slot_pt;   // t
+  double *rec;        // t x kRec
+  // camera-pair bins (lower triangle, bin(i,k) = i(i+1)/2 + k, i >= k)
+  int32_t *bin_cnt;   // nbins
+  int64_t *bin_ptr;   // nbins + 1
+  int32_t *bin_cur;   // nbins
+  int2 *pairs;        // n_pairs (slot a of camera i, slot b of camera k)
+  // per camera
+  double *zdiag;      // n x 81, diagonal blocks of Z (row-major)
+  double *hc;         // N x 7 column-major (ld N)
+  double *q;          // N x 7 column-major (ld N)
+  double *s;          // N, Jacobi scaling of Z + a QQ^T
+  double *alpha;      // 1
+  int64_t *scan_tmp;  // scan block sums
+};
+
+void exclusive_scan(const int32_t *in, int64_t *out, int64_t len, int64_t *tmp,
+                    hipStream_t st);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+void fill_f64(double *p, double v, int64_t n, hipStream_t st);
+
+void launch_count_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
+void launch_group_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
+void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *jx_out,
+                      DevStatus *ds, hipStream_t st);
+void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
+void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st);
+void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st);
+void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
+// Orthonormal Q (Cholesky-QR2 of hc; skipped when hc is null and q is given),
+// the gauge weight alpha and the Jacobi scaling s.  diag(Z) comes from the
+// per-camera blocks zdiag (n x 81) or, when that is null, from a dense z.
+void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
+                  const double *zdense, int64_t ldz, double user_alpha, double *s,
+                  double *alpha, DevStatus *ds, hipStream_t st);
+// mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
+// S (Z + a QQ^T) S into out
+void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
+                     hipStream_t st);
+
+// ---- dense stage (dense_kernels.hip) ---------------------------------------
+// Scaled positive-definite matrix a = S (Z + alpha QQ^T) S from a caller's Z.
+void launch_scale_dense(int64_t N, const double *z, int64_t ldz, const double *q,
+                        const double *s, const double *alpha, double *a, int64_t lda,
+                        hipStream_t st);
+// Identity on the padding rows/columns [N, Np) of the lower triangle.
+void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStream_t st);
+// In-place L^-1 of the Cholesky factor of the lower triangle of a (Np x Np).
+void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, int64_t ldt,
+                            DevStatus *ds, hipStream_t st);
+// cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha
+void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
+                    const double *q, const double *alpha, double *cov, hipStream_t st);
+
+}  // namespace ucov

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Tolerance: per-camera-block relative Frobenius error <= 1e-6 for the
+covariance (the contract); intermediate stages, which involve no inverse of
+an ill-conditioned matrix, are compared far tighter.  A scaled metric
+|dS_lm| / sqrt(S_ll S_mm) is checked as well, since the Frobenius norm of a
+block is dominated by its focal-length variance.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import camera, covariance
+from oracle.pipeline import camera_covariance as oracle_cov
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ucov():
+    import torch
+    import paper_1808_02414_amd as u
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = u.Context(0)
+    yield u, ctx
+    ctx.close()
+
+
+def block_errors(got, ref):
+    fro = max(np.linalg.norm(g - r) / np.linalg.norm(r) for g, r in zip(got, ref))
+    d = np.sqrt(np.abs(np.diagonal(ref, axis1=1, axis2=2)))
+    scaled = np.max(np.abs(got - ref) / (d[:, :, None] * d[:, None, :]))
+    return fro, scaled
+
+
+def dev(u, scene):
+    return u.DeviceScene.from_scene(scene, "cuda:0")
+
+
+@pytest.mark.parametrize("seed,with_info", [(0, False), (1, True), (2, False)])
+def test_jacobians(ucov, seed, with_info):
+    u, ctx = ucov
+    s = sg.tiny_circle(seed, with_info=with_info)
+    print(f"jacobians seed={seed} info={with_info}", flush=True)
+    jp, jx = ctx.jacobians(dev(u, s))
+    JP, JX = camera.jacobians(s.cams, s.pts, s.obs_cam, s.obs_pt)
+    jp, jx = jp.cpu().numpy(), jx.cpu().numpy()
+    scale = np.abs(JP).max(axis=(0, 1))
+    assert np.all(np.abs(jp - JP).max(axis=(0, 1)) <= 1e-12 * scale)
+    assert np.abs(jx - JX).max() <= 1e-12 * np.abs(JX).max()
+
+
+@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(3), lambda: sg.tiny_circle(4, with_info=True),
+                                   lambda: sg.spiral_slab(5, n=60, m=3000)])
+def test_reduced_camera_matrix(ucov, maker):
+    u, ctx = ucov
+    s = maker()
+    print(f"Z {s.name} n={s.n_cams}", flush=True)
+    z, rep = ctx.reduced_camera_matrix(dev(u, s))
+    z = z.cpu().numpy()
+    ref = oracle_cov(s, keep=True)
+    Z = ref["Z"]
+    assert np.linalg.norm(z - Z) / np.linalg.norm(Z) < 1e-12
+    assert np.array_equal(z, z.T)
+    Hc = ref["Hc"]
+    assert np.abs(z @ Hc).max() <= 1e-13 * np.abs(z).max() * np.abs(Hc).max()
+
+
+@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(6), lambda: sg.spiral_slab(7, n=80, m=4000)])
+def test_gauge_basis(ucov, maker):
+    u, ctx = ucov
+    s = maker()
+    print(f"gauge {s.name} n={s.n_cams}", flush=True)
+    hc, q = ctx.gauge_basis(dev(u, s))
+    hc, q = hc.cpu().numpy(), q.cpu().numpy()
+    ref = oracle_cov(s, keep=True)
+    assert np.abs(hc - ref["Hc"]).max() <= 1e-10 * np.abs(ref["Hc"]).max()
+    assert np.abs(q.T @ q - np.eye(7)).max() < 1e-13
+    P, Pr = q @ q.T, ref["Q"] @ ref["Q"].T
+    assert np.abs(P - Pr).max() < 1e-12
+
+
+@pytest.mark.parametrize("N,kappa", [(90, 1e3), (576, 1e6), (1161, 1e8), (2007, 1e5)])
+def test_pinv_known_spectrum(ucov, N, kappa):
+    """Dense stage alone on Z = B diag(lam) B^T with a prescribed null space."""
+    import torch
+    u, ctx = ucov
+    print(f"pinv N={N} kappa={kappa:g}", flush=True)
+    rng = np.random.default_rng(N)
+    B, _ = np.linalg.qr(rng.normal(size=(N, N)))
+    lam = np.geomspace(1.0, 1.0 / kappa, N - 7)
+    R, Q0 = B[:, :N - 7], B[:, N - 7:]
+    Z = (R * lam) @ R.T
+    Z = 0.5 * (Z + Z.T)
+    ref = covariance.camera_blocks((R / lam) @ R.T)
+    got, rep = ctx.pinv_blocks(torch.from_numpy(Z).cuda(), torch.from_numpy(Q0.copy()).cuda())
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    assert fro < 1e-15 * kappa * 100, (fro, scaled)
+
+
+@pytest.mark.parametrize("seed,with_info", [(0, False), (1, False), (2, True), (3, False)])
+def test_covariance_tiny(ucov, seed, with_info):
+    u, ctx = ucov
+    s = sg.tiny_circle(seed, with_info=with_info)
+    print(f"covariance tiny seed={seed}", flush=True)
+    got, rep = ctx.camera_covariance(dev(u, s))
+    ref = oracle_cov(s)["blocks"]
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+@pytest.mark.parametrize("n,m", [(37, 2000), (150, 15000)])
+def test_covariance_ragged(ucov, n, m):
+    """Several tiles with a ragged tail (9n not a multiple of the tile)."""
+    u, ctx = ucov
+    s = sg.spiral_slab(11, n=n, m=m)
+    print(f"covariance spiral n={n}", flush=True)
+    got, rep = ctx.camera_covariance(dev(u, s))
+    ref = oracle_cov(s)["blocks"]
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+def test_covariance_full_medium_scene(ucov):
+    """The 500-camera spiral scene (Z 4500 x 4500), every block."""
+    u, ctx = ucov
+    s = sg.spiral_slab(0)
+    print("covariance spiral n=500", flush=True)
+    got, rep = ctx.camera_covariance(dev(u, s))
+    ref = oracle_cov(s)["blocks"]
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    print(f"  fro {fro:.3e} scaled {scaled:.3e} report {rep}")
+    assert fro < 1e-6, (fro, scaled)
+
+
+def test_repeat_calls_agree(ucov):
+    u, ctx = ucov
+    s = sg.spiral_slab(12, n=40, m=2000)
+    d = dev(u, s)
+    a, _ = ctx.camera_covariance(d)
+    a = a.cpu().numpy()
+    small = dev(u, sg.tiny_circle(1))
+    ctx.camera_covariance(small)  # a smaller call in between reuses the workspace
+    b, _ = ctx.camera_covariance(d)
+    fro, _ = block_errors(b.cpu().numpy(), a)
+    # the Schur scatter sums each camera-pair bin in arrival order, so repeated
+    # calls agree to rounding, not bit for bit
+    assert fro < 1e-9
+
+
+def test_errors(ucov):
+    u, ctx = ucov
+    s = sg.tiny_circle(17)
+    bad = sg.Scene(s.cams, s.pts, s.obs_cam.copy(), s.obs_pt.copy())
+    bad.obs_cam[3] = s.n_cams
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, bad))
+    assert e.value.kind == "EINVAL"
+
+    dup = sg.Scene(s.cams, s.pts, np.append(s.obs_cam, s.obs_cam[0]).astype(np.int32),
+                   np.append(s.obs_pt, s.obs_pt[0]).astype(np.int32))
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, dup))
+    assert e.value.kind == "EINVAL"
+
+    j = int(s.obs_pt[0])
+    sel = (s.obs_pt != j) | (np.arange(s.n_obs) == 0)
+    lone = sg.Scene(s.cams, s.pts, s.obs_cam[sel], s.obs_pt[sel])
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, lone))
+    assert e.value.kind == "EPOINT" and e.value.index == j
+
+    a = sg.tiny_circle(18, n=5, m=60)
+    b = sg.tiny_circle(19, n=5, m=60)
+    two = sg.Scene(np.vstack([a.cams, b.cams]), np.vstack([a.pts, b.pts]),
+                   np.concatenate([a.obs_cam, b.obs_cam + 5]).astype(np.int32),
+                   np.concatenate([a.obs_pt, b.obs_pt + 60]).astype(np.int32))
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, two))
+    assert e.value.kind == "EGAUGE"
+
+    # the context still works after errors
+    got, _ = ctx.camera_covariance(dev(u, s))
+    ref = oracle_cov(s)["blocks"]
+    assert block_errors(got.cpu().numpy(), ref)[0] < 1e-6
