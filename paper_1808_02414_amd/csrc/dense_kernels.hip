@@ -14,8 +14,10 @@
 //                      L22^-1 <- recurse(A22)
 //                      A21    <- -L22^-1 A21           (= (L^-1)21)
 //
-// The leaves are 64x64 blocks factored and inverted in LDS by one workgroup;
+// The leaves are 64x64 or 128x128 blocks factored and inverted by one workgroup;
 // the products run on FP64 MFMA (v_mfma_f64_16x16x4f64) in 64x64 output tiles.
+#include <algorithm>
+
 #include "ucov_internal.h"
 #include "../../include/ucov.h"
 
@@ -37,17 +39,34 @@ enum KMode { kFull = 0, kLeN = 1, kGeN = 2, kLeM = 3 };
 //   kLeM  k < (tile_m + 1) * 64  (A lower triangular)
 // MFMA operand layout (16x16x4, 64 lanes): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; the accumulator holds D[4*v + l/16][l%16], v = 0..3.
+// (Measured on MI355X: single-buffered LDS with a register prefetch and
+// occupancy 4 beats double buffering, larger tiles and die-aware tile orders
+// for every product shape of the recursion.)
 // ---------------------------------------------------------------------------
 constexpr int kKc = 16;     // K chunk staged in LDS
 constexpr int kLdsPad = 4;  // row padding of the LDS tiles (doubles)
 
+struct GemmArgs {
+  int64_t M, N, K;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc;
+  double alpha, beta;
+  int kmode;
+};
+
 template <bool BT, bool LOWER>
-__global__ __launch_bounds__(256) void k_gemm64(int64_t K, const double *__restrict__ A,
-                                               int64_t lda, const double *__restrict__ B,
-                                               int64_t ldb, double *__restrict__ C, int64_t ldc,
-                                               double alpha, double beta, int kmode) {
-  const int tm = blockIdx.x, tn = blockIdx.y;
+__device__ inline void gemm_tile(const GemmArgs &g, int tm, int tn) {
   if (LOWER && tn > tm) return;
+  const int64_t K = g.K, lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+  const double *__restrict__ A = g.A;
+  const double *__restrict__ B = g.B;
+  double *__restrict__ C = g.C;
+  const double alpha = g.alpha, beta = g.beta;
+  const int kmode = g.kmode;
   int64_t kb = 0, ke = K;
   if (kmode == kLeN) ke = min(K, (int64_t)(tn + 1) * 64);
   else if (kmode == kGeN) kb = (int64_t)tn * 64;
@@ -124,63 +143,257 @@ __global__ __launch_bounds__(256) void k_gemm64(int64_t K, const double *__restr
     }
 }
 
-// ---------------------------------------------------------------------------
-// 64x64 leaf: Cholesky factor L of the lower triangle and its inverse, in
-// LDS; writes L^-1 (lower) and zeros above the diagonal of the tile.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_leaf64(double *A, int64_t lda, int64_t o,
-                                               DevStatus *ds) {
-  __shared__ double Ls[64][65];
-  __shared__ double Xs[64][65];
-  __shared__ double dg[64];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  double *T = A + o + o * lda;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    Ls[r][c] = r >= c ? T[r + (int64_t)c * lda] : 0.0;
-    Xs[r][c] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // symmetric Gaussian elimination: after step j, column j holds L[:, j] L[j][j]
-  for (int j = 0; j < 64; ++j) {
-    const double piv = Ls[j][j];
-    if (tid == 0 && !(piv > 0.0)) report_error(ds, UCOV_EGAUGE, (int)((o + j) / 9));
-    const double inv = 1.0 / piv;
-    const double lr = Ls[lane][j];
-    for (int c = j + 1 + wid; c < 64; c += 4) {
-      if (lane >= c) Ls[lane][c] -= lr * Ls[c][j] * inv;
-    }
-    __syncthreads();
-  }
-  if (tid < 64) dg[tid] = sqrt(Ls[tid][tid]);
-  __syncthreads();
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    if (r > c) Ls[r][c] /= dg[c];
-    else if (r == c) Ls[r][c] = dg[c];
-  }
-  __syncthreads();
-  // X = L^-1 by forward elimination on the identity: with y_j final,
-  // y_r -= (L[r][j] / L[j][j]) y_j for r > j; finally x_r = y_r / L[r][r].
-  for (int j = 0; j < 63; ++j) {
-    const double f = (lane > j) ? Ls[lane][j] / Ls[j][j] : 0.0;
-    for (int c = wid; c <= j; c += 4) {
-      if (lane > j) Xs[lane][c] -= f * Xs[j][c];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    T[r + (int64_t)c * lda] = r >= c ? Xs[r][c] / Ls[r][r] : 0.0;
+// One product; grid (M/64, N/64), tile rows fastest.
+template <bool BT, bool LOWER>
+__global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
+  gemm_tile<BT, LOWER>(g, blockIdx.x, blockIdx.y);
+}
+
+// The two independent products of one recursion node in one launch: the
+// Schur update A22 -= T T^T (lower tiles, first nblk_s workgroups) and
+// T2 = T L11^-1.
+__global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs s, GemmArgs t, int nblk_s) {
+  const int b = blockIdx.x;
+  if (b < nblk_s) {
+    const int mt = (int)(s.M / 64);
+    gemm_tile<true, true>(s, b % mt, b / mt);
+  } else {
+    const int mt = (int)(t.M / 64), bb = b - nblk_s;
+    gemm_tile<false, false>(t, bb % mt, bb / mt);
   }
 }
 
-// copy an m x n block
-__global__ void k_copy(int64_t m, int64_t n, const double *src, int64_t lds, double *dst,
-                       int64_t ldd) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (r < m && c < n) dst[r + c * ldd] = src[r + c * lds];
+// ---------------------------------------------------------------------------
+// Leaf of NB x NB (64 or 128): Cholesky factor L of the lower triangle and its
+// inverse L^-1, by 4-column block steps.  The lower triangle is cut into 4x4
+// micro-tiles (R, C), one per thread, held in registers.
+//
+// Factorisation, block step J:
+//   1. the owners of block column J publish their (updated) tiles in LDS;
+//   2. they factor the 4x4 diagonal block D = L_JJ L_JJ^T (each one locally)
+//      and publish L(R,J) = A(R,J) L_JJ^-T;
+//   3. every tile right of J applies A(R,C) -= L(R,J) L(C,J)^T.
+// Inversion, block step J (right-looking forward elimination of L Y = I):
+//   Y(J,C) = L_JJ^-1 W(J,C), then W(R,C) -= L(R,J) Y(J,C) for R > J, C <= J.
+// Writes L^-1 (lower) into the tile and zeros above its diagonal.
+// ---------------------------------------------------------------------------
+// 4x4 Cholesky of the symmetric block d (only d[a][b], a >= b, is read):
+// writes the lower factor into l and its inverse into li; returns false if a
+// pivot is not positive.
+__device__ inline bool chol4(const double (&d)[4][4], double (&l)[4][4], double (&li)[4][4]) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) l[a][b] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double p = d[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) p -= l[j][k] * l[j][k];
+    ok = ok && (p > 0.0);
+    const double ljj = sqrt(p);
+    const double il = 1.0 / ljj;
+    l[j][j] = ljj;
+#pragma unroll
+    for (int r = j + 1; r < 4; ++r) {
+      double x = d[r][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) x -= l[r][k] * l[j][k];
+      l[r][j] = x * il;
+    }
+    li[j][j] = il;
+  }
+  // li = l^-1 (lower), column by column
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < c) li[r][c] = 0.0;
+      if (r > c) {
+        double x = 0.0;
+#pragma unroll
+        for (int k = c; k < r; ++k) x -= l[r][k] * li[k][c];
+        li[r][c] = x * li[r][r];
+      }
+    }
+  }
+  return ok;
+}
+
+template <int NB, int NT>
+__global__ __launch_bounds__(NT) void k_leaf(double *A, int64_t lda, int64_t o, DevStatus *ds) {
+  constexpr int MB = NB / 4;                // micro-tiles per edge
+  constexpr int NMT = MB * (MB + 1) / 2;    // lower-triangle micro-tiles
+  static_assert(NMT <= NT, "one micro-tile per thread");
+  // panels indexed [column b][row a within the tile][tile row R] so that lanes
+  // (consecutive tile rows) touch consecutive words
+  __shared__ double P[4][4][MB];            // raw block column J
+  __shared__ double Q[2][4][4][MB];         // L(., J)
+  __shared__ double Yb[2][4][NB];           // block row J of W
+  __shared__ double Dinv[MB][4][4];         // L_JJ^-1
+  const int tid = threadIdx.x;
+  const bool own = tid < NMT;
+  double *T = A + o + o * lda;
+  int R = MB, C = MB;  // idle threads own no tile
+  if (own) {
+    const double b = 2.0 * MB + 1.0;
+    int cg = (int)((b - sqrt(b * b - 8.0 * tid)) * 0.5);
+    cg = cg < 0 ? 0 : (cg > MB - 1 ? MB - 1 : cg);
+    while (cg > 0 && cg * MB - cg * (cg - 1) / 2 > tid) --cg;
+    while (cg < MB - 1 && (cg + 1) * MB - (cg + 1) * cg / 2 <= tid) ++cg;
+    C = cg;
+    R = C + (tid - (C * MB - C * (C - 1) / 2));
+  }
+  const int r0 = 4 * R, c0 = 4 * C;
+  const int rr = own ? r0 : 0, cr = own ? c0 : 0;  // clamped LDS indices
+  double v[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      // diagonal tiles are loaded symmetric so they stay symmetric under updates
+      const int r = r0 + a, c = c0 + b;
+      const int hi = r > c ? r : c, lo = r > c ? c : r;
+      v[a][b] = own ? T[hi + (int64_t)lo * lda] : 0.0;
+    }
+
+  for (int J = 0; J < MB; ++J) {
+    if (C == J) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) P[b][a][R] = v[a][b];
+    }
+    __syncthreads();
+    if (C == J) {
+      double d[4][4], l[4][4], li[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[a][b] = P[b][a][J];
+      const bool ok = chol4(d, l, li);
+      if (R == J) {
+        if (!ok) report_error(ds, UCOV_EGAUGE, (int)((o + 4 * J) / 9));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            v[a][b] = l[a][b];
+            Dinv[J][a][b] = li[a][b];
+          }
+      } else {
+        // L(R,J) = A(R,J) L_JJ^-T: row a times li^T
+        double x[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m <= k; ++m) acc += v[a][m] * li[k][m];
+            x[a][k] = acc;
+          }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            v[a][b] = x[a][b];
+            Q[0][b][a][R] = x[a][b];
+          }
+      }
+    }
+    __syncthreads();
+    if (C > J && C < MB) {
+      double lr[4][4], lc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          lr[a][b] = Q[0][b][a][rr >> 2];
+          lc[a][b] = Q[0][b][a][cr >> 2];
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          v[a][b] -= lr[a][0] * lc[b][0] + lr[a][1] * lc[b][1] + lr[a][2] * lc[b][2] +
+                     lr[a][3] * lc[b][3];
+    }
+  }
+  // v now holds L (lower; the upper part of diagonal tiles is zero)
+  double y[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[a][b] = (R == C && a == b) ? 1.0 : 0.0;
+  for (int J = 0; J < MB; ++J) {
+    const int buf = J & 1;
+    if (C == J && R > J) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Q[buf][b][a][R] = v[a][b];
+    }
+    if (R == J) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Yb[buf][a][c0 + b] = y[a][b];
+    }
+    __syncthreads();
+    if (C <= J && R >= J && R < MB) {
+      double di[4][4], w[4][4], x[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          di[a][b] = Dinv[J][a][b];
+          w[a][b] = Yb[buf][a][cr + b];
+        }
+      // X = Y(J,C) = L_JJ^-1 W(J,C)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m <= a; ++m) acc += di[a][m] * w[m][b];
+          x[a][b] = acc;
+        }
+      if (R == J) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) y[a][b] = x[a][b];
+      } else {
+        double lr[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) lr[a][b] = Q[buf][b][a][rr >> 2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            y[a][b] -= lr[a][0] * x[0][b] + lr[a][1] * x[1][b] + lr[a][2] * x[2][b] +
+                       lr[a][3] * x[3][b];
+      }
+    }
+  }
+  if (own) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = r0 + a, c = c0 + b;
+        T[r + (int64_t)c * lda] = r >= c ? y[a][b] : 0.0;
+      }
+  }
+  for (int e = tid; e < NB * NB; e += NT) {
+    const int r = e % NB, c = e / NB;
+    if ((r >> 2) < (c >> 2)) T[r + (int64_t)c * lda] = 0.0;
+  }
 }
 
 __global__ void k_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda) {
@@ -249,34 +462,63 @@ __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, 
   }
 }
 
+GemmArgs make_args(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double *C, int64_t ldc, double alpha,
+                   double beta, int kmode) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.kmode = kmode;
+  return g;
+}
+
 template <bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
           int64_t ldb, double *C, int64_t ldc, double alpha, double beta, int kmode,
           hipStream_t st) {
-  dim3 grid((unsigned)(M / 64), (unsigned)(N / 64));
-  hipLaunchKernelGGL((k_gemm64<BT, LOWER>), grid, dim3(256), 0, st, K, A, lda, B, ldb, C, ldc,
-                     alpha, beta, kmode);
+  GemmArgs g = make_args(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
+  hipLaunchKernelGGL((k_gemm64<BT, LOWER>), dim3((unsigned)(M / 64), (unsigned)(N / 64)),
+                     dim3(256), 0, st, g);
 }
 
-void recurse(double *A, int64_t lda, int64_t o, int64_t n, double *T, int64_t ldt,
-             DevStatus *ds, hipStream_t st) {
+void gemm_pair(const GemmArgs &s, const GemmArgs &t, hipStream_t st) {
+  const unsigned a = (unsigned)((s.M / 64) * (s.N / 64)), b = (unsigned)((t.M / 64) * (t.N / 64));
+  hipLaunchKernelGGL(k_gemm64_pair, dim3(a + b), dim3(256), 0, st, s, t, (int)a);
+}
+
+// Scratch needed by recurse() for an n x n block (doubles).
+int64_t recurse_scratch(int64_t n) {
+  if (n <= 128) return 0;
+  const int64_t tiles = n / 64, n1 = (tiles / 2) * 64, n2 = n - n1;
+  return n2 * n1 + std::max(n2 * n1, std::max(recurse_scratch(n1), recurse_scratch(n2)));
+}
+
+// In-place L^-1 of the n x n block at offset o.  tmp[0, n2*n1) holds this
+// level's T2 = L21 L11^-1 across the recursion into A22; the rest is scratch
+// for T = L21 and for the children.
+void recurse(double *A, int64_t lda, int64_t o, int64_t n, double *tmp, DevStatus *ds,
+             hipStream_t st) {
   if (n == 64) {
-    hipLaunchKernelGGL(k_leaf64, dim3(1), dim3(256), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf<64, 192>), dim3(1), dim3(192), 0, st, A, lda, o, ds);
+    return;
+  }
+  if (n == 128) {
+    hipLaunchKernelGGL((k_leaf<128, 576>), dim3(1), dim3(576), 0, st, A, lda, o, ds);
     return;
   }
   const int64_t tiles = n / 64;
   const int64_t n1 = (tiles / 2) * 64, n2 = n - n1;
-  recurse(A, lda, o, n1, T, ldt, ds, st);
+  double *T2 = tmp;
+  double *T = tmp + n2 * n1;
+  double *child = T;
+  recurse(A, lda, o, n1, child, ds, st);
   double *A11 = A + o + o * lda;
   double *A21 = A + (o + n1) + o * lda;
   double *A22 = A + (o + n1) + (o + n1) * lda;
-  gemm<true, false>(n2, n1, n1, A21, lda, A11, lda, T, ldt, 1.0, 0.0, kLeN, st);
-  gemm<true, true>(n2, n2, n1, T, ldt, T, ldt, A22, lda, -1.0, 1.0, kFull, st);
-  gemm<false, false>(n2, n1, n1, T, ldt, A11, lda, A21, lda, 1.0, 0.0, kGeN, st);
-  recurse(A, lda, o + n1, n2, T, ldt, ds, st);
-  gemm<false, false>(n2, n1, n2, A22, lda, A21, lda, T, ldt, -1.0, 0.0, kLeM, st);
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 255) / 256), (unsigned)n1), dim3(256), 0,
-                     st, n2, n1, T, ldt, A21, lda);
+  gemm<true, false>(n2, n1, n1, A21, lda, A11, lda, T, n2, 1.0, 0.0, kLeN, st);   // L21
+  gemm_pair(make_args(n2, n2, n1, T, n2, T, n2, A22, lda, -1.0, 1.0, kFull),      // Schur
+            make_args(n2, n1, n1, T, n2, A11, lda, T2, n2, 1.0, 0.0, kGeN), st);  // L21 L11^-1
+  recurse(A, lda, o + n1, n2, child, ds, st);
+  gemm<false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, -1.0, 0.0, kLeM, st); // (L^-1)21
 }
 
 }  // namespace
@@ -293,9 +535,11 @@ void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStrea
   hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)Np), dim3(64), 0, st, N, Np, a, lda);
 }
 
-void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, int64_t ldt,
-                            DevStatus *ds, hipStream_t st) {
-  recurse(a, lda, 0, Np, tmp, ldt, ds, st);
+int64_t spd_lower_inverse_scratch(int64_t Np) { return recurse_scratch(Np); }
+
+void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
+                            hipStream_t st) {
+  recurse(a, lda, 0, Np, tmp, ds, st);
 }
 
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,

@@ -16,6 +16,8 @@ namespace {
 
 constexpr int kBlk = 256;
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 __device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
@@ -403,13 +405,23 @@ __global__ void k_point_blocks(SceneDev sc, const int64_t *ptr_p, double *rec, D
 // camera-pair bins: every ordered pair (a, b) of observations of one point
 // with cam(a) >= cam(b) contributes to block Z(cam a, cam b)
 // ---------------------------------------------------------------------------
+// The first pair that lands in a bin also appends (i, k) to the list of
+// non-empty bins.
 __global__ void k_pair_count(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
-                             const int32_t *slot_pt, int32_t *bin_cnt) {
+                             const int32_t *slot_pt, int32_t *bin_cnt, int2 *nzlist,
+                             unsigned long long *nzcount) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= ptr_p[sc.m]) return;
   const int64_t p0 = ptr_p[slot_pt[a]];
-  const int64_t base = tri(slot_cam[a]);
-  for (int64_t b = p0; b <= a; ++b) atomicAdd(&bin_cnt[base + slot_cam[b]], 1);
+  const int ci = slot_cam[a];
+  const int64_t base = tri(ci);
+  for (int64_t b = p0; b <= a; ++b) {
+    const int ck = slot_cam[b];
+    if (atomicAdd(&bin_cnt[base + ck], 1) == 0) {
+      const unsigned long long pos = atomicAdd(nzcount, 1ull);
+      nzlist[pos] = make_int2(ci, ck);
+    }
+  }
 }
 
 __global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
@@ -732,81 +744,89 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double
 }
 
 // ---------------------------------------------------------------------------
-// assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1), one workgroup per
-// block column k; wave w handles the row blocks i = k + w, k + w + 4, ...
-// Lane l holds elements e = l and e = 64 + l (l < 17) of the 9x9 block,
-// element e at row e % 9 and column e / 9.
+// assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1)
+//
+// k_fill_empty writes the camera blocks without Schur terms (Z_ik = 0): zeros
+// in mode 0, the scaled gauge term in mode 1; one thread per element, columns
+// walked with coalesced stores.  k_bin_blocks takes one wave per non-empty
+// bin (i, k) and writes that whole 9x9 block.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_assemble(SceneDev sc, const int64_t *bin_ptr,
-                                                 const int2 *pairs, const double *rec,
-                                                 const double *zdiag, const double *q,
-                                                 const double *s, const double *alpha,
-                                                 int mode, double *out, int64_t ld) {
-  const int k = blockIdx.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__global__ void k_fill_empty(int64_t N, const int32_t *bin_cnt, const double *q,
+                             const double *s, const double *alpha, int mode, double *out,
+                             int64_t ld) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= N || r < c) return;
+  const int64_t i = r / 9, k = c / 9;
+  if (bin_cnt[tri(i) + k] != 0) return;
+  if (mode == 0) {
+    out[r + c * ld] = 0.0;
+    out[c + r * ld] = 0.0;
+    return;
+  }
+  double g = 0.0;
+#pragma unroll
+  for (int h = 0; h < 7; ++h) g += q[h * N + r] * q[h * N + c];
+  out[r + c * ld] = s[r] * ((*alpha) * g) * s[c];
+}
+
+// Off-diagonal block Z_ik = -sum_e J_P,a^T K_e J_P,b with K_e = Y_a J_X,b^T
+// (2x2), written as -A^T B with A the stacked J_P,a (2E x 9) and B the stacked
+// K_e J_P,b (2E x 9): an FP64 MFMA (16x16x4) contraction over the pair
+// dimension, two pairs per instruction, rows and columns padded 9 -> 16.
+// Lane l supplies A[kk][l%16] and B[kk][l%16] with kk = l/16 = 2 (pair) + row.
+__global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzlist,
+                                                   const int64_t *nzcount, const int64_t *bin_ptr,
+                                                   const int2 *pairs, const double *rec,
+                                                   const double *zdiag, const double *q,
+                                                   const double *s, const double *alpha,
+                                                   int mode, double *out, int64_t ld) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= *nzcount) return;
+  const int lane = threadIdx.x & 63;
+  const int2 ik = nzlist[w];
+  const int i = ik.x, k = ik.y;
   const int64_t N = 9 * (int64_t)sc.n;
-  const int e0 = lane, e1 = 64 + lane;
-  const bool has1 = lane < 17;
-  const int r0 = e0 % 9, c0 = e0 / 9, r1 = e1 % 9, c1 = e1 / 9;
-  const double a = mode ? *alpha : 0.0;
-  for (int i = k + wid; i < sc.n; i += 4) {
-    double z0, z1;
-    if (i == k) {
-      z0 = zdiag[81 * (int64_t)k + 9 * r0 + c0];
-      z1 = has1 ? zdiag[81 * (int64_t)k + 9 * r1 + c1] : 0.0;
-    } else {
-      z0 = 0.0;
-      z1 = 0.0;
-      const int64_t bin = tri(i) + k;
-      const int64_t b0 = bin_ptr[bin], b1 = bin_ptr[bin + 1];
-      for (int64_t e = b0; e < b1; ++e) {
-        const int2 pr = pairs[e];
-        const double *ra = rec + (int64_t)pr.x * kRec;
-        const double *rb = rec + (int64_t)pr.y * kRec;
-        // K = Y_a J_X,b^T (2x2)
-        double K[2][2];
+  d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  const int col = lane & 15, kk = lane >> 4, p = kk & 1;
+  if (i != k) {
+    const int64_t bin = tri(i) + k;
+    const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
+    for (int64_t e = e0; e < e1; e += 4) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-          for (int qq = 0; qq < 2; ++qq)
-            K[p][qq] = ra[kRecY + 3 * p] * rb[kRecJX + 3 * qq] +
-                       ra[kRecY + 3 * p + 1] * rb[kRecJX + 3 * qq + 1] +
-                       ra[kRecY + 3 * p + 2] * rb[kRecJX + 3 * qq + 2];
-        {
-          const double pa0 = ra[kRecJP + r0], pa1 = ra[kRecJP + 9 + r0];
-          const double pb0 = rb[kRecJP + c0], pb1 = rb[kRecJP + 9 + c0];
-          z0 -= pa0 * (K[0][0] * pb0 + K[0][1] * pb1) + pa1 * (K[1][0] * pb0 + K[1][1] * pb1);
+      for (int h = 0; h < 2; ++h) {
+        const int64_t ee = e + 2 * h + (kk >> 1);
+        double av = 0.0, bv = 0.0;
+        if (ee < e1 && col < 9) {
+          const int2 pr = pairs[ee];
+          const double *ra = rec + (int64_t)pr.x * kRec;
+          const double *rb = rec + (int64_t)pr.y * kRec;
+          av = ra[kRecJP + 9 * p + col];
+          const double y0 = ra[kRecY + 3 * p], y1 = ra[kRecY + 3 * p + 1], y2 = ra[kRecY + 3 * p + 2];
+          const double k0 = y0 * rb[kRecJX + 0] + y1 * rb[kRecJX + 1] + y2 * rb[kRecJX + 2];
+          const double k1 = y0 * rb[kRecJX + 3] + y1 * rb[kRecJX + 4] + y2 * rb[kRecJX + 5];
+          bv = k0 * rb[kRecJP + col] + k1 * rb[kRecJP + 9 + col];
         }
-        if (has1) {
-          const double pa0 = ra[kRecJP + r1], pa1 = ra[kRecJP + 9 + r1];
-          const double pb0 = rb[kRecJP + c1], pb1 = rb[kRecJP + 9 + c1];
-          z1 -= pa0 * (K[0][0] * pb0 + K[0][1] * pb1) + pa1 * (K[1][0] * pb0 + K[1][1] * pb1);
-        }
+        if (h == 0) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
+        else acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
       }
     }
-    const int64_t row0 = 9 * (int64_t)i, col0 = 9 * (int64_t)k;
+  }
+  const double a = mode ? *alpha : 0.0;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const int row = 4 * v + (lane >> 4);
+    if (row >= 9 || col >= 9) continue;
+    const double z = (i == k) ? zdiag[81 * (int64_t)i + 9 * row + col] : -(acc0[v] + acc1[v]);
+    const int64_t pr = 9 * (int64_t)i + row, pc = 9 * (int64_t)k + col;
     if (mode == 0) {
-      out[(col0 + c0) * ld + row0 + r0] = z0;
-      if (i != k) out[(row0 + r0) * ld + col0 + c0] = z0;
-      if (has1) {
-        out[(col0 + c1) * ld + row0 + r1] = z1;
-        if (i != k) out[(row0 + r1) * ld + col0 + c1] = z1;
-      }
+      out[pr + pc * ld] = z;
+      out[pc + pr * ld] = z;
     } else {
-      {
-        const int64_t pr = row0 + r0, pc = col0 + c0;
-        double g = 0.0;
+      double g = 0.0;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) g += q[c * N + pr] * q[c * N + pc];
-        out[pc * ld + pr] = s[pr] * (z0 + a * g) * s[pc];
-      }
-      if (has1) {
-        const int64_t pr = row0 + r1, pc = col0 + c1;
-        double g = 0.0;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) g += q[c * N + pr] * q[c * N + pc];
-        out[pc * ld + pr] = s[pr] * (z1 + a * g) * s[pc];
-      }
+      for (int h = 0; h < 7; ++h) g += q[h * N + pr] * q[h * N + pc];
+      out[pr + pc * ld] = s[pr] * (z + a * g) * s[pc];
     }
   }
 }
@@ -861,7 +881,8 @@ void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStr
 
 void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_count, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
-                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_cnt);
+                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_cnt, w.nzlist,
+                     reinterpret_cast<unsigned long long *>(w.nzcount));
 }
 
 void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st) {
@@ -882,9 +903,14 @@ void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
 }
 
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs, w.rec,
-                     w.zdiag, w.q, w.s, w.alpha, mode, out, ld);
+                     int64_t n_nonzero, hipStream_t st) {
+  const int64_t N = 9 * (int64_t)sc.n;
+  hipLaunchKernelGGL(k_fill_empty, dim3(blocks_for(N, kBlk), (unsigned)N), dim3(kBlk), 0, st, N,
+                     w.bin_cnt, w.q, w.s, w.alpha, mode, out, ld);
+  if (n_nonzero > 0)
+    hipLaunchKernelGGL(k_bin_blocks, dim3(blocks_for(n_nonzero, 4)), dim3(256), 0, st, sc,
+                       w.nzlist, w.nzcount, w.bin_ptr, w.pairs, w.rec, w.zdiag, w.q, w.s,
+                       w.alpha, mode, out, ld);
 }
 
 }  // namespace ucov

@@ -38,11 +38,12 @@ struct ucov_ctx {
   std::string last_error;
   DevStatus *ds = nullptr;       // device
   DevStatus *ds_host = nullptr;  // pinned host mirror
-  int64_t *i64_host = nullptr;   // pinned host scalar
+  int64_t *i64_host = nullptr;   // pinned host scalars [0] pairs, [1] non-empty bins
+  int64_t n_nonzero = 0;         // non-empty bins of the last scene stage
   hipEvent_t ev[8] = {};
   // workspace
   Buf cnt_p, ptr_p, cur_p, slot_obs, slot_cam, slot_pt, rec;
-  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp;
+  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount;
   Buf zdiag, hc, q, s, alpha, amat, tmat;
 
   int fail(int code, const std::string &msg) {
@@ -164,19 +165,26 @@ int run_scene_stage(ucov_ctx *c, const ucov_scene *scene, double *jp_out, double
   UCOV_TRY(ensure(c, c->bin_cnt, 4 * nbins));
   UCOV_TRY(ensure(c, c->bin_ptr, 8 * (nbins + 1)));
   UCOV_TRY(ensure(c, c->bin_cur, 4 * nbins));
+  UCOV_TRY(ensure(c, c->nzlist, sizeof(int2) * nbins));  // at most one entry per bin
+  UCOV_TRY(ensure(c, c->nzcount, 8));
   w.bin_cnt = as<int32_t>(c->bin_cnt);
   w.bin_ptr = as<int64_t>(c->bin_ptr);
   w.bin_cur = as<int32_t>(c->bin_cur);
+  w.nzlist = as<int2>(c->nzlist);
+  w.nzcount = as<int64_t>(c->nzcount);
   launch_point_blocks(sc, w, c->ds, st);
   fill_i32(w.bin_cnt, 0, nbins, st);
   fill_i32(w.bin_cur, 0, nbins, st);
+  fill_i32(reinterpret_cast<int32_t *>(w.nzcount), 0, 2, st);
   launch_pair_count(sc, w, st);
   exclusive_scan(w.bin_cnt, w.bin_ptr, nbins, w.scan_tmp, st);
   UCOV_TRY(check_hip(c, "point kernels"));
   // the pair count sizes the next buffer: one host round trip
   hipMemcpyAsync(c->i64_host, w.bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(c->i64_host + 1, w.nzcount, sizeof(int64_t), hipMemcpyDeviceToHost, st);
   UCOV_TRY(sync_status(c, rep, "point blocks"));
-  const int64_t npairs = *c->i64_host;
+  const int64_t npairs = c->i64_host[0];
+  c->n_nonzero = c->i64_host[1];
   if (rep) rep->n_pairs = npairs;
   UCOV_TRY(ensure(c, c->pairs, sizeof(int2) * npairs));
   UCOV_TRY(ensure(c, c->zdiag, 8 * 81 * n));
@@ -204,6 +212,8 @@ SceneWork scene_work(ucov_ctx *c) {
   w.bin_ptr = as<int64_t>(c->bin_ptr);
   w.bin_cur = as<int32_t>(c->bin_cur);
   w.pairs = as<int2>(c->pairs);
+  w.nzlist = as<int2>(c->nzlist);
+  w.nzcount = as<int64_t>(c->nzcount);
   w.zdiag = as<double>(c->zdiag);
   w.hc = as<double>(c->hc);
   w.q = as<double>(c->q);
@@ -243,15 +253,13 @@ void fill_defaults(const ucov_options *opt, ucov_options &o) {
 int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_out,
                     ucov_report *rep) {
   const int64_t Np = round_up(N, kTile);
-  const int64_t tiles = Np / kTile;
-  const int64_t ldt = ((tiles + 1) / 2) * kTile;
-  UCOV_TRY(ensure(c, c->tmat, 8 * ldt * ldt));
+  UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
   hipStream_t st = c->stream;
   double *A = as<double>(c->amat);
   launch_pad_identity(N, Np, A, Np, st);
   hipEventRecord(c->ev[3], st);
   if (o.precision != UCOV_FP64) return c->fail(UCOV_EINVAL, "unsupported precision");
-  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), ldt, c->ds, st);
+  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
   hipEventRecord(c->ev[4], st);
   launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), as<double>(c->alpha), cov_out,
                  st);
@@ -281,7 +289,7 @@ int ucov_create(ucov_ctx **ctx, int device) {
   c->device = device;
   if (hipMalloc(&c->ds, sizeof(DevStatus)) != hipSuccess ||
       hipHostMalloc(&c->ds_host, sizeof(DevStatus)) != hipSuccess ||
-      hipHostMalloc(&c->i64_host, sizeof(int64_t)) != hipSuccess) {
+      hipHostMalloc(&c->i64_host, 2 * sizeof(int64_t)) != hipSuccess) {
     hipGetLastError();
     delete c;
     return UCOV_ENOMEM;
@@ -307,7 +315,7 @@ void ucov_destroy(ucov_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_obs, &c->slot_cam, &c->slot_pt,
-                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp,
+                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
@@ -338,7 +346,7 @@ int ucov_reduced_camera_matrix(ucov_ctx *c, const ucov_scene *scene, double *z, 
   UCOV_TRY(run_scene_stage(c, scene, nullptr, nullptr, false, rep));
   SceneDev sc = scene_dev(scene);
   SceneWork w = scene_work(c);
-  launch_assemble(sc, w, 0, z, ldz, c->stream);
+  launch_assemble(sc, w, 0, z, ldz, c->n_nonzero, c->stream);
   UCOV_TRY(check_hip(c, "assemble"));
   return sync_status(c, rep, "reduced camera matrix");
 }
@@ -380,7 +388,7 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   SceneWork w = scene_work(c);
   hipEventRecord(c->ev[2], c->stream);
   launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, c->stream);
-  launch_assemble(sc, w, 1, as<double>(c->amat), Np, c->stream);
+  launch_assemble(sc, w, 1, as<double>(c->amat), Np, c->n_nonzero, c->stream);
   UCOV_TRY(check_hip(c, "assemble"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
   if (rep) {

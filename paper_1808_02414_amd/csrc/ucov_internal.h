@@ -53,6 +53,8 @@ struct SceneWork {
   int64_t *bin_ptr;   // nbins + 1
   int32_t *bin_cur;   // nbins
   int2 *pairs;        // n_pairs (slot a of camera i, slot b of camera k)
+  int2 *nzlist;       // (i, k) of every non-empty bin, in arbitrary order
+  int64_t *nzcount;   // [0]: number of non-empty bins
   // per camera
   double *zdiag;      // n x 81, diagonal blocks of Z (row-major)
   double *hc;         // N x 7 column-major (ld N)
@@ -82,9 +84,9 @@ void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
                   const double *zdense, int64_t ldz, double user_alpha, double *s,
                   double *alpha, DevStatus *ds, hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
-// S (Z + a QQ^T) S into out
+// S (Z + a QQ^T) S into out.  n_nonzero is the number of non-empty bins.
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
-                     hipStream_t st);
+                     int64_t n_nonzero, hipStream_t st);
 
 // ---- dense stage (dense_kernels.hip) ---------------------------------------
 // Scaled positive-definite matrix a = S (Z + alpha QQ^T) S from a caller's Z.
@@ -93,9 +95,11 @@ void launch_scale_dense(int64_t N, const double *z, int64_t ldz, const double *q
                         hipStream_t st);
 // Identity on the padding rows/columns [N, Np) of the lower triangle.
 void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStream_t st);
-// In-place L^-1 of the Cholesky factor of the lower triangle of a (Np x Np).
-void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, int64_t ldt,
-                            DevStatus *ds, hipStream_t st);
+// In-place L^-1 of the Cholesky factor of the lower triangle of a (Np x Np),
+// using tmp (spd_lower_inverse_scratch(Np) doubles) as workspace.
+int64_t spd_lower_inverse_scratch(int64_t Np);
+void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
+                            hipStream_t st);
 // cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
                     const double *q, const double *alpha, double *cov, hipStream_t st);
