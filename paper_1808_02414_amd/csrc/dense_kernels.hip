@@ -396,6 +396,223 @@ __global__ __launch_bounds__(NT) void k_leaf(double *A, int64_t lda, int64_t o, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Leaf of NB x NB (64 or 128) on MFMA: Cholesky factor and inverse with the
+// block resident in LDS (column-major, padded leading dimension) and 16-column
+// panels.  Factorisation, panel p:
+//   1. one wave factors the 16x16 diagonal block in registers (cross-lane
+//      shuffles, reciprocal square roots refined by Newton steps) and inverts
+//      it: L_pp and L_pp^-1;
+//   2. the panel below: L_ip = A_ip L_pp^-T            (FP64 MFMA, 4 waves)
+//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (FP64 MFMA, 4 waves)
+// Inversion (forward elimination of L Y = I by block rows), panel p:
+//   a. L(., p) is staged in the unused upper blocks of block row p, and
+//      Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1;
+//   b. W(i, c) -= L_ip Y(p, c) for i > p, c <= p.
+// Writes L^-1 (lower) into the tile and zeros above its diagonal.
+// ---------------------------------------------------------------------------
+constexpr int kLP = 4;  // LDS leading-dimension padding (doubles)
+
+// Broadcast lane l's value of x to the whole wave (scalar lane reads).
+__device__ inline double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double rsqrt_nr(double x) {
+  // hardware reciprocal square root, then two Newton-Raphson steps
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64_t o,
+                                                  DevStatus *ds) {
+  constexpr int LD = NB + kLP;
+  constexpr int NPAN = NB / 16;
+  __shared__ double S[NB * LD];
+  __shared__ double Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double *T = A + o + o * lda;
+  // whole columns with 16-byte loads (the upper part is read and discarded)
+  constexpr int NL = NB * NB / 2 / 256;
+  double2 ld2[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = 2 * (tid + 256 * k);
+    const int r = e % NB, c = e / NB;
+    ld2[k] = *reinterpret_cast<const double2 *>(T + r + (int64_t)c * lda);
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = 2 * (tid + 256 * k);
+    const int r = e % NB, c = e / NB;
+    S[c * LD + r] = r >= c ? ld2[k].x : 0.0;
+    S[c * LD + r + 1] = r + 1 >= c ? ld2[k].y : 0.0;
+  }
+  __syncthreads();
+  const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
+
+  for (int p = 0; p < NPAN; ++p) {
+    const int c0 = 16 * p;
+    // ---- 1. diagonal block on wave 0: lane r < 16 holds row r in registers;
+    //         column values are broadcast with scalar lane reads ----
+    if (wid == 0) {
+      double v[16], y[16], rsv[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        v[c] = S[(c0 + c) * LD + c0 + lr];
+        y[c] = (lr == c) ? 1.0 : 0.0;
+      }
+      bool ok = true;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double piv = readlane_d(v[j], j);
+        ok = ok && (piv > 0.0);
+        const double rs = rsqrt_nr(piv);
+        rsv[j] = rs;
+        const double lj = v[j] * rs;  // L[lr][j]
+#pragma unroll
+        for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane_d(v[j], c) * rs);
+        v[j] = lr > j ? lj : (lr == j ? piv * rs : 0.0);
+      }
+      // y = L^-1: with row y_j final, y_r -= (L[r][j] / L[j][j]) y_j for r > j
+#pragma unroll
+      for (int j = 0; j < 15; ++j) {
+        const double f = v[j] * rsv[j];
+#pragma unroll
+        for (int c = 0; c <= j; ++c) {
+          const double yjc = readlane_d(y[c], j);
+          if (lr > j) y[c] -= f * yjc;
+        }
+      }
+      double my_rs = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) my_rs = (lr == j) ? rsv[j] : my_rs;
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          S[(c0 + c) * LD + c0 + lr] = v[c];
+          Dinv[p][c * 16 + lr] = y[c] * my_rs;
+        }
+      }
+      if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
+    }
+    __syncthreads();
+    // ---- 2. panel: L_ip = A_ip L_pp^-T ----
+    for (int i = p + 1 + wid; i < NPAN; i += 4) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + lg;
+        const double a = S[(c0 + k) * LD + 16 * i + lr];
+        const double b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+    }
+    __syncthreads();
+    // ---- 3. trailing: A_ij -= L_ip L_jp^T, p < j <= i ----
+    {
+      const int m = NPAN - 1 - p;  // trailing block rows
+      const int nblk = m * (m + 1) / 2;
+      for (int b = wid; b < nblk; b += 4) {
+        // b -> (ii, jj) in the lower triangle of the m x m trailing blocks
+        int jj = 0, rem = b;
+        while (rem >= m - jj) {
+          rem -= m - jj;
+          ++jj;
+        }
+        const int i = p + 1 + jj + rem, j = p + 1 + jj;
+        d4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = S[(16 * j + lr) * LD + 16 * i + 4 * v + lg];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const double a = -S[(c0 + k) * LD + 16 * i + lr];
+          const double bb = S[(c0 + k) * LD + 16 * j + lr];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- inversion by block rows ----
+  for (int p = 0; p < NPAN; ++p) {
+    const int c0 = 16 * p;
+    // a. stage L(i, p), i > p, in block (p, i) (upper, unused) as a 16x16
+    //    column-major copy; Y(p, c) = L_pp^-1 W(p, c) for c < p; Y(p, p).
+    for (int i = p + 1 + wid; i < NPAN; i += 4) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lg;  // (row r, col lr) of L_ip
+        S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
+      }
+    }
+    for (int c = wid; c <= p; c += 4) {
+      if (c == p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = lg + 4 * v;
+          S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * 16 + lr];
+        }
+      } else {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const double a = Dinv[p][k * 16 + lr];                  // (L_pp^-1)[lr][k]
+          const double b = S[(16 * c + lr) * LD + c0 + k];         // W(p, c)[k][lr]
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + 4 * v + lg] = acc[v];
+      }
+    }
+    __syncthreads();
+    // b. W(i, c) -= L_ip Y(p, c), i > p, c <= p (W(i, p) starts at zero)
+    {
+      const int m = NPAN - 1 - p;
+      const int nblk = m * (p + 1);
+      for (int b = wid; b < nblk; b += 4) {
+        const int i = p + 1 + b % m, c = b / m;
+        d4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[v] = (c == p) ? 0.0 : S[(16 * c + lr) * LD + 16 * i + 4 * v + lg];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const double a = -S[(16 * i + k) * LD + c0 + lr];        // L_ip[lr][k] from the stage
+          const double bb = S[(16 * c + lr) * LD + c0 + k];       // Y(p, c)[k][lr]
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = 2 * (tid + 256 * k);
+    const int r = e % NB, c = e / NB;
+    double2 x;
+    x.x = r >= c ? S[c * LD + r] : 0.0;
+    x.y = r + 1 >= c ? S[c * LD + r + 1] : 0.0;
+    *reinterpret_cast<double2 *>(T + r + (int64_t)c * lda) = x;
+  }
+}
+
 __global__ void k_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda) {
   const int64_t c = blockIdx.x;
   const int64_t r0 = c > N ? c : N;
@@ -498,11 +715,11 @@ int64_t recurse_scratch(int64_t n) {
 void recurse(double *A, int64_t lda, int64_t o, int64_t n, double *tmp, DevStatus *ds,
              hipStream_t st) {
   if (n == 64) {
-    hipLaunchKernelGGL((k_leaf<64, 192>), dim3(1), dim3(192), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<64>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
     return;
   }
   if (n == 128) {
-    hipLaunchKernelGGL((k_leaf<128, 576>), dim3(1), dim3(576), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<128>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
     return;
   }
   const int64_t tiles = n / 64;

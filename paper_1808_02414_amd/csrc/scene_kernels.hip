@@ -635,11 +635,23 @@ __device__ bool cholqr_pass(int64_t N, const double *A, double *out, double *red
 #pragma unroll
       for (int b = a; b < 7; ++b) g[idx++] += row[a] * row[b];
   }
-  for (int k = 0; k < 28; ++k) {
-    double v = block_sum(g[k], red);
-    if (threadIdx.x == 0) Gs[k] = v;
+  // one reduction pass for all 28 sums: wave sums, then across the waves
+  __shared__ double part[kGaugeThreads / 64][28];
+  {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 28; ++k) {
+      const double v = wave_sum(g[k]);
+      if (lane == 0) part[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 28) {
+      double v = 0.0;
+      for (int w = 0; w < kGaugeThreads / 64; ++w) v += part[w][threadIdx.x];
+      Gs[threadIdx.x] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   __shared__ int okflag;
   if (threadIdx.x == 0) {
     double G[7][7], L[7][7];
@@ -792,23 +804,34 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
   if (i != k) {
     const int64_t bin = tri(i) + k;
     const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
-    for (int64_t e = e0; e < e1; e += 4) {
+    // 16 pairs (8 MFMAs) per iteration; all loads are issued before the MFMAs
+    constexpr int U = 8;
+    for (int64_t e = e0; e < e1; e += 2 * U) {
+      int2 pr[U];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < U; ++h) {
         const int64_t ee = e + 2 * h + (kk >> 1);
-        double av = 0.0, bv = 0.0;
-        if (ee < e1 && col < 9) {
-          const int2 pr = pairs[ee];
-          const double *ra = rec + (int64_t)pr.x * kRec;
-          const double *rb = rec + (int64_t)pr.y * kRec;
-          av = ra[kRecJP + 9 * p + col];
+        pr[h] = (ee < e1) ? pairs[ee] : make_int2(-1, -1);
+      }
+      double av[U], bv[U];
+#pragma unroll
+      for (int h = 0; h < U; ++h) {
+        av[h] = 0.0;
+        bv[h] = 0.0;
+        if (pr[h].x >= 0 && col < 9) {
+          const double *ra = rec + (int64_t)pr[h].x * kRec;
+          const double *rb = rec + (int64_t)pr[h].y * kRec;
+          av[h] = ra[kRecJP + 9 * p + col];
           const double y0 = ra[kRecY + 3 * p], y1 = ra[kRecY + 3 * p + 1], y2 = ra[kRecY + 3 * p + 2];
           const double k0 = y0 * rb[kRecJX + 0] + y1 * rb[kRecJX + 1] + y2 * rb[kRecJX + 2];
           const double k1 = y0 * rb[kRecJX + 3] + y1 * rb[kRecJX + 4] + y2 * rb[kRecJX + 5];
-          bv = k0 * rb[kRecJP + col] + k1 * rb[kRecJP + 9 + col];
+          bv[h] = k0 * rb[kRecJP + col] + k1 * rb[kRecJP + 9 + col];
         }
-        if (h == 0) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
-        else acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < U; h += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[h], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h + 1], bv[h + 1], acc1, 0, 0, 0);
       }
     }
   }
