@@ -110,7 +110,7 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "dense inverse stage (k_leaf64 + k_gemm64 + k_copy), 2N^3/3 flops"},
+                     "kernel": "dense inverse stage (k_leaf_mfma + k_gemm64 + k_gemm64_pair), 2N^3/3 flops"},
         "stages_ms": stages,
         "n_pairs": int(reps[-1]["n_pairs"]),
     }
