@@ -114,6 +114,9 @@ def main():
         "stages_ms": stages,
         "n_pairs": int(reps[-1]["n_pairs"]),
     }
+    if args.precision == "fp32ns":
+        line["ns_iters"] = int(reps[-1]["ns_iters"])
+        line["ns_residual"] = float(reps[-1]["ns_residual"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(line), flush=True)

@@ -70,7 +70,10 @@ extern "C" {
 
 /* Precision of the dense inverse (step a4). */
 #define UCOV_FP64     0   /* FP64 Cholesky inverse on FP64 MFMA */
-#define UCOV_FP32_NS  1   /* FP32 MFMA Cholesky inverse + Newton-Schulz with FP64 residuals */
+#define UCOV_FP32_NS  1   /* FP32 MFMA Cholesky inverse X0 of A_s, then Newton-Schulz steps
+                             X <- X + X (I - A_s X): residual in FP64, correction on FP32
+                             MFMA; UCOV_ENOCONV if the FP32 factorisation fails or the
+                             tolerance is not reached */
 
 typedef struct ucov_ctx ucov_ctx;
 
@@ -88,7 +91,7 @@ typedef struct {
 typedef struct {
   int32_t precision;  /* UCOV_FP64 or UCOV_FP32_NS */
   int32_t max_iter;   /* Newton-Schulz iterations allowed (UCOV_FP32_NS); 0 = default 6 */
-  double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-12 */
+  double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-10 */
   double alpha;       /* gauge weight a; 0 = balanced automatic choice */
 } ucov_options;
 

@@ -9,13 +9,16 @@
 //
 //   [A11      ]        L11^-1 <- recurse(A11)
 //   [A21  A22 ]  ->    T      <- A21 L11^-T            (= L21)
-//                      A22    <- A22 - T T^T
-//                      A21    <- T L11^-1
+//                      A22    <- A22 - T T^T       } one launch
+//                      T2     <- T L11^-1          }
 //                      L22^-1 <- recurse(A22)
-//                      A21    <- -L22^-1 A21           (= (L^-1)21)
+//                      A21    <- -L22^-1 T2            (= (L^-1)21)
 //
-// The leaves are 64x64 or 128x128 blocks factored and inverted by one workgroup;
-// the products run on FP64 MFMA (v_mfma_f64_16x16x4f64) in 64x64 output tiles.
+// Leaves of 128 (or 64) are factored and inverted by one workgroup in LDS;
+// every product runs on MFMA.  The recursion is generic over the element
+// type: FP64 (v_mfma_f64_16x16x4f64) for the plain path, FP32
+// (v_mfma_f32_16x16x4f32) for the initial inverse of the mixed path, which
+// Newton-Schulz steps with FP64 residuals then refine (see ucov_api.hip).
 #include <algorithm>
 
 #include "ucov_internal.h"
@@ -26,93 +29,122 @@ namespace ucov {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-enum KMode { kFull = 0, kLeN = 1, kGeN = 2, kLeM = 3 };
+// MFMA 16x16x4 of the element type.  Operand layout (64 lanes): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16].  Accumulator register v of lane l
+// holds D[row(l, v)][l%16] with row = 4*v + l/16 for FP64 and
+// row = 4*(l/16) + v for FP32 (the two instructions interleave rows
+// differently).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  typedef double2 vec2;
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  typedef float2 vec2;
+  __device__ static acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+enum KMode { kFull = 0, kLeN = 1, kGeN = 2, kLeM = 3, kGeMN = 4 };
 
 // ---------------------------------------------------------------------------
 // C = alpha op(A) op(B) + beta C, 64x64 tile per workgroup, M, N, K multiples
-// of 64.  BT: B is stored N x K and used transposed (C = A B^T); otherwise
-// B is K x N.  LOWER: only tiles on or below the diagonal are computed.
-// kmode restricts the K range to the nonzero part of a triangular operand:
+// of 64.  AT: A is stored K x M and used transposed; BT: B is stored N x K
+// and used transposed; otherwise A is M x K and B is K x N (column-major).
+// LOWER: only tiles on or below the diagonal are computed.  kmode restricts
+// the K range to the nonzero part of a triangular operand (tile granular;
+// the upper part of diagonal tiles of a triangular operand is zero):
 //   kLeN  k < (tile_n + 1) * 64  (B lower triangular, used transposed)
 //   kGeN  k >= tile_n * 64       (B lower triangular)
 //   kLeM  k < (tile_m + 1) * 64  (A lower triangular)
-// MFMA operand layout (16x16x4, 64 lanes): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; the accumulator holds D[4*v + l/16][l%16], v = 0..3.
-// (Measured on MI355X: single-buffered LDS with a register prefetch and
-// occupancy 4 beats double buffering, larger tiles and die-aware tile orders
-// for every product shape of the recursion.)
+//   kGeMN k >= max(tile_m, tile_n) * 64  (A^T B with A, B lower triangular)
+// Measured on MI355X: single-buffered LDS with a register prefetch and 4
+// waves/SIMD occupancy beats double buffering, larger tiles and die-aware
+// tile orders for every product shape of the recursion.
 // ---------------------------------------------------------------------------
-constexpr int kKc = 16;     // K chunk staged in LDS
-constexpr int kLdsPad = 4;  // row padding of the LDS tiles (doubles)
+constexpr int kKc = 16;  // K chunk staged in LDS
+constexpr int kPad = 4;  // row padding of the LDS tiles
 
+template <typename T>
 struct GemmArgs {
   int64_t M, N, K;
-  const double *A;
+  const T *A;
   int64_t lda;
-  const double *B;
+  const T *B;
   int64_t ldb;
-  double *C;
+  T *C;
   int64_t ldc;
-  double alpha, beta;
+  T alpha, beta;
   int kmode;
 };
 
-template <bool BT, bool LOWER>
-__device__ inline void gemm_tile(const GemmArgs &g, int tm, int tn) {
+template <typename T, bool AT, bool BT, bool LOWER>
+__device__ inline void gemm_tile(const GemmArgs<T> &g, int tm, int tn) {
+  typedef Mfma<T> MF;
+  typedef typename MF::vec2 V2;
   if (LOWER && tn > tm) return;
   const int64_t K = g.K, lda = g.lda, ldb = g.ldb, ldc = g.ldc;
-  const double *__restrict__ A = g.A;
-  const double *__restrict__ B = g.B;
-  double *__restrict__ C = g.C;
-  const double alpha = g.alpha, beta = g.beta;
+  const T *__restrict__ A = g.A;
+  const T *__restrict__ B = g.B;
+  T *__restrict__ C = g.C;
   const int kmode = g.kmode;
   int64_t kb = 0, ke = K;
   if (kmode == kLeN) ke = min(K, (int64_t)(tn + 1) * 64);
   else if (kmode == kGeN) kb = (int64_t)tn * 64;
   else if (kmode == kLeM) ke = min(K, (int64_t)(tm + 1) * 64);
+  else if (kmode == kGeMN) kb = (int64_t)max(tm, tn) * 64;
 
-  __shared__ double As[kKc][64 + kLdsPad];
-  __shared__ double Bs[kKc][64 + kLdsPad];
+  __shared__ T As[kKc][64 + kPad];
+  __shared__ T Bs[kKc][64 + kPad];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
-  d4 acc[2][2];
+  typename MF::acc_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = MF::zero();
 
-  const int la_k = tid >> 4, la_m = (tid & 15) * 4;  // A (and B^T) loader
-  const int lb_n = tid >> 2, lb_k = (tid & 3) * 4;   // B (K x N) loader
-  const double *pa = A + (int64_t)tm * 64 + la_m + la_k * lda;
-  const double *pb = BT ? B + (int64_t)tn * 64 + la_m + la_k * ldb
-                        : B + lb_k + ((int64_t)tn * 64 + lb_n) * ldb;
-  double ra[4], rb[4];
+  // loaders: 4 consecutive elements per thread per chunk
+  const int lt_k = tid >> 4, lt_m = (tid & 15) * 4;  // K-major tile (M contiguous)
+  const int lc_m = tid >> 2, lc_k = (tid & 3) * 4;   // M-major tile (K contiguous)
+  const T *pa = AT ? A + lc_k + ((int64_t)tm * 64 + lc_m) * lda
+                   : A + (int64_t)tm * 64 + lt_m + lt_k * lda;
+  const T *pb = BT ? B + (int64_t)tn * 64 + lt_m + lt_k * ldb
+                   : B + lc_k + ((int64_t)tn * 64 + lc_m) * ldb;
+  T ra[4], rb[4];
   auto load = [&](int64_t k0) {
-    const double2 a01 = *reinterpret_cast<const double2 *>(pa + k0 * lda);
-    const double2 a23 = *reinterpret_cast<const double2 *>(pa + k0 * lda + 2);
+    const T *qa = AT ? pa + k0 : pa + k0 * lda;
+    const V2 a01 = *reinterpret_cast<const V2 *>(qa);
+    const V2 a23 = *reinterpret_cast<const V2 *>(qa + 2);
     ra[0] = a01.x; ra[1] = a01.y; ra[2] = a23.x; ra[3] = a23.y;
-    if (BT) {
-      const double2 b01 = *reinterpret_cast<const double2 *>(pb + k0 * ldb);
-      const double2 b23 = *reinterpret_cast<const double2 *>(pb + k0 * ldb + 2);
-      rb[0] = b01.x; rb[1] = b01.y; rb[2] = b23.x; rb[3] = b23.y;
-    } else {
-      const double2 b01 = *reinterpret_cast<const double2 *>(pb + k0);
-      const double2 b23 = *reinterpret_cast<const double2 *>(pb + k0 + 2);
-      rb[0] = b01.x; rb[1] = b01.y; rb[2] = b23.x; rb[3] = b23.y;
-    }
+    const T *qb = BT ? pb + k0 * ldb : pb + k0;
+    const V2 b01 = *reinterpret_cast<const V2 *>(qb);
+    const V2 b23 = *reinterpret_cast<const V2 *>(qb + 2);
+    rb[0] = b01.x; rb[1] = b01.y; rb[2] = b23.x; rb[3] = b23.y;
   };
   if (kb < ke) load(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += kKc) {
     __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 4; ++v) As[la_k][la_m + v] = ra[v];
-    if (BT) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Bs[la_k][la_m + v] = rb[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Bs[lb_k + v][lb_n] = rb[v];
+    for (int v = 0; v < 4; ++v) {
+      if (AT) As[lc_k + v][lc_m] = ra[v];
+      else As[lt_k][lt_m + v] = ra[v];
+      if (BT) Bs[lt_k][lt_m + v] = rb[v];
+      else Bs[lc_k + v][lc_m] = rb[v];
     }
     __syncthreads();
     if (k0 + kKc < ke) load(k0 + kKc);  // prefetch the next chunk during the MFMAs
@@ -120,12 +152,12 @@ __device__ inline void gemm_tile(const GemmArgs &g, int tm, int tn) {
     for (int kk = 0; kk < kKc / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
       const int c = lane & 15;
-      const double a0 = As[kr][wm * 32 + c], a1 = As[kr][wm * 32 + 16 + c];
-      const double b0 = Bs[kr][wn * 32 + c], b1 = Bs[kr][wn * 32 + 16 + c];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = As[kr][wm * 32 + c], a1 = As[kr][wm * 32 + 16 + c];
+      const T b0 = Bs[kr][wn * 32 + c], b1 = Bs[kr][wn * 32 + 16 + c];
+      acc[0][0] = MF::mma(a0, b0, acc[0][0]);
+      acc[0][1] = MF::mma(a0, b1, acc[0][1]);
+      acc[1][0] = MF::mma(a1, b0, acc[1][0]);
+      acc[1][1] = MF::mma(a1, b1, acc[1][1]);
     }
   }
 #pragma unroll
@@ -133,266 +165,34 @@ __device__ inline void gemm_tile(const GemmArgs &g, int tm, int tn) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int64_t col = (int64_t)tn * 64 + wn * 32 + bj * 16 + (lane & 15);
-      const int64_t row = (int64_t)tm * 64 + wm * 32 + bi * 16 + (lane >> 4);
-      double *pc = C + row + col * ldc;
+      const int64_t row0 = (int64_t)tm * 64 + wm * 32 + bi * 16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double x = alpha * acc[bi][bj][v];
-        pc[4 * v] = beta == 0.0 ? x : x + beta * pc[4 * v];
+        T *pc = C + row0 + MF::row(lane, v) + col * ldc;
+        const T x = g.alpha * acc[bi][bj][v];
+        *pc = g.beta == T(0) ? x : x + g.beta * (*pc);
       }
     }
 }
 
 // One product; grid (M/64, N/64), tile rows fastest.
-template <bool BT, bool LOWER>
-__global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
-  gemm_tile<BT, LOWER>(g, blockIdx.x, blockIdx.y);
+template <typename T, bool AT, bool BT, bool LOWER>
+__global__ __launch_bounds__(256) void k_gemm64(GemmArgs<T> g) {
+  gemm_tile<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
 }
 
 // The two independent products of one recursion node in one launch: the
 // Schur update A22 -= T T^T (lower tiles, first nblk_s workgroups) and
 // T2 = T L11^-1.
-__global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs s, GemmArgs t, int nblk_s) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> t, int nblk_s) {
   const int b = blockIdx.x;
   if (b < nblk_s) {
     const int mt = (int)(s.M / 64);
-    gemm_tile<true, true>(s, b % mt, b / mt);
+    gemm_tile<T, false, true, true>(s, b % mt, b / mt);
   } else {
     const int mt = (int)(t.M / 64), bb = b - nblk_s;
-    gemm_tile<false, false>(t, bb % mt, bb / mt);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Leaf of NB x NB (64 or 128): Cholesky factor L of the lower triangle and its
-// inverse L^-1, by 4-column block steps.  The lower triangle is cut into 4x4
-// micro-tiles (R, C), one per thread, held in registers.
-//
-// Factorisation, block step J:
-//   1. the owners of block column J publish their (updated) tiles in LDS;
-//   2. they factor the 4x4 diagonal block D = L_JJ L_JJ^T (each one locally)
-//      and publish L(R,J) = A(R,J) L_JJ^-T;
-//   3. every tile right of J applies A(R,C) -= L(R,J) L(C,J)^T.
-// Inversion, block step J (right-looking forward elimination of L Y = I):
-//   Y(J,C) = L_JJ^-1 W(J,C), then W(R,C) -= L(R,J) Y(J,C) for R > J, C <= J.
-// Writes L^-1 (lower) into the tile and zeros above its diagonal.
-// ---------------------------------------------------------------------------
-// 4x4 Cholesky of the symmetric block d (only d[a][b], a >= b, is read):
-// writes the lower factor into l and its inverse into li; returns false if a
-// pivot is not positive.
-__device__ inline bool chol4(const double (&d)[4][4], double (&l)[4][4], double (&li)[4][4]) {
-  bool ok = true;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) l[a][b] = 0.0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    double p = d[j][j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) p -= l[j][k] * l[j][k];
-    ok = ok && (p > 0.0);
-    const double ljj = sqrt(p);
-    const double il = 1.0 / ljj;
-    l[j][j] = ljj;
-#pragma unroll
-    for (int r = j + 1; r < 4; ++r) {
-      double x = d[r][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) x -= l[r][k] * l[j][k];
-      l[r][j] = x * il;
-    }
-    li[j][j] = il;
-  }
-  // li = l^-1 (lower), column by column
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (r < c) li[r][c] = 0.0;
-      if (r > c) {
-        double x = 0.0;
-#pragma unroll
-        for (int k = c; k < r; ++k) x -= l[r][k] * li[k][c];
-        li[r][c] = x * li[r][r];
-      }
-    }
-  }
-  return ok;
-}
-
-template <int NB, int NT>
-__global__ __launch_bounds__(NT) void k_leaf(double *A, int64_t lda, int64_t o, DevStatus *ds) {
-  constexpr int MB = NB / 4;                // micro-tiles per edge
-  constexpr int NMT = MB * (MB + 1) / 2;    // lower-triangle micro-tiles
-  static_assert(NMT <= NT, "one micro-tile per thread");
-  // panels indexed [column b][row a within the tile][tile row R] so that lanes
-  // (consecutive tile rows) touch consecutive words
-  __shared__ double P[4][4][MB];            // raw block column J
-  __shared__ double Q[2][4][4][MB];         // L(., J)
-  __shared__ double Yb[2][4][NB];           // block row J of W
-  __shared__ double Dinv[MB][4][4];         // L_JJ^-1
-  const int tid = threadIdx.x;
-  const bool own = tid < NMT;
-  double *T = A + o + o * lda;
-  int R = MB, C = MB;  // idle threads own no tile
-  if (own) {
-    const double b = 2.0 * MB + 1.0;
-    int cg = (int)((b - sqrt(b * b - 8.0 * tid)) * 0.5);
-    cg = cg < 0 ? 0 : (cg > MB - 1 ? MB - 1 : cg);
-    while (cg > 0 && cg * MB - cg * (cg - 1) / 2 > tid) --cg;
-    while (cg < MB - 1 && (cg + 1) * MB - (cg + 1) * cg / 2 <= tid) ++cg;
-    C = cg;
-    R = C + (tid - (C * MB - C * (C - 1) / 2));
-  }
-  const int r0 = 4 * R, c0 = 4 * C;
-  const int rr = own ? r0 : 0, cr = own ? c0 : 0;  // clamped LDS indices
-  double v[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      // diagonal tiles are loaded symmetric so they stay symmetric under updates
-      const int r = r0 + a, c = c0 + b;
-      const int hi = r > c ? r : c, lo = r > c ? c : r;
-      v[a][b] = own ? T[hi + (int64_t)lo * lda] : 0.0;
-    }
-
-  for (int J = 0; J < MB; ++J) {
-    if (C == J) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) P[b][a][R] = v[a][b];
-    }
-    __syncthreads();
-    if (C == J) {
-      double d[4][4], l[4][4], li[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) d[a][b] = P[b][a][J];
-      const bool ok = chol4(d, l, li);
-      if (R == J) {
-        if (!ok) report_error(ds, UCOV_EGAUGE, (int)((o + 4 * J) / 9));
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            v[a][b] = l[a][b];
-            Dinv[J][a][b] = li[a][b];
-          }
-      } else {
-        // L(R,J) = A(R,J) L_JJ^-T: row a times li^T
-        double x[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int m = 0; m <= k; ++m) acc += v[a][m] * li[k][m];
-            x[a][k] = acc;
-          }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            v[a][b] = x[a][b];
-            Q[0][b][a][R] = x[a][b];
-          }
-      }
-    }
-    __syncthreads();
-    if (C > J && C < MB) {
-      double lr[4][4], lc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          lr[a][b] = Q[0][b][a][rr >> 2];
-          lc[a][b] = Q[0][b][a][cr >> 2];
-        }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          v[a][b] -= lr[a][0] * lc[b][0] + lr[a][1] * lc[b][1] + lr[a][2] * lc[b][2] +
-                     lr[a][3] * lc[b][3];
-    }
-  }
-  // v now holds L (lower; the upper part of diagonal tiles is zero)
-  double y[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) y[a][b] = (R == C && a == b) ? 1.0 : 0.0;
-  for (int J = 0; J < MB; ++J) {
-    const int buf = J & 1;
-    if (C == J && R > J) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) Q[buf][b][a][R] = v[a][b];
-    }
-    if (R == J) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) Yb[buf][a][c0 + b] = y[a][b];
-    }
-    __syncthreads();
-    if (C <= J && R >= J && R < MB) {
-      double di[4][4], w[4][4], x[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          di[a][b] = Dinv[J][a][b];
-          w[a][b] = Yb[buf][a][cr + b];
-        }
-      // X = Y(J,C) = L_JJ^-1 W(J,C)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = 0; m <= a; ++m) acc += di[a][m] * w[m][b];
-          x[a][b] = acc;
-        }
-      if (R == J) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) y[a][b] = x[a][b];
-      } else {
-        double lr[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) lr[a][b] = Q[buf][b][a][rr >> 2];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            y[a][b] -= lr[a][0] * x[0][b] + lr[a][1] * x[1][b] + lr[a][2] * x[2][b] +
-                       lr[a][3] * x[3][b];
-      }
-    }
-  }
-  if (own) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = r0 + a, c = c0 + b;
-        T[r + (int64_t)c * lda] = r >= c ? y[a][b] : 0.0;
-      }
-  }
-  for (int e = tid; e < NB * NB; e += NT) {
-    const int r = e % NB, c = e / NB;
-    if ((r >> 2) < (c >> 2)) T[r + (int64_t)c * lda] = 0.0;
+    gemm_tile<T, false, false, false>(t, bb % mt, bb / mt);
   }
 }
 
@@ -400,97 +200,106 @@ __global__ __launch_bounds__(NT) void k_leaf(double *A, int64_t lda, int64_t o, 
 // Leaf of NB x NB (64 or 128) on MFMA: Cholesky factor and inverse with the
 // block resident in LDS (column-major, padded leading dimension) and 16-column
 // panels.  Factorisation, panel p:
-//   1. one wave factors the 16x16 diagonal block in registers (cross-lane
-//      shuffles, reciprocal square roots refined by Newton steps) and inverts
-//      it: L_pp and L_pp^-1;
-//   2. the panel below: L_ip = A_ip L_pp^-T            (FP64 MFMA, 4 waves)
-//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (FP64 MFMA, 4 waves)
+//   1. one wave factors the 16x16 diagonal block in registers (row per lane,
+//      scalar lane broadcasts, hardware reciprocal square roots refined by
+//      Newton steps) and inverts it: L_pp and L_pp^-1;
+//   2. the panel below: L_ip = A_ip L_pp^-T            (MFMA, 4 waves)
+//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA, 4 waves)
 // Inversion (forward elimination of L Y = I by block rows), panel p:
 //   a. L(., p) is staged in the unused upper blocks of block row p, and
 //      Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1;
 //   b. W(i, c) -= L_ip Y(p, c) for i > p, c <= p.
 // Writes L^-1 (lower) into the tile and zeros above its diagonal.
 // ---------------------------------------------------------------------------
-constexpr int kLP = 4;  // LDS leading-dimension padding (doubles)
+constexpr int kLP = 4;  // LDS leading-dimension padding
 
 // Broadcast lane l's value of x to the whole wave (scalar lane reads).
-__device__ inline double readlane_d(double x, int l) {
+__device__ inline double readlane(double x, int l) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)b, l);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+__device__ inline float readlane(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
 
+// Hardware reciprocal square root refined by Newton-Raphson steps
+// (y <- y (3 - x y^2) / 2) to the working precision.
 __device__ inline double rsqrt_nr(double x) {
-  // hardware reciprocal square root, then two Newton-Raphson steps
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
   y = y * (1.5 - 0.5 * x * y * y);
   return y;
 }
+__device__ inline float rsqrt_nr(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  y = y * (1.5f - 0.5f * x * y * y);
+  return y;
+}
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64_t o,
-                                                  DevStatus *ds) {
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_leaf_mfma(T *A, int64_t lda, int64_t o, DevStatus *ds) {
+  typedef Mfma<T> MF;
+  typedef typename MF::vec2 V2;
   constexpr int LD = NB + kLP;
   constexpr int NPAN = NB / 16;
-  __shared__ double S[NB * LD];
-  __shared__ double Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
+  __shared__ T S[NB * LD];
+  __shared__ T Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  double *T = A + o + o * lda;
-  // whole columns with 16-byte loads (the upper part is read and discarded)
+  T *G = A + o + o * lda;
+  // whole columns with paired loads (the upper part is read and discarded)
   constexpr int NL = NB * NB / 2 / 256;
-  double2 ld2[NL];
+  V2 ld2[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     const int e = 2 * (tid + 256 * k);
     const int r = e % NB, c = e / NB;
-    ld2[k] = *reinterpret_cast<const double2 *>(T + r + (int64_t)c * lda);
+    ld2[k] = *reinterpret_cast<const V2 *>(G + r + (int64_t)c * lda);
   }
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     const int e = 2 * (tid + 256 * k);
     const int r = e % NB, c = e / NB;
-    S[c * LD + r] = r >= c ? ld2[k].x : 0.0;
-    S[c * LD + r + 1] = r + 1 >= c ? ld2[k].y : 0.0;
+    S[c * LD + r] = r >= c ? ld2[k].x : T(0);
+    S[c * LD + r + 1] = r + 1 >= c ? ld2[k].y : T(0);
   }
   __syncthreads();
   const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
 
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
-    // ---- 1. diagonal block on wave 0: lane r < 16 holds row r in registers;
-    //         column values are broadcast with scalar lane reads ----
+    // ---- 1. diagonal block on wave 0: lane r < 16 holds row r ----
     if (wid == 0) {
-      double v[16], y[16], rsv[16];
+      T v[16], y[16], rsv[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         v[c] = S[(c0 + c) * LD + c0 + lr];
-        y[c] = (lr == c) ? 1.0 : 0.0;
+        y[c] = (lr == c) ? T(1) : T(0);
       }
       bool ok = true;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double piv = readlane_d(v[j], j);
-        ok = ok && (piv > 0.0);
-        const double rs = rsqrt_nr(piv);
+        const T piv = readlane(v[j], j);
+        ok = ok && (piv > T(0));
+        const T rs = rsqrt_nr(piv);
         rsv[j] = rs;
-        const double lj = v[j] * rs;  // L[lr][j]
+        const T lj = v[j] * rs;  // L[lr][j]
 #pragma unroll
-        for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane_d(v[j], c) * rs);
-        v[j] = lr > j ? lj : (lr == j ? piv * rs : 0.0);
+        for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane(v[j], c) * rs);
+        v[j] = lr > j ? lj : (lr == j ? piv * rs : T(0));
       }
       // y = L^-1: with row y_j final, y_r -= (L[r][j] / L[j][j]) y_j for r > j
 #pragma unroll
       for (int j = 0; j < 15; ++j) {
-        const double f = v[j] * rsv[j];
+        const T f = v[j] * rsv[j];
 #pragma unroll
         for (int c = 0; c <= j; ++c) {
-          const double yjc = readlane_d(y[c], j);
+          const T yjc = readlane(y[c], j);
           if (lr > j) y[c] -= f * yjc;
         }
       }
-      double my_rs = 0.0;
+      T my_rs = T(0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) my_rs = (lr == j) ? rsv[j] : my_rs;
       if (lane < 16) {
@@ -505,16 +314,16 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
     __syncthreads();
     // ---- 2. panel: L_ip = A_ip L_pp^-T ----
     for (int i = p + 1 + wid; i < NPAN; i += 4) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      typename MF::acc_t acc = MF::zero();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int k = 4 * kk + lg;
-        const double a = S[(c0 + k) * LD + 16 * i + lr];
-        const double b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        const T a = S[(c0 + k) * LD + 16 * i + lr];
+        const T b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+        acc = MF::mma(a, b, acc);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+      for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
     }
     __syncthreads();
     // ---- 3. trailing: A_ij -= L_ip L_jp^T, p < j <= i ----
@@ -522,25 +331,24 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
       const int m = NPAN - 1 - p;  // trailing block rows
       const int nblk = m * (m + 1) / 2;
       for (int b = wid; b < nblk; b += 4) {
-        // b -> (ii, jj) in the lower triangle of the m x m trailing blocks
-        int jj = 0, rem = b;
+        int jj = 0, rem = b;  // b -> (ii, jj) in the lower triangle of m x m blocks
         while (rem >= m - jj) {
           rem -= m - jj;
           ++jj;
         }
         const int i = p + 1 + jj + rem, j = p + 1 + jj;
-        d4 acc;
+        typename MF::acc_t acc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = S[(16 * j + lr) * LD + 16 * i + 4 * v + lg];
+        for (int v = 0; v < 4; ++v) acc[v] = S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + lg;
-          const double a = -S[(c0 + k) * LD + 16 * i + lr];
-          const double bb = S[(c0 + k) * LD + 16 * j + lr];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+          const T a = -S[(c0 + k) * LD + 16 * i + lr];
+          const T bb = S[(c0 + k) * LD + 16 * j + lr];
+          acc = MF::mma(a, bb, acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+        for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
       }
     }
     __syncthreads();
@@ -549,12 +357,11 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
   // ---- inversion by block rows ----
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
-    // a. stage L(i, p), i > p, in block (p, i) (upper, unused) as a 16x16
-    //    column-major copy; Y(p, c) = L_pp^-1 W(p, c) for c < p; Y(p, p).
+    // a. stage L(i, p), i > p, in block (p, i) (upper, unused); Y(p, c)
     for (int i = p + 1 + wid; i < NPAN; i += 4) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = 4 * v + lg;  // (row r, col lr) of L_ip
+        const int r = MF::row(lane, v);  // (row r, col lr) of L_ip
         S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
       }
     }
@@ -566,16 +373,16 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
           S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * 16 + lr];
         }
       } else {
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        typename MF::acc_t acc = MF::zero();
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + lg;
-          const double a = Dinv[p][k * 16 + lr];                  // (L_pp^-1)[lr][k]
-          const double b = S[(16 * c + lr) * LD + c0 + k];         // W(p, c)[k][lr]
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          const T a = Dinv[p][k * 16 + lr];           // (L_pp^-1)[lr][k]
+          const T b = S[(16 * c + lr) * LD + c0 + k];  // W(p, c)[k][lr]
+          acc = MF::mma(a, b, acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + 4 * v + lg] = acc[v];
+        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + MF::row(lane, v)] = acc[v];
       }
     }
     __syncthreads();
@@ -585,19 +392,19 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
       const int nblk = m * (p + 1);
       for (int b = wid; b < nblk; b += 4) {
         const int i = p + 1 + b % m, c = b / m;
-        d4 acc;
+        typename MF::acc_t acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          acc[v] = (c == p) ? 0.0 : S[(16 * c + lr) * LD + 16 * i + 4 * v + lg];
+          acc[v] = (c == p) ? T(0) : S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k = 4 * kk + lg;
-          const double a = -S[(16 * i + k) * LD + c0 + lr];        // L_ip[lr][k] from the stage
-          const double bb = S[(16 * c + lr) * LD + c0 + k];       // Y(p, c)[k][lr]
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+          const T a = -S[(16 * i + k) * LD + c0 + lr];  // L_ip[lr][k] from the stage
+          const T bb = S[(16 * c + lr) * LD + c0 + k];  // Y(p, c)[k][lr]
+          acc = MF::mma(a, bb, acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + 16 * i + 4 * v + lg] = acc[v];
+        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
       }
     }
     __syncthreads();
@@ -606,13 +413,16 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(double *A, int64_t lda, int64
   for (int k = 0; k < NL; ++k) {
     const int e = 2 * (tid + 256 * k);
     const int r = e % NB, c = e / NB;
-    double2 x;
-    x.x = r >= c ? S[c * LD + r] : 0.0;
-    x.y = r + 1 >= c ? S[c * LD + r + 1] : 0.0;
-    *reinterpret_cast<double2 *>(T + r + (int64_t)c * lda) = x;
+    V2 x;
+    x.x = r >= c ? S[c * LD + r] : T(0);
+    x.y = r + 1 >= c ? S[c * LD + r + 1] : T(0);
+    *reinterpret_cast<V2 *>(G + r + (int64_t)c * lda) = x;
   }
 }
 
+// ---------------------------------------------------------------------------
+// elementwise helpers
+// ---------------------------------------------------------------------------
 __global__ void k_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda) {
   const int64_t c = blockIdx.x;
   const int64_t r0 = c > N ? c : N;
@@ -631,10 +441,68 @@ __global__ void k_scale_dense(int64_t N, const double *z, int64_t ldz, const dou
   a[r + c * lda] = s[r] * (z[r + c * ldz] + (*alpha) * g) * s[c];
 }
 
+// lower triangle of a (FP64) -> lower triangle of a32 (FP32), n x n
+__global__ void k_lower_to_f32(int64_t n, const double *a, int64_t lda, float *a32,
+                               int64_t ld32) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n && r >= c) a32[r + c * ld32] = (float)a[r + c * lda];
+}
+
+// a <- full symmetric matrix from its lower triangle (n x n)
+__global__ void k_symmetrize(int64_t n, double *a, int64_t lda) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n && r < c) a[r + c * lda] = a[c + r * lda];
+}
+
+__global__ void k_f32_to_f64(int64_t n, const float *x, int64_t ldx, double *y, int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n) y[r + c * ldy] = (double)x[r + c * ldx];
+}
+
+__global__ void k_f64_to_f32(int64_t n, const double *x, int64_t ldx, float *y, int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n) y[r + c * ldy] = (float)x[r + c * ldx];
+}
+
+__global__ void k_identity(int64_t n, double *a, int64_t lda) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n) a[r + c * lda] = (r == c) ? 1.0 : 0.0;
+}
+
+// x += (double) d
+__global__ void k_add_f32(int64_t n, const float *d, int64_t ldd, double *x, int64_t ldx) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r < n) x[r + c * ldx] += (double)d[r + c * ldd];
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
+}
+
+// out[0] += sum of squares of the n x n matrix (one partial per workgroup,
+// accumulated with an FP64 atomic add; rounding order does not matter for a
+// convergence test)
+__global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *a, int64_t lda,
+                                              double *out) {
+  const int64_t c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const double v = a[r + c * lda];
+    s += v * v;
+  }
+  __shared__ double part[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
 }
 
 // One workgroup per camera: (A_s^-1)_ii = sum over rows r >= 9i of the outer
@@ -679,30 +547,48 @@ __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, 
   }
 }
 
-GemmArgs make_args(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                   const double *B, int64_t ldb, double *C, int64_t ldc, double alpha,
-                   double beta, int kmode) {
-  GemmArgs g;
+// cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X (81 threads
+// per camera)
+__global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
+                               const double *q, const double *alpha, double *cov) {
+  const int64_t i = blockIdx.x;
+  const int t = threadIdx.x;
+  if (t >= 81) return;
+  const int64_t r = 9 * i + t / 9, c = 9 * i + t % 9;
+  const double xs = 0.5 * (x[r + c * ld] + x[c + r * ld]);
+  double g = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) g += q[k * N + r] * q[k * N + c];
+  cov[81 * i + t] = s[r] * xs * s[c] - g / (*alpha);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename T>
+GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B,
+                      int64_t ldb, T *C, int64_t ldc, T alpha, T beta, int kmode) {
+  GemmArgs<T> g;
   g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.alpha = alpha; g.beta = beta; g.kmode = kmode;
   return g;
 }
 
-template <bool BT, bool LOWER>
-void gemm(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
-          int64_t ldb, double *C, int64_t ldc, double alpha, double beta, int kmode,
-          hipStream_t st) {
-  GemmArgs g = make_args(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
-  hipLaunchKernelGGL((k_gemm64<BT, LOWER>), dim3((unsigned)(M / 64), (unsigned)(N / 64)),
+template <typename T, bool AT, bool BT, bool LOWER>
+void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
+          T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st) {
+  GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
+  hipLaunchKernelGGL((k_gemm64<T, AT, BT, LOWER>), dim3((unsigned)(M / 64), (unsigned)(N / 64)),
                      dim3(256), 0, st, g);
 }
 
-void gemm_pair(const GemmArgs &s, const GemmArgs &t, hipStream_t st) {
+template <typename T>
+void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st) {
   const unsigned a = (unsigned)((s.M / 64) * (s.N / 64)), b = (unsigned)((t.M / 64) * (t.N / 64));
-  hipLaunchKernelGGL(k_gemm64_pair, dim3(a + b), dim3(256), 0, st, s, t, (int)a);
+  hipLaunchKernelGGL((k_gemm64_pair<T>), dim3(a + b), dim3(256), 0, st, s, t, (int)a);
 }
 
-// Scratch needed by recurse() for an n x n block (doubles).
+// Scratch needed by recurse() for an n x n block (elements).
 int64_t recurse_scratch(int64_t n) {
   if (n <= 128) return 0;
   const int64_t tiles = n / 64, n1 = (tiles / 2) * 64, n2 = n - n1;
@@ -712,39 +598,41 @@ int64_t recurse_scratch(int64_t n) {
 // In-place L^-1 of the n x n block at offset o.  tmp[0, n2*n1) holds this
 // level's T2 = L21 L11^-1 across the recursion into A22; the rest is scratch
 // for T = L21 and for the children.
-void recurse(double *A, int64_t lda, int64_t o, int64_t n, double *tmp, DevStatus *ds,
-             hipStream_t st) {
+template <typename T>
+void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hipStream_t st) {
   if (n == 64) {
-    hipLaunchKernelGGL((k_leaf_mfma<64>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<T, 64>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
     return;
   }
   if (n == 128) {
-    hipLaunchKernelGGL((k_leaf_mfma<128>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<T, 128>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
     return;
   }
   const int64_t tiles = n / 64;
   const int64_t n1 = (tiles / 2) * 64, n2 = n - n1;
-  double *T2 = tmp;
-  double *T = tmp + n2 * n1;
-  double *child = T;
+  T *T2 = tmp;
+  T *Tm = tmp + n2 * n1;
+  T *child = Tm;
   recurse(A, lda, o, n1, child, ds, st);
-  double *A11 = A + o + o * lda;
-  double *A21 = A + (o + n1) + o * lda;
-  double *A22 = A + (o + n1) + (o + n1) * lda;
-  gemm<true, false>(n2, n1, n1, A21, lda, A11, lda, T, n2, 1.0, 0.0, kLeN, st);   // L21
-  gemm_pair(make_args(n2, n2, n1, T, n2, T, n2, A22, lda, -1.0, 1.0, kFull),      // Schur
-            make_args(n2, n1, n1, T, n2, A11, lda, T2, n2, 1.0, 0.0, kGeN), st);  // L21 L11^-1
+  T *A11 = A + o + o * lda;
+  T *A21 = A + (o + n1) + o * lda;
+  T *A22 = A + (o + n1) + (o + n1) * lda;
+  const T one = T(1), zero = T(0), mone = T(-1);
+  gemm<T, false, true, false>(n2, n1, n1, A21, lda, A11, lda, Tm, n2, one, zero, kLeN, st);  // L21
+  gemm_pair<T>(make_args<T>(n2, n2, n1, Tm, n2, Tm, n2, A22, lda, mone, one, kFull),  // Schur
+               make_args<T>(n2, n1, n1, Tm, n2, A11, lda, T2, n2, one, zero, kGeN), st);
   recurse(A, lda, o + n1, n2, child, ds, st);
-  gemm<false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, -1.0, 0.0, kLeM, st); // (L^-1)21
+  gemm<T, false, false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, mone, zero, kLeM, st);
 }
+
+inline dim3 grid2(int64_t n) { return dim3((unsigned)((n + 255) / 256), (unsigned)n); }
 
 }  // namespace
 
 void launch_scale_dense(int64_t N, const double *z, int64_t ldz, const double *q,
                         const double *s, const double *alpha, double *a, int64_t lda,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_dense, dim3((unsigned)((N + 255) / 256), (unsigned)N), dim3(256),
-                     0, st, N, z, ldz, q, s, alpha, a, lda);
+  hipLaunchKernelGGL(k_scale_dense, grid2(N), dim3(256), 0, st, N, z, ldz, q, s, alpha, a, lda);
 }
 
 void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStream_t st) {
@@ -756,13 +644,51 @@ int64_t spd_lower_inverse_scratch(int64_t Np) { return recurse_scratch(Np); }
 
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st) {
-  recurse(a, lda, 0, Np, tmp, ds, st);
+  recurse<double>(a, lda, 0, Np, tmp, ds, st);
 }
 
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
                     const double *q, const double *alpha, double *cov, hipStream_t st) {
   hipLaunchKernelGGL(k_extract, dim3((unsigned)(N / 9)), dim3(256), 0, st, N, linv, ld, s, q,
                      alpha, cov);
+}
+
+void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
+                         const double *q, const double *alpha, double *cov, hipStream_t st) {
+  hipLaunchKernelGGL(k_extract_full, dim3((unsigned)(N / 9)), dim3(128), 0, st, N, x, ld, s, q,
+                     alpha, cov);
+}
+
+void mixed_initial_inverse(int64_t Np, const double *a, int64_t lda, float *a32, float *x32,
+                           float *tmp32, DevStatus *ds, hipStream_t st) {
+  // FP32 copy of the lower triangle, its inverse Cholesky factor, then
+  // X0 = L^-T L^-1 (full, both triangles) on FP32 MFMA
+  hipLaunchKernelGGL(k_lower_to_f32, grid2(Np), dim3(256), 0, st, Np, a, lda, a32, Np);
+  recurse<float>(a32, Np, 0, Np, tmp32, ds, st);
+  gemm<float, true, false, false>(Np, Np, Np, a32, Np, a32, Np, x32, Np, 1.0f, 0.0f, kGeMN, st);
+}
+
+void mixed_prepare(int64_t Np, double *a, int64_t lda, const float *x32, double *x,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, grid2(Np), dim3(256), 0, st, Np, a, lda);
+  hipLaunchKernelGGL(k_f32_to_f64, grid2(Np), dim3(256), 0, st, Np, x32, Np, x, Np);
+}
+
+void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, double *r,
+                    double *sumsq, hipStream_t st) {
+  // R = I - A X in FP64, and |R|_F^2 accumulated into sumsq[0]
+  hipLaunchKernelGGL(k_identity, grid2(Np), dim3(256), 0, st, Np, r, Np);
+  gemm<double, false, false, false>(Np, Np, Np, a, lda, x, Np, r, Np, -1.0, 1.0, kFull, st);
+  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)Np), dim3(256), 0, st, Np, r, Np, sumsq);
+}
+
+void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32, float *d32,
+                  hipStream_t st) {
+  // X <- X + X R with the correction X R on FP32 MFMA
+  hipLaunchKernelGGL(k_f64_to_f32, grid2(Np), dim3(256), 0, st, Np, x, Np, x32, Np);
+  hipLaunchKernelGGL(k_f64_to_f32, grid2(Np), dim3(256), 0, st, Np, r, Np, r32, Np);
+  gemm<float, false, false, false>(Np, Np, Np, x32, Np, r32, Np, d32, Np, 1.0f, 0.0f, kFull, st);
+  hipLaunchKernelGGL(k_add_f32, grid2(Np), dim3(256), 0, st, Np, d32, Np, x, Np);
 }
 
 }  // namespace ucov

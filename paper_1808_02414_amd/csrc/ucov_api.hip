@@ -45,6 +45,7 @@ struct ucov_ctx {
   Buf cnt_p, ptr_p, cur_p, slot_obs, slot_cam, slot_pt, rec;
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount;
   Buf zdiag, hc, q, s, alpha, amat, tmat;
+  Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
 
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
@@ -239,7 +240,7 @@ SceneDev scene_dev(const ucov_scene *scene) {
 void fill_defaults(const ucov_options *opt, ucov_options &o) {
   o.precision = UCOV_FP64;
   o.max_iter = 6;
-  o.tol = 1e-12;
+  o.tol = 1e-10;
   o.alpha = 0.0;
   if (opt) {
     o.precision = opt->precision;
@@ -249,20 +250,81 @@ void fill_defaults(const ucov_options *opt, ucov_options &o) {
   }
 }
 
+// Mixed-precision inverse of A_s (Np x Np in c->amat): FP32 MFMA Cholesky
+// inverse X0, then Newton-Schulz steps X <- X + X (I - A X) with the residual
+// in FP64 and the correction on FP32 MFMA, until |I - A X|_F / sqrt(N) <= tol.
+int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double *cov_out,
+              ucov_report *rep) {
+  hipStream_t st = c->stream;
+  const size_t f32 = 4 * (size_t)Np * Np, f64 = 8 * (size_t)Np * Np;
+  UCOV_TRY(ensure(c, c->m_a32, f32));
+  UCOV_TRY(ensure(c, c->m_x32, f32));
+  UCOV_TRY(ensure(c, c->m_r32, f32));
+  UCOV_TRY(ensure(c, c->m_d32, f32));
+  UCOV_TRY(ensure(c, c->m_tmp32, 4 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
+  UCOV_TRY(ensure(c, c->m_x64, f64));
+  UCOV_TRY(ensure(c, c->m_r64, f64));
+  UCOV_TRY(ensure(c, c->m_sum, 8));
+  double *A = as<double>(c->amat);
+  mixed_initial_inverse(Np, A, Np, as<float>(c->m_a32), as<float>(c->m_x32),
+                        as<float>(c->m_tmp32), c->ds, st);
+  UCOV_TRY(check_hip(c, "mixed initial inverse"));
+  {
+    const int rc = sync_status(c, rep, "FP32 factorisation");
+    if (rc == UCOV_EGAUGE)
+      return c->fail(UCOV_ENOCONV, "FP32 Cholesky factorisation failed: the scaled matrix is "
+                                   "too ill-conditioned for the mixed path (use UCOV_FP64)");
+    if (rc != UCOV_OK) return rc;
+  }
+  mixed_prepare(Np, A, Np, as<float>(c->m_x32), as<double>(c->m_x64), st);
+  double res = 0.0;
+  int it = 0;
+  for (;; ++it) {
+    fill_f64(as<double>(c->m_sum), 0.0, 1, st);
+    mixed_residual(Np, A, Np, as<double>(c->m_x64), as<double>(c->m_r64), as<double>(c->m_sum),
+                   st);
+    double h = 0.0;
+    if (hipMemcpyAsync(&h, c->m_sum.p, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return c->fail(UCOV_EDEVICE, "residual readback");
+    res = std::sqrt(h / (double)N);
+    if (res <= o.tol || it >= o.max_iter) break;
+    mixed_update(Np, as<double>(c->m_x64), as<double>(c->m_r64), as<float>(c->m_x32),
+                 as<float>(c->m_r32), as<float>(c->m_d32), st);
+  }
+  if (rep) {
+    rep->ns_iters = it;
+    rep->ns_residual = res;
+  }
+  if (!(res <= o.tol)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "Newton-Schulz residual %.3e above tol %.3e after %d steps", res,
+             o.tol, it);
+    return c->fail(UCOV_ENOCONV, buf);
+  }
+  hipEventRecord(c->ev[4], st);
+  launch_extract_full(N, as<double>(c->m_x64), Np, as<double>(c->s), as<double>(c->q),
+                      as<double>(c->alpha), cov_out, st);
+  return UCOV_OK;
+}
+
 // Dense stage on the already assembled lower triangle of A_s in c->amat.
 int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_out,
                     ucov_report *rep) {
   const int64_t Np = round_up(N, kTile);
-  UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
   hipStream_t st = c->stream;
   double *A = as<double>(c->amat);
   launch_pad_identity(N, Np, A, Np, st);
   hipEventRecord(c->ev[3], st);
-  if (o.precision != UCOV_FP64) return c->fail(UCOV_EINVAL, "unsupported precision");
-  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
-  hipEventRecord(c->ev[4], st);
-  launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), as<double>(c->alpha), cov_out,
-                 st);
+  if (o.precision == UCOV_FP64) {
+    UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
+    spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
+    hipEventRecord(c->ev[4], st);
+    launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), as<double>(c->alpha), cov_out,
+                   st);
+  } else {
+    UCOV_TRY(run_mixed(c, N, Np, o, cov_out, rep));
+  }
   hipEventRecord(c->ev[5], st);
   UCOV_TRY(check_hip(c, "dense kernels"));
   UCOV_TRY(sync_status(c, rep, "dense inverse"));
@@ -316,7 +378,9 @@ void ucov_destroy(ucov_ctx *c) {
   else hipDeviceSynchronize();
   Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_obs, &c->slot_cam, &c->slot_pt,
                  &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount,
-                 &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat};
+                 &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
+                 &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
+                 &c->m_sum};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   if (c->ds) hipFree(c->ds);
@@ -406,6 +470,8 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
     return c->fail(UCOV_EINVAL, "bad dense arguments");
   ucov_options o;
   fill_defaults(opt, o);
+  if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
+    return c->fail(UCOV_EINVAL, "unknown precision");
   hipSetDevice(c->device);
   if (rep) memset(rep, 0, sizeof *rep);
   const int64_t N = n, Np = round_up(N, kTile);

@@ -103,5 +103,22 @@ void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, Dev
 // cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
                     const double *q, const double *alpha, double *cov, hipStream_t st);
+// cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X
+void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
+                         const double *q, const double *alpha, double *cov, hipStream_t st);
+
+// Mixed precision (all matrices Np x Np, leading dimension Np):
+// X0 = L^-T L^-1 of the FP32 Cholesky factor of the lower triangle of a;
+void mixed_initial_inverse(int64_t Np, const double *a, int64_t lda, float *a32, float *x32,
+                           float *tmp32, DevStatus *ds, hipStream_t st);
+// a made symmetric from its lower triangle, x = (double) x32;
+void mixed_prepare(int64_t Np, double *a, int64_t lda, const float *x32, double *x,
+                   hipStream_t st);
+// r = I - a x (FP64), sumsq[0] += |r|_F^2;
+void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, double *r,
+                    double *sumsq, hipStream_t st);
+// x += x r with the correction on FP32 MFMA.
+void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32, float *d32,
+                  hipStream_t st);
 
 }  // namespace ucov

@@ -183,3 +183,43 @@ def test_errors(ucov):
     got, _ = ctx.camera_covariance(dev(u, s))
     ref = oracle_cov(s)["blocks"]
     assert block_errors(got.cpu().numpy(), ref)[0] < 1e-6
+
+
+@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(5), lambda: sg.spiral_slab(13, n=150, m=15000)])
+def test_covariance_mixed_precision(ucov, maker):
+    """FP32 MFMA initial inverse + Newton-Schulz with FP64 residuals."""
+    u, ctx = ucov
+    s = maker()
+    print(f"mixed {s.name} n={s.n_cams}", flush=True)
+    got, rep = ctx.camera_covariance(dev(u, s), precision=u.FP32_NS)
+    ref = oracle_cov(s)["blocks"]
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    print(f"  ns_iters {rep['ns_iters']} residual {rep['ns_residual']:.2e} fro {fro:.2e} scaled {scaled:.2e}")
+    assert rep["ns_iters"] >= 1 and rep["ns_residual"] <= 1e-10
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+@pytest.mark.parametrize("N,kappa", [(576, 1e3), (1161, 1e5)])
+def test_pinv_known_spectrum_mixed(ucov, N, kappa):
+    import torch
+    u, ctx = ucov
+    rng = np.random.default_rng(N + 1)
+    B, _ = np.linalg.qr(rng.normal(size=(N, N)))
+    lam = np.geomspace(1.0, 1.0 / kappa, N - 7)
+    R, Q0 = B[:, :N - 7], B[:, N - 7:]
+    Z = (R * lam) @ R.T
+    Z = 0.5 * (Z + Z.T)
+    ref = covariance.camera_blocks((R / lam) @ R.T)
+    got, rep = ctx.pinv_blocks(torch.from_numpy(Z).cuda(), torch.from_numpy(Q0.copy()).cuda(),
+                               precision=u.FP32_NS)
+    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    assert fro < 1e-15 * kappa * 1000, (fro, rep)
+
+
+def test_mixed_precision_reports_no_convergence(ucov):
+    """max_iter = 1 with a tolerance the first step cannot reach: ENOCONV."""
+    u, ctx = ucov
+    s = sg.spiral_slab(14, n=60, m=4000)
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, s), precision=u.FP32_NS, max_iter=1, tol=1e-30)
+    assert e.value.kind == "ENOCONV"
