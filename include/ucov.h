@@ -6,8 +6,8 @@
  * diagonal block of Z^+, the Moore-Penrose inverse of the reduced camera
  * matrix Z = U - W V^-1 W^T (Polic, Forstner, Pajdla, "Fast and Accurate
  * Camera Covariance Computation for Large 3D Reconstruction", ECCV 2018:
- * Sec. 3 for the normal equations and the gauge, Sec. 4.1 for the similarity
- * nullspace, Sec. 4.2 for the block inversion and the Schur complement).
+ * Sec. 4 for the normal equations and the gauge, Sec. 5.1 for the similarity
+ * nullspace, Sec. 5.2 for the block inversion and the Schur complement).
  * Z^+ is evaluated as (Z + a Q Q^T)^-1 - Q Q^T / a with Q an orthonormal basis
  * of the camera rows H_c of the nullspace and a > 0.
  *
@@ -38,7 +38,7 @@
  *   obs_info[3*o+0..2] (a, b, c) of the 2x2 information Sigma_u^-1 =
  *                      [[a, b], [b, c]]; NULL means identity
  * The projection is u = f d(rho2) pi + (cx, cy) with pi = x[0:2] / x[2],
- * x = R(r)(X - C), rho2 = |pi|^2 and d = 1 + k1 rho2 + k2 rho2^2 (Sec. 4.1,
+ * x = R(r)(X - C), rho2 = |pi|^2 and d = 1 + k1 rho2 + k2 rho2^2 (Sec. 5.1,
  * focal length applied after the division); the principal point is a
  * constant and does not enter the covariance.
  *
@@ -127,20 +127,20 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
                            const ucov_options *opt, double *cov_out,
                            ucov_report *rep);
 
-/* Step a1 alone: per-observation Jacobian blocks of the projection (Sec. 4.1),
+/* Step a1 alone: per-observation Jacobian blocks of the projection (Sec. 5.1),
  * in the caller's observation order, unweighted by obs_info.
  * jp: n_obs x 18 (2x9 row-major per observation, columns r, C, f, k1, k2);
  * jx: n_obs x 6 (2x3 row-major per observation). */
 int ucov_jacobians(ucov_ctx *ctx, const ucov_scene *scene, double *jp, double *jx);
 
-/* Steps a1-a2: the reduced camera matrix Z = U - W V^-1 W^T (Sec. 4.2,
+/* Steps a1-a2: the reduced camera matrix Z = U - W V^-1 W^T (Sec. 5.2,
  * Schur complement of the point block), written densely (both triangles)
  * into z, an N x N column-major matrix with leading dimension ldz >= N,
  * N = 9 n_cams. */
 int ucov_reduced_camera_matrix(ucov_ctx *ctx, const ucov_scene *scene,
                                double *z, int64_t ldz, ucov_report *rep);
 
-/* Step a3: the camera rows H_c of the similarity nullspace (Sec. 4.1,
+/* Step a3: the camera rows H_c of the similarity nullspace (Sec. 5.1,
  * column order translation, rotation, scale; rotation block from
  * J_r H_r = B) and an orthonormal basis Q of their span.
  * hc, q: N x 7 column-major with leading dimension N (either may be NULL). */

@@ -14,14 +14,14 @@ blocked MFMA kernels).
 Modules, in the order of the paper's method:
 
 * ``dual``       forward-mode dual numbers (derivative machinery)
-* ``camera``     projection function and its Jacobian blocks (Sec. 4.1)
+* ``camera``     projection function and its Jacobian blocks (Sec. 5.1)
 * ``schur``      normal-equation blocks U, V, W and Z = U - W V^-1 W^T
-                 (Sec. 3 normal equations; Sec. 4.2 block inversion and Schur
+                 (Sec. 4 normal equations; Sec. 5.2 block inversion and Schur
                  complement)
 * ``nullspace``  similarity nullspace H with the rotation block solved from
-                 J_r H_r = B (Sec. 4.1)
+                 J_r H_r = B (Sec. 5.1)
 * ``covariance`` Moore-Penrose camera covariance Z^+ = (Z + a Q Q^T)^-1 - Q Q^T / a
-                 with Jacobi conditioning (Sec. 3 gauge, Sec. 4.2 conditioning)
+                 with Jacobi conditioning (Sec. 4 gauge, Sec. 5.2 conditioning)
 * ``pipeline``   end to end, plus the input checks shared by the error tests
 
 Parity status: every function is pinned by a CPU test against something other

@@ -1,4 +1,4 @@
-"""Projection function and its Jacobian blocks (oracle; paper Sec. 4.1).
+"""Projection function and its Jacobian blocks (oracle; paper Sec. 5.1).
 
 The paper's projection is p(X_j, P_i) = Phi_i(c_i R(r_i)(X_j - C_i)), with
 Phi_i dividing by the third coordinate and then applying radial distortion.
@@ -69,7 +69,7 @@ def jacobians(cams: np.ndarray, pts: np.ndarray, obs_cam: np.ndarray, obs_pt: np
     coordinates with respect to the observing camera's parameters in the
     order (r, C, f, k1, k2), and J_X of shape (t, 2, 3), the derivative with
     respect to the observed point (the nonzero blocks of the sparse J of
-    Sec. 4.1).
+    Sec. 5.1).
     """
     k = 12
     c = cams[obs_cam]

@@ -1,6 +1,6 @@
 """Moore-Penrose camera covariance (oracle).
 
-Sec. 3: the information matrix is rank deficient by the seven similarity
+Sec. 4: the information matrix is rank deficient by the seven similarity
 degrees of freedom, and the natural (inner) covariance is its Moore-Penrose
 inverse, obtained through constraints H^T dtheta = 0 with H the nullspace.
 Restricted to the cameras, the reduced camera matrix Z is symmetric positive
@@ -11,7 +11,7 @@ range(H_c) and any a > 0, Z + a Q Q^T is positive definite and
 
 because Z + a Q Q^T acts as Z on range(Z) and as a on range(Q).
 
-Sec. 4.2 conditions the matrix to be inverted with diagonal scalings before
+Sec. 5.2 conditions the matrix to be inverted with diagonal scalings before
 inverting; here that is the Jacobi scaling S = diag(A)^-1/2 of the positive
 definite A = Z + a Q Q^T, with A^-1 = S (S A S)^-1 S exactly.
 

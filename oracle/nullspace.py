@@ -1,4 +1,4 @@
-"""Similarity nullspace H of the Jacobian (oracle; paper Sec. 4.1).
+"""Similarity nullspace H of the Jacobian (oracle; paper Sec. 5.1).
 
 A similarity q = [T, s, mu] (translation, rotation, scale) leaves every
 projection unchanged, so H = d(theta)/dq spans the null space of J.  Its

@@ -1,16 +1,16 @@
 """End-to-end oracle: reconstruction in, per-camera 9x9 covariance blocks out.
 
-Steps, in the paper's order (Sec. 3 problem formulation, Sec. 4 solution):
+Steps, in the paper's order (Sec. 4 problem formulation, Sec. 5 solution):
 
 1. check the inputs (the same rules the library enforces, listed in
    ``validate``);
-2. Jacobian blocks J_P, J_X of every observation (Sec. 4.1, projection);
-3. normal-equation blocks U, V, W (Sec. 3) and the point-block inverses;
-4. Z = U - W V^-1 W^T (Sec. 4.2, Schur complement of the point block);
+2. Jacobian blocks J_P, J_X of every observation (Sec. 5.1, projection);
+3. normal-equation blocks U, V, W (Sec. 4) and the point-block inverses;
+4. Z = U - W V^-1 W^T (Sec. 5.2, Schur complement of the point block);
 5. nullspace camera rows H_c with the rotation block from J_r H_r = B
-   (Sec. 4.1) and an orthonormal basis Q of range(H_c);
-6. Z^+ = (Z + a Q Q^T)^-1 - Q Q^T / a with Jacobi conditioning (Sec. 3 gauge,
-   Sec. 4.2 conditioning), keeping the diagonal 9x9 blocks.
+   (Sec. 5.1) and an orthonormal basis Q of range(H_c);
+6. Z^+ = (Z + a Q Q^T)^-1 - Q Q^T / a with Jacobi conditioning (Sec. 4 gauge,
+   Sec. 5.2 conditioning), keeping the diagonal 9x9 blocks.
 """
 from __future__ import annotations
 

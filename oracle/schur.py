@@ -1,10 +1,10 @@
 """Normal-equation blocks and the reduced camera matrix (oracle).
 
-Sec. 3 defines the normal equations M = J^T Sigma_u^-1 J with a block-diagonal
-Sigma_u of 2x2 blocks.  Ordering cameras before points (Sec. 4.1), M splits
+Sec. 4 defines the normal equations M = J^T Sigma_u^-1 J with a block-diagonal
+Sigma_u of 2x2 blocks.  Ordering cameras before points (Sec. 5.1), M splits
 into a camera block U (block diagonal, one 9x9 block per camera), a point
-block V (block diagonal, one 3x3 block per point, the A_p of Sec. 4.2) and the
-coupling W.  Sec. 4.2 eliminates the points with a block inversion, which
+block V (block diagonal, one 3x3 block per point, the A_p of Sec. 5.2) and the
+coupling W.  Sec. 5.2 eliminates the points with a block inversion, which
 leaves the Schur complement of the point block,
 
     Z = U - W V^-1 W^T,
@@ -79,7 +79,7 @@ def point_block_inverses(V):
 
 
 def reduced_camera_matrix(U, W, Vinv, obs_cam, obs_pt, n: int, m: int) -> np.ndarray:
-    """Dense Z = U - W V^-1 W^T using sparse products (Sec. 4.2)."""
+    """Dense Z = U - W V^-1 W^T using sparse products (Sec. 5.2)."""
     t = obs_cam.size
     ar9 = np.arange(9)
     ar3 = np.arange(3)

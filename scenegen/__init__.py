@@ -1,7 +1,7 @@
 """Seeded synthetic reconstructions (inputs only).
 
 This module produces the *inputs* of the camera-covariance computation:
-cameras, points and the observation index set S (paper, Sec. 3, "Problem
+cameras, points and the observation index set S (paper, Sec. 4, "Problem
 formulation").  It holds none of the method's arithmetic: no projection, no
 Jacobian, no normal equations.  Camera orientations are built as look-at
 frames and converted to angle-axis with SciPy; visibility uses only camera
@@ -12,7 +12,7 @@ Python binding) consume the same ``Scene`` objects, so neither side generates
 its own inputs.
 
 Camera parameter layout, one row of 9 float64 per camera, in the order the
-paper uses for P_i = {r_i, C_i, c_i, k_i} (Sec. 4.1) extended to two radial
+paper uses for P_i = {r_i, C_i, c_i, k_i} (Sec. 5.1) extended to two radial
 coefficients:
 
     r0 r1 r2   angle-axis of the world-to-camera rotation R(r)
@@ -41,7 +41,7 @@ Recipes (all distributions are seeded with numpy's PCG64 ``default_rng``):
   log-uniform in [20, 400], 100 points per camera and mean track length 5.
 
 The observed image coordinates (and their 1 px noise) are not generated: a
-first-order covariance does not depend on the residuals (Sec. 3, the normal
+first-order covariance does not depend on the residuals (Sec. 4, the normal
 equations), so the library never reads them.
 """
 from __future__ import annotations
