@@ -107,6 +107,7 @@ typedef struct {
   float ms_gauge;      /* nullspace, orthonormalisation, scaling (step a3) */
   float ms_inverse;    /* dense factorisation and inversion (step a4) */
   float ms_extract;    /* covariance block extraction (step a4) */
+  int32_t bad_scene;   /* batched calls: scene of the failure, -1 if none */
 } ucov_report;
 
 /* Create a context on HIP device `device`.  Returns UCOV_EDEVICE if the
@@ -126,6 +127,26 @@ void ucov_destroy(ucov_ctx *ctx);
 int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
                            const ucov_options *opt, double *cov_out,
                            ucov_report *rep);
+
+/* Covariance blocks of several independent scenes in one call: the
+ * sub-reconstructions of Sec. 6, each evaluated exactly on its own gauge (a
+ * camera's covariance from a sub-reconstruction around it bounds the one from
+ * the whole reconstruction from above).
+ * scenes: HOST array of n_scenes descriptors (n_scenes >= 1); the arrays each
+ * descriptor points to are device arrays whose indices are local to that
+ * scene.  The input rules of ucov_camera_covariance hold per scene.
+ * cov_out: (sum of n_cams) x 81 float64; the blocks of scene s follow those of
+ * scene s - 1, each as in ucov_camera_covariance.
+ * alphas: HOST array receiving the gauge weight of every scene, or NULL.
+ * opt->precision must be UCOV_FP64 (else UCOV_EINVAL).
+ * rep: ms_inverse covers the dense stage of all scenes (factorisation,
+ * inversion and block extraction overlap across scenes), ms_extract is 0,
+ * alpha is scene 0's; on failure bad_scene names the scene and bad_index the
+ * observation, point or camera within it.
+ * Limits: at most 2^27 cameras and 2^31 - 1 points and observations in total. */
+int ucov_camera_covariance_batched(ucov_ctx *ctx, int32_t n_scenes, const ucov_scene *scenes,
+                                   const ucov_options *opt, double *cov_out, double *alphas,
+                                   ucov_report *rep);
 
 /* Step a1 alone: per-observation Jacobian blocks of the projection (Sec. 5.1),
  * in the caller's observation order, unweighted by obs_info.

@@ -38,13 +38,14 @@ class Report(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64),
                 ("ms_structure", ctypes.c_float), ("ms_schur", ctypes.c_float),
                 ("ms_gauge", ctypes.c_float), ("ms_inverse", ctypes.c_float),
-                ("ms_extract", ctypes.c_float)]
+                ("ms_extract", ctypes.c_float), ("bad_scene", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covariance",
+           "ucov_camera_covariance_batched",
            "ucov_jacobians", "ucov_reduced_camera_matrix", "ucov_gauge_basis",
            "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error"]
 
@@ -67,6 +68,9 @@ def load(path: str = LIB_PATH):
         "ucov_destroy": (None, [P]),
         "ucov_camera_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), ctypes.POINTER(Options),
                                                   P, ctypes.POINTER(Report)]),
+        "ucov_camera_covariance_batched": (ctypes.c_int, [P, I32, ctypes.POINTER(Scene),
+                                                          ctypes.POINTER(Options), P,
+                                                          ctypes.POINTER(D), ctypes.POINTER(Report)]),
         "ucov_jacobians": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
         "ucov_reduced_camera_matrix": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, I64,
                                                       ctypes.POINTER(Report)]),
@@ -86,11 +90,12 @@ def load(path: str = LIB_PATH):
 
 
 class UcovError(RuntimeError):
-    def __init__(self, code: int, message: str, index: int = -1):
+    def __init__(self, code: int, message: str, index: int = -1, scene: int = -1):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {message}")
         self.code = code
         self.kind = ERROR_NAMES.get(code, str(code))
         self.index = index
+        self.scene = scene
 
 
 def _torch():
@@ -161,7 +166,8 @@ class Context:
     def _check(self, rc, rep=None):
         if rc != OK:
             msg = self.lib.ucov_last_error(self.h).decode()
-            raise UcovError(rc, msg, rep.bad_index if rep is not None else -1)
+            raise UcovError(rc, msg, rep.bad_index if rep is not None else -1,
+                            rep.bad_scene if rep is not None else -1)
 
     def camera_covariance(self, scene: DeviceScene, precision=FP64, alpha=0.0, tol=0.0,
                           max_iter=0, out=None):
@@ -178,6 +184,29 @@ class Context:
                                              out.data_ptr(), ctypes.byref(rep))
         self._check(rc, rep)
         return out, rep.as_dict()
+
+    def camera_covariance_batched(self, scenes, alpha=0.0, out=None):
+        """Covariance blocks of independent scenes in one call: a list of
+        (n_s, 9, 9) views into one (sum n_s, 9, 9) device tensor, the per-scene
+        gauge weights and the report."""
+        torch = self.torch
+        sizes = [s.n_cams for s in scenes]
+        total = sum(sizes)
+        if out is None:
+            out = torch.empty((total, 9, 9), dtype=torch.float64, device=scenes[0].cams.device)
+        arr = (Scene * len(scenes))(*[s.struct() for s in scenes])
+        alphas = (ctypes.c_double * len(scenes))()
+        opt = Options(FP64, 0, 0.0, alpha)
+        rep = Report()
+        self._stream()
+        rc = self.lib.ucov_camera_covariance_batched(self.h, len(scenes), arr, ctypes.byref(opt),
+                                                     out.data_ptr(), alphas, ctypes.byref(rep))
+        self._check(rc, rep)
+        views, o = [], 0
+        for n in sizes:
+            views.append(out[o:o + n])
+            o += n
+        return views, list(alphas), rep.as_dict()
 
     def jacobians(self, scene: DeviceScene):
         torch = self.torch

@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *a, int64
 // One workgroup per camera: (A_s^-1)_ii = sum over rows r >= 9i of the outer
 // products of row r of L^-1 restricted to the camera's 9 columns.
 __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, int64_t ld,
-                                                const double *s, const double *q,
+                                                const double *s, const double *q, int64_t ldq,
                                                 const double *alpha, double *cov) {
   const int64_t i = blockIdx.x;
   const int64_t c0 = 9 * i;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, 
     const double x = part[0][idx] + part[1][idx] + part[2][idx] + part[3][idx];
     double g = 0.0;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) g += q[k * N + c0 + a0] * q[k * N + c0 + b0];
+    for (int k = 0; k < 7; ++k) g += q[k * ldq + c0 + a0] * q[k * ldq + c0 + b0];
     cov[81 * i + threadIdx.x] = s[c0 + a0] * x * s[c0 + b0] - g / (*alpha);
   }
 }
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, 
 // cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X (81 threads
 // per camera)
 __global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                               const double *q, const double *alpha, double *cov) {
+                               const double *q, int64_t ldq, const double *alpha, double *cov) {
   const int64_t i = blockIdx.x;
   const int t = threadIdx.x;
   if (t >= 81) return;
@@ -558,7 +558,7 @@ __global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const dou
   const double xs = 0.5 * (x[r + c * ld] + x[c + r * ld]);
   double g = 0.0;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) g += q[k * N + r] * q[k * N + c];
+  for (int k = 0; k < 7; ++k) g += q[k * ldq + r] * q[k * ldq + c];
   cov[81 * i + t] = s[r] * xs * s[c] - g / (*alpha);
 }
 
@@ -648,15 +648,17 @@ void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, Dev
 }
 
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
-                    const double *q, const double *alpha, double *cov, hipStream_t st) {
+                    const double *q, int64_t ldq, const double *alpha, double *cov,
+                    hipStream_t st) {
   hipLaunchKernelGGL(k_extract, dim3((unsigned)(N / 9)), dim3(256), 0, st, N, linv, ld, s, q,
-                     alpha, cov);
+                     ldq, alpha, cov);
 }
 
 void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                         const double *q, const double *alpha, double *cov, hipStream_t st) {
+                         const double *q, int64_t ldq, const double *alpha, double *cov,
+                         hipStream_t st) {
   hipLaunchKernelGGL(k_extract_full, dim3((unsigned)(N / 9)), dim3(128), 0, st, N, x, ld, s, q,
-                     alpha, cov);
+                     ldq, alpha, cov);
 }
 
 void mixed_initial_inverse(int64_t Np, const double *a, int64_t lda, float *a32, float *x32,

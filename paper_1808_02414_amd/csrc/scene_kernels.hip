@@ -1,12 +1,14 @@
 // Scene stage of the camera covariance (steps a1-a3):
 //   * observations grouped by point (counting sort on device),
-//   * per-observation projection Jacobians (paper Sec. 4.1, projection),
-//   * per-point 3x3 blocks V_j and their FP64 inverses (Sec. 4.2, A_p),
+//   * per-observation projection Jacobians (paper Sec. 5.1, projection),
+//   * per-point 3x3 blocks V_j and their FP64 inverses (Sec. 5.2, A_p),
 //   * camera-pair binning of the Schur-complement terms and their reduction
-//     into Z = U - W V^-1 W^T (Sec. 4.2, Schur complement),
+//     into Z = U - W V^-1 W^T (Sec. 5.2, Schur complement),
 //   * the camera rows of the similarity nullspace with the rotation block
-//     from J_r H_r = B (Sec. 4.1) and its Cholesky-QR2 orthonormalisation,
-//   * Jacobi scaling of Z + a QQ^T (Sec. 4.2, conditioning).
+//     from J_r H_r = B (Sec. 5.1) and its Cholesky-QR2 orthonormalisation,
+//   * Jacobi scaling of Z + a QQ^T (Sec. 5.2, conditioning).
+#include <algorithm>
+
 #include "ucov_internal.h"
 #include "../../include/ucov.h"
 
@@ -21,6 +23,14 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 __device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
+
+// Lower-triangular camera-pair bin of cameras ci >= ck (of one scene).
+__device__ inline int64_t bin_of(const SceneDev &sc, int ci, int ck) {
+  if (!sc.cam_scene) return tri(ci) + ck;
+  const int s = sc.cam_scene[ci];
+  const int c0 = sc.cam_off[s];
+  return sc.bin_off[s] + tri(ci - c0) + (ck - c0);
+}
 
 // ---------------------------------------------------------------------------
 // fills and an exclusive scan of int32 counts into int64 offsets
@@ -414,10 +424,9 @@ __global__ void k_pair_count(SceneDev sc, const int64_t *ptr_p, const int32_t *s
   if (a >= ptr_p[sc.m]) return;
   const int64_t p0 = ptr_p[slot_pt[a]];
   const int ci = slot_cam[a];
-  const int64_t base = tri(ci);
   for (int64_t b = p0; b <= a; ++b) {
     const int ck = slot_cam[b];
-    if (atomicAdd(&bin_cnt[base + ck], 1) == 0) {
+    if (atomicAdd(&bin_cnt[bin_of(sc, ci, ck)], 1) == 0) {
       const unsigned long long pos = atomicAdd(nzcount, 1ull);
       nzlist[pos] = make_int2(ci, ck);
     }
@@ -430,9 +439,9 @@ __global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *sl
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= ptr_p[sc.m]) return;
   const int64_t p0 = ptr_p[slot_pt[a]];
-  const int64_t base = tri(slot_cam[a]);
+  const int ci = slot_cam[a];
   for (int64_t b = p0; b <= a; ++b) {
-    const int64_t bin = base + slot_cam[b];
+    const int64_t bin = bin_of(sc, ci, slot_cam[b]);
     const int64_t pos = bin_ptr[bin] + atomicAdd(&bin_cur[bin], 1);
     pairs[pos] = make_int2((int)a, (int)b);
   }
@@ -459,7 +468,7 @@ __global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t 
                                                     const int32_t *slot_pt, double *zdiag,
                                                     double *hc, DevStatus *ds) {
   const int i = blockIdx.x;
-  const int64_t bin = tri(i) + i;
+  const int64_t bin = bin_of(sc, i, i);
   const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
   double acc[kDiagVals];
 #pragma unroll
@@ -620,7 +629,7 @@ __device__ inline double block_sum(double v, double *red) {
 // Gram matrix G = A^T A of an N x 7 column-major matrix, then R = chol(G)
 // (G = R^T R) and A <- A R^-1, written into out.  Returns false if G is not
 // positive definite.
-__device__ bool cholqr_pass(int64_t N, const double *A, double *out, double *red,
+__device__ __forceinline__ bool cholqr_pass(int64_t N, int64_t ld, const double *A, double *out, double *red,
                             double *Gs, double *Ri) {
   double g[28];
 #pragma unroll
@@ -628,7 +637,7 @@ __device__ bool cholqr_pass(int64_t N, const double *A, double *out, double *red
   for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
     double row[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) row[c] = A[c * N + p];
+    for (int c = 0; c < 7; ++c) row[c] = A[c * ld + p];
     int idx = 0;
 #pragma unroll
     for (int a = 0; a < 7; ++a)
@@ -701,50 +710,53 @@ __device__ bool cholqr_pass(int64_t N, const double *A, double *out, double *red
   for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
     double row[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) row[c] = A[c * N + p];
+    for (int c = 0; c < 7; ++c) row[c] = A[c * ld + p];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       double v = 0.0;
 #pragma unroll
       for (int k = 0; k < 7; ++k) v += row[k] * Ri[k * 7 + c];
-      out[c * N + p] = v;
+      out[c * ld + p] = v;
     }
   }
   __syncthreads();
   return true;
 }
 
-__global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double *hc,
-                                                        double *q, const double *zdiag,
-                                                        const double *zdense, int64_t ldz,
-                                                        double user_alpha, double *s,
-                                                        double *alpha_out, DevStatus *ds) {
-  __shared__ double red[kGaugeThreads / 64];
-  __shared__ double Gs[28];
-  __shared__ double Ri[49];
+// One workgroup per scene.  Scene s owns the rows [row0, row0 + N) of the
+// N_total x 7 matrices hc and q (leading dimension ld); diag(Z) of its rows
+// comes from the per-camera blocks zdiag (camera = row / 9) or, when that is
+// null, from the dense zdense (single scene).
+__device__ void gauge_scene(int64_t row0, int64_t N, int64_t ld, const double *hc, double *q,
+                            const double *zdiag, const double *zdense, int64_t ldz,
+                            double user_alpha, double *s, double *alpha_out, DevStatus *ds,
+                            double *red, double *Gs, double *Ri) {
   if (hc) {
-    if (!cholqr_pass(N, hc, q, red, Gs, Ri) || !cholqr_pass(N, q, q, red, Gs, Ri)) {
-      if (threadIdx.x == 0) report_error(ds, UCOV_EGAUGE, -1);
+    if (!cholqr_pass(N, ld, hc + row0, q + row0, red, Gs, Ri) ||
+        !cholqr_pass(N, ld, q + row0, q + row0, red, Gs, Ri)) {
+      if (threadIdx.x == 0) report_error(ds, UCOV_EGAUGE, (int)(row0 / 9));
       return;
     }
   }
   // a = 7 / sum_p sum_k Q_pk^2 / Z_pp unless given
   double part = 0.0;
-  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
-    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[p * ldz + p];
+  for (int64_t pl = threadIdx.x; pl < N; pl += kGaugeThreads) {
+    const int64_t p = row0 + pl;
+    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[pl * ldz + pl];
     double qq = 0.0;
 #pragma unroll
-    for (int c = 0; c < 7; ++c) qq += q[c * N + p] * q[c * N + p];
+    for (int c = 0; c < 7; ++c) qq += q[c * ld + p] * q[c * ld + p];
     part += qq / zpp;
   }
   const double tot = block_sum(part, red);
   const double a = user_alpha > 0.0 ? user_alpha : 7.0 / tot;
   if (threadIdx.x == 0) *alpha_out = a;
-  for (int64_t p = threadIdx.x; p < N; p += kGaugeThreads) {
-    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[p * ldz + p];
+  for (int64_t pl = threadIdx.x; pl < N; pl += kGaugeThreads) {
+    const int64_t p = row0 + pl;
+    const double zpp = zdiag ? zdiag[81 * (p / 9) + 10 * (p % 9)] : zdense[pl * ldz + pl];
     double qq = 0.0;
 #pragma unroll
-    for (int c = 0; c < 7; ++c) qq += q[c * N + p] * q[c * N + p];
+    for (int c = 0; c < 7; ++c) qq += q[c * ld + p] * q[c * ld + p];
     const double dA = zpp + a * qq;
     if (!(dA > 0.0) || !isfinite(dA)) {
       report_error(ds, UCOV_EGAUGE, (int)(p / 9));
@@ -755,6 +767,31 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double
   }
 }
 
+__global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double *hc,
+                                                        double *q, const double *zdiag,
+                                                        const double *zdense, int64_t ldz,
+                                                        double user_alpha, double *s,
+                                                        double *alpha_out, DevStatus *ds) {
+  __shared__ double red[kGaugeThreads / 64];
+  __shared__ double Gs[28];
+  __shared__ double Ri[49];
+  gauge_scene(0, N, N, hc, q, zdiag, zdense, ldz, user_alpha, s, alpha_out, ds, red, Gs, Ri);
+}
+
+__global__ __launch_bounds__(kGaugeThreads) void k_gauge_scenes(SceneDev sc, const double *hc,
+                                                               double *q, const double *zdiag,
+                                                               double user_alpha, double *s,
+                                                               double *alpha, DevStatus *ds) {
+  __shared__ double red[kGaugeThreads / 64];
+  __shared__ double Gs[28];
+  __shared__ double Ri[49];
+  const int si = blockIdx.x;
+  const int64_t row0 = 9 * (int64_t)sc.cam_off[si];
+  const int64_t N = 9 * (int64_t)(sc.cam_off[si + 1] - sc.cam_off[si]);
+  gauge_scene(row0, N, 9 * (int64_t)sc.n, hc, q, zdiag, nullptr, 0, user_alpha, s, alpha + si,
+              ds, red, Gs, Ri);
+}
+
 // ---------------------------------------------------------------------------
 // assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1)
 //
@@ -763,23 +800,71 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge(int64_t N, const double
 // walked with coalesced stores.  k_bin_blocks takes one wave per non-empty
 // bin (i, k) and writes that whole 9x9 block.
 // ---------------------------------------------------------------------------
-__global__ void k_fill_empty(int64_t N, const int32_t *bin_cnt, const double *q,
-                             const double *s, const double *alpha, int mode, double *out,
-                             int64_t ld) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (r >= N || r < c) return;
-  const int64_t i = r / 9, k = c / 9;
-  if (bin_cnt[tri(i) + k] != 0) return;
-  if (mode == 0) {
-    out[r + c * ld] = 0.0;
-    out[c + r * ld] = 0.0;
-    return;
+// One workgroup per global column gc; its threads walk the rows r >= c of the
+// column's scene (coalesced).  The scene gives the matrix (offset a_off[s],
+// leading dimension a_ld[s]) and the row range.
+__global__ __launch_bounds__(256) void k_fill_empty(SceneDev sc, const int32_t *bin_cnt,
+                                                   const double *q, const double *s,
+                                                   const double *alpha, int mode, double *out,
+                                                   int64_t ld) {
+  const int64_t N = 9 * (int64_t)sc.n;  // rows of q (all scenes)
+  const int64_t gc = blockIdx.x;
+  int si = 0;
+  int64_t row0 = 0, Ns = N, off = 0, lds = ld;
+  if (sc.cam_scene) {
+    si = sc.cam_scene[gc / 9];
+    row0 = 9 * (int64_t)sc.cam_off[si];
+    Ns = 9 * (int64_t)(sc.cam_off[si + 1] - sc.cam_off[si]);
+    off = sc.a_off[si];
+    lds = sc.a_ld[si];
   }
-  double g = 0.0;
+  const int64_t c = gc - row0;
+  const int kc = (int)(gc / 9);
+  double qc[7];
 #pragma unroll
-  for (int h = 0; h < 7; ++h) g += q[h * N + r] * q[h * N + c];
-  out[r + c * ld] = s[r] * ((*alpha) * g) * s[c];
+  for (int h = 0; h < 7; ++h) qc[h] = mode ? q[h * N + gc] : 0.0;
+  const double a = mode ? alpha[si] : 0.0;
+  const double sc_c = mode ? s[gc] : 0.0;
+  double *o = out + off;
+  for (int64_t r = c + threadIdx.x; r < Ns; r += blockDim.x) {
+    const int64_t gr = row0 + r;
+    if (bin_cnt[bin_of(sc, (int)(gr / 9), kc)] != 0) continue;
+    if (mode == 0) {
+      o[r + c * lds] = 0.0;
+      o[c + r * lds] = 0.0;
+      continue;
+    }
+    double g = 0.0;
+#pragma unroll
+    for (int h = 0; h < 7; ++h) g += q[h * N + gr] * qc[h];
+    o[r + c * lds] = s[gr] * (a * g) * sc_c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_concat(const BatchEntry *tab, double *cams, double *pts,
+                                               double *info, int32_t *oc, int32_t *op,
+                                               int32_t *cam_scene, DevStatus *ds) {
+  const BatchEntry e = tab[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < e.t; i += stride) {
+    int c = e.oc[i], p = e.op[i];
+    if (c < 0 || c >= e.n || p < 0 || p >= e.m) {
+      report_error(ds, UCOV_EINVAL, (int)(e.obs0 + i));
+      c = 0;
+      p = 0;
+    }
+    oc[e.obs0 + i] = e.cam0 + c;
+    op[e.obs0 + i] = e.pt0 + p;
+    if (info) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        info[3 * (e.obs0 + i) + k] = e.info ? e.info[3 * i + k] : (k == 1 ? 0.0 : 1.0);
+    }
+  }
+  for (int64_t i = i0; i < 9 * (int64_t)e.n; i += stride) cams[9 * (int64_t)e.cam0 + i] = e.cams[i];
+  for (int64_t i = i0; i < 3 * (int64_t)e.m; i += stride) pts[3 * (int64_t)e.pt0 + i] = e.pts[i];
+  for (int64_t i = i0; i < e.n; i += stride) cam_scene[e.cam0 + i] = (int32_t)blockIdx.y;
 }
 
 // Off-diagonal block Z_ik = -sum_e J_P,a^T K_e J_P,b with K_e = Y_a J_X,b^T
@@ -802,7 +887,7 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
   d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   const int col = lane & 15, kk = lane >> 4, p = kk & 1;
   if (i != k) {
-    const int64_t bin = tri(i) + k;
+    const int64_t bin = bin_of(sc, i, k);
     const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
     // 16 pairs (8 MFMAs) per iteration; all loads are issued before the MFMAs
     constexpr int U = 8;
@@ -835,21 +920,31 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
       }
     }
   }
-  const double a = mode ? *alpha : 0.0;
+  int si = 0;
+  int64_t row0 = 0, off = 0, lds = ld;
+  if (sc.cam_scene) {
+    si = sc.cam_scene[i];
+    row0 = 9 * (int64_t)sc.cam_off[si];
+    off = sc.a_off[si];
+    lds = sc.a_ld[si];
+  }
+  const double a = mode ? alpha[si] : 0.0;
+  double *o = out + off;
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     const int row = 4 * v + (lane >> 4);
     if (row >= 9 || col >= 9) continue;
     const double z = (i == k) ? zdiag[81 * (int64_t)i + 9 * row + col] : -(acc0[v] + acc1[v]);
-    const int64_t pr = 9 * (int64_t)i + row, pc = 9 * (int64_t)k + col;
+    const int64_t pr = 9 * (int64_t)i + row, pc = 9 * (int64_t)k + col;  // global rows
+    const int64_t lr = pr - row0, lc = pc - row0;                        // rows in the scene
     if (mode == 0) {
-      out[pr + pc * ld] = z;
-      out[pc + pr * ld] = z;
+      o[lr + lc * lds] = z;
+      o[lc + lr * lds] = z;
     } else {
       double g = 0.0;
 #pragma unroll
       for (int h = 0; h < 7; ++h) g += q[h * N + pr] * q[h * N + pc];
-      out[pr + pc * ld] = s[pr] * (z + a * g) * s[pc];
+      o[lr + lc * lds] = s[pr] * (z + a * g) * s[pc];
     }
   }
 }
@@ -925,11 +1020,26 @@ void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
                      ldz, user_alpha, s, alpha, ds);
 }
 
+void launch_concat_scenes(int n_scenes, const BatchEntry *tab, int64_t max_elems, double *cams,
+                          double *pts, double *info, int32_t *oc, int32_t *op,
+                          int32_t *cam_scene, DevStatus *ds, hipStream_t st) {
+  const unsigned bx = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (max_elems + 255) / 256), 1024);
+  hipLaunchKernelGGL(k_concat, dim3(bx, (unsigned)n_scenes), dim3(256), 0, st, tab, cams, pts,
+                     info, oc, op, cam_scene, ds);
+}
+
+void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const double *zdiag,
+                         double user_alpha, double *s, double *alpha, DevStatus *ds,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gauge_scenes, dim3((unsigned)sc.n_scenes), dim3(kGaugeThreads), 0, st, sc,
+                     hc, q, zdiag, user_alpha, s, alpha, ds);
+}
+
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
                      int64_t n_nonzero, hipStream_t st) {
   const int64_t N = 9 * (int64_t)sc.n;
-  hipLaunchKernelGGL(k_fill_empty, dim3(blocks_for(N, kBlk), (unsigned)N), dim3(kBlk), 0, st, N,
-                     w.bin_cnt, w.q, w.s, w.alpha, mode, out, ld);
+  hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)N), dim3(256), 0, st, sc, w.bin_cnt, w.q, w.s,
+                     w.alpha, mode, out, ld);
   if (n_nonzero > 0)
     hipLaunchKernelGGL(k_bin_blocks, dim3(blocks_for(n_nonzero, 4)), dim3(256), 0, st, sc,
                        w.nzlist, w.nzcount, w.bin_ptr, w.pairs, w.rec, w.zdiag, w.q, w.s,

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ucov_internal.h"
 #include "../../include/ucov.h"
@@ -46,6 +47,17 @@ struct ucov_ctx {
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount;
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
+  // batched calls: the concatenated scenes, their tables, per-scene status and
+  // the worker streams that run the dense stages of the scenes side by side
+  static constexpr int kWorkers = 8;
+  hipStream_t workers[kWorkers] = {};
+  hipEvent_t wev[kWorkers] = {};
+  Buf b_cams, b_pts, b_info, b_oc, b_op, b_cam_scene, b_tab, b_ds;
+  Buf wtmp[kWorkers];
+  void *h_stage = nullptr;  // pinned host staging of the scene tables
+  size_t h_stage_cap = 0;
+  DevStatus *h_ds = nullptr;  // pinned host copy of the per-scene status
+  size_t h_ds_cap = 0;
 
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
@@ -94,8 +106,8 @@ int sync_status(ucov_ctx *c, ucov_report *rep, const char *where) {
     hipError_t e = hipGetLastError();
     return c->fail(UCOV_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
   }
-  if (rep) rep->bad_index = c->ds_host->index;
   if (c->ds_host->code != 0) {
+    if (rep) rep->bad_index = c->ds_host->index;
     char buf[160];
     snprintf(buf, sizeof buf, "%s (index %d)", where, c->ds_host->index);
     return c->fail(c->ds_host->code, buf);
@@ -118,20 +130,12 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Steps a1-a2 up to the per-camera diagonal blocks and the nullspace rows.
 // On return the slot records, pair bins, zdiag and hc are valid.
-int run_scene_stage(ucov_ctx *c, const ucov_scene *scene, double *jp_out, double *jx_out,
-                    bool jac_only, ucov_report *rep) {
-  SceneDev sc;
-  sc.n = scene->n_cams;
-  sc.m = scene->n_pts;
-  sc.t = scene->n_obs;
-  sc.cams = scene->cams;
-  sc.pts = scene->pts;
-  sc.info = scene->obs_info;
-  sc.oc = scene->obs_cam;
-  sc.op = scene->obs_pt;
+// nbins: camera-pair bins, n(n+1)/2 for one scene, the sum over the scenes of
+// a concatenation.  The status must have been cleared by the caller.
+int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_out,
+                    double *jx_out, bool jac_only, ucov_report *rep) {
   const int64_t n = sc.n, m = sc.m, t = sc.t;
   const int64_t N = 9 * n;
-  const int64_t nbins = n * (n + 1) / 2;
   const int64_t scan_tiles = (std::max(nbins, m) + 4095) / 4096 + 2;
   UCOV_TRY(ensure(c, c->cnt_p, 4 * m));
   UCOV_TRY(ensure(c, c->ptr_p, 8 * (m + 1)));
@@ -153,7 +157,6 @@ int run_scene_stage(ucov_ctx *c, const ucov_scene *scene, double *jp_out, double
   hipStream_t st = c->stream;
 
   hipEventRecord(c->ev[0], st);
-  fill_i32(reinterpret_cast<int32_t *>(c->ds), 0, 2, st);
   fill_i32(w.cnt_p, 0, m, st);
   fill_i32(w.cur_p, 0, m, st);
   launch_count_points(sc, w, c->ds, st);
@@ -237,6 +240,19 @@ SceneDev scene_dev(const ucov_scene *scene) {
   return sc;
 }
 
+int64_t single_bins(const SceneDev &sc) { return (int64_t)sc.n * (sc.n + 1) / 2; }
+
+void clear_status(ucov_ctx *c) {
+  fill_i32(reinterpret_cast<int32_t *>(c->ds), 0, 2, c->stream);
+}
+
+void reset_report(ucov_report *rep) {
+  if (!rep) return;
+  memset(rep, 0, sizeof *rep);
+  rep->bad_index = -1;
+  rep->bad_scene = -1;
+}
+
 void fill_defaults(const ucov_options *opt, ucov_options &o) {
   o.precision = UCOV_FP64;
   o.max_iter = 6;
@@ -303,7 +319,7 @@ int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double 
     return c->fail(UCOV_ENOCONV, buf);
   }
   hipEventRecord(c->ev[4], st);
-  launch_extract_full(N, as<double>(c->m_x64), Np, as<double>(c->s), as<double>(c->q),
+  launch_extract_full(N, as<double>(c->m_x64), Np, as<double>(c->s), as<double>(c->q), N,
                       as<double>(c->alpha), cov_out, st);
   return UCOV_OK;
 }
@@ -320,8 +336,8 @@ int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_o
     UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
     spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
     hipEventRecord(c->ev[4], st);
-    launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), as<double>(c->alpha), cov_out,
-                   st);
+    launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), N, as<double>(c->alpha),
+                   cov_out, st);
   } else {
     UCOV_TRY(run_mixed(c, N, Np, o, cov_out, rep));
   }
@@ -357,6 +373,15 @@ int ucov_create(ucov_ctx **ctx, int device) {
     return UCOV_ENOMEM;
   }
   for (auto &e : c->ev) hipEventCreate(&e);
+  for (int k = 0; k < ucov_ctx::kWorkers; ++k) {
+    // default priority, non-blocking with respect to the null stream
+    if (hipStreamCreateWithFlags(&c->workers[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->wev[k], hipEventDisableTiming) != hipSuccess) {
+      hipGetLastError();
+      ucov_destroy(c);
+      return UCOV_EDEVICE;
+    }
+  }
   if (ensure(c, c->alpha, 8) != UCOV_OK) {
     ucov_destroy(c);
     return UCOV_ENOMEM;
@@ -380,9 +405,17 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
-                 &c->m_sum};
+                 &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
+                 &c->b_cam_scene, &c->b_tab, &c->b_ds};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
+  for (int k = 0; k < ucov_ctx::kWorkers; ++k) {
+    if (c->wtmp[k].p) hipFree(c->wtmp[k].p);
+    if (c->workers[k]) hipStreamDestroy(c->workers[k]);
+    if (c->wev[k]) hipEventDestroy(c->wev[k]);
+  }
+  if (c->h_stage) hipHostFree(c->h_stage);
+  if (c->h_ds) hipHostFree(c->h_ds);
   if (c->ds) hipFree(c->ds);
   if (c->ds_host) hipHostFree(c->ds_host);
   if (c->i64_host) hipHostFree(c->i64_host);
@@ -396,7 +429,9 @@ int ucov_jacobians(ucov_ctx *c, const ucov_scene *scene, double *jp, double *jx)
   UCOV_TRY(check_scene(c, scene));
   if (!jp || !jx) return c->fail(UCOV_EINVAL, "NULL output");
   hipSetDevice(c->device);
-  return run_scene_stage(c, scene, jp, jx, true, nullptr);
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  return run_scene_stage(c, sc, single_bins(sc), jp, jx, true, nullptr);
 }
 
 int ucov_reduced_camera_matrix(ucov_ctx *c, const ucov_scene *scene, double *z, int64_t ldz,
@@ -406,9 +441,10 @@ int ucov_reduced_camera_matrix(ucov_ctx *c, const ucov_scene *scene, double *z, 
   const int64_t N = 9 * (int64_t)scene->n_cams;
   if (!z || ldz < N) return c->fail(UCOV_EINVAL, "bad output matrix");
   hipSetDevice(c->device);
-  if (rep) memset(rep, 0, sizeof *rep);
-  UCOV_TRY(run_scene_stage(c, scene, nullptr, nullptr, false, rep));
-  SceneDev sc = scene_dev(scene);
+  reset_report(rep);
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, single_bins(sc), nullptr, nullptr, false, rep));
   SceneWork w = scene_work(c);
   launch_assemble(sc, w, 0, z, ldz, c->n_nonzero, c->stream);
   UCOV_TRY(check_hip(c, "assemble"));
@@ -419,7 +455,9 @@ int ucov_gauge_basis(ucov_ctx *c, const ucov_scene *scene, double *hc, double *q
   if (!c) return UCOV_EINVAL;
   UCOV_TRY(check_scene(c, scene));
   hipSetDevice(c->device);
-  UCOV_TRY(run_scene_stage(c, scene, nullptr, nullptr, false, nullptr));
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, single_bins(sc), nullptr, nullptr, false, nullptr));
   const int64_t N = 9 * (int64_t)scene->n_cams;
   UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
   UCOV_TRY(ensure(c, c->s, 8 * N));
@@ -441,14 +479,15 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   hipSetDevice(c->device);
-  if (rep) memset(rep, 0, sizeof *rep);
-  UCOV_TRY(run_scene_stage(c, scene, nullptr, nullptr, false, rep));
+  reset_report(rep);
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, single_bins(sc), nullptr, nullptr, false, rep));
   const int64_t N = 9 * (int64_t)scene->n_cams;
   const int64_t Np = round_up(N, kTile);
   UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
   UCOV_TRY(ensure(c, c->s, 8 * N));
   UCOV_TRY(ensure(c, c->amat, 8 * Np * Np));
-  SceneDev sc = scene_dev(scene);
   SceneWork w = scene_work(c);
   hipEventRecord(c->ev[2], c->stream);
   launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, c->stream);
@@ -473,7 +512,7 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
   if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   hipSetDevice(c->device);
-  if (rep) memset(rep, 0, sizeof *rep);
+  reset_report(rep);
   const int64_t N = n, Np = round_up(N, kTile);
   UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
   UCOV_TRY(ensure(c, c->s, 8 * N));
@@ -489,6 +528,241 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
   UCOV_TRY(check_hip(c, "scale"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
   if (rep) hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+  return UCOV_OK;
+}
+
+// Several independent scenes in one call.  The scene stage runs once over the
+// concatenation (one launch per kernel for all scenes: camera-pair bins, the
+// gauge basis and the dense matrices are kept per scene); the dense inverse of
+// each scene then runs on one of the worker streams, largest scenes first, so
+// that small inverses fill the GPU beside the large ones.
+int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_scene *scenes,
+                                   const ucov_options *opt, double *cov_out, double *alphas,
+                                   ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  reset_report(rep);
+  if (n_scenes < 1 || !scenes || !cov_out) return c->fail(UCOV_EINVAL, "bad batch arguments");
+  ucov_options o;
+  fill_defaults(opt, o);
+  if (o.precision != UCOV_FP64)
+    return c->fail(UCOV_EINVAL, "batched calls support UCOV_FP64 only");
+  const int S = n_scenes;
+  // host tables: offsets of every scene in the concatenation
+  std::vector<int32_t> cam_off(S + 1), pt_off(S + 1);
+  std::vector<int64_t> obs_off(S + 1), bin_off(S + 1), a_off(S + 1), a_ld(S);
+  bool any_info = false;
+  int64_t max_elems = 0;
+  {
+    int64_t nc = 0, np = 0, no = 0, nb = 0, na = 0;
+    for (int s = 0; s < S; ++s) {
+      const int rc = check_scene(c, &scenes[s]);
+      if (rc != UCOV_OK) {
+        if (rep) rep->bad_scene = s;
+        return rc;
+      }
+      const ucov_scene &e = scenes[s];
+      cam_off[s] = (int32_t)nc;
+      pt_off[s] = (int32_t)np;
+      obs_off[s] = no;
+      bin_off[s] = nb;
+      a_off[s] = na;
+      const int64_t Np = round_up(9 * (int64_t)e.n_cams, kTile);
+      a_ld[s] = Np;
+      nc += e.n_cams;
+      np += e.n_pts;
+      no += e.n_obs;
+      nb += (int64_t)e.n_cams * (e.n_cams + 1) / 2;
+      na += Np * Np;
+      any_info |= e.obs_info != nullptr;
+      max_elems = std::max({max_elems, e.n_obs, 9 * (int64_t)e.n_cams, 3 * (int64_t)e.n_pts});
+      if (nc > (int64_t)1 << 27 || np >= (int64_t)1 << 31 || no >= (int64_t)1 << 31)
+        return c->fail(UCOV_EINVAL, "batch too large: at most 2^27 cameras and 2^31 - 1 points "
+                                    "and observations in total");
+    }
+    cam_off[S] = (int32_t)nc;
+    pt_off[S] = (int32_t)np;
+    obs_off[S] = no;
+    bin_off[S] = nb;
+    a_off[S] = na;
+  }
+  const int64_t n = cam_off[S], m = pt_off[S], t = obs_off[S];
+  const int64_t N = 9 * n;
+  hipSetDevice(c->device);
+  hipStream_t st = c->stream;
+
+  // staged tables: [entries | cam_off | bin_off | a_off | a_ld], 8-byte aligned
+  const size_t sz_tab = sizeof(BatchEntry) * S, sz_co = round_up(4 * (S + 1), 8),
+               sz_bo = 8 * (S + 1), sz_ao = 8 * (S + 1), sz_ld = 8 * S;
+  const size_t total = sz_tab + sz_co + sz_bo + sz_ao + sz_ld;
+  if (c->h_stage_cap < total) {
+    if (c->h_stage) hipHostFree(c->h_stage);
+    c->h_stage = nullptr;
+    c->h_stage_cap = 0;
+    if (hipHostMalloc(&c->h_stage, total) != hipSuccess) {
+      hipGetLastError();
+      return c->fail(UCOV_ENOMEM, "pinned staging buffer");
+    }
+    c->h_stage_cap = total;
+  }
+  char *hs = static_cast<char *>(c->h_stage);
+  BatchEntry *tab = reinterpret_cast<BatchEntry *>(hs);
+  for (int s = 0; s < S; ++s) {
+    const ucov_scene &e = scenes[s];
+    tab[s] = BatchEntry{e.cams, e.pts, e.obs_info, e.obs_cam, e.obs_pt, e.n_cams, e.n_pts,
+                        e.n_obs, cam_off[s], pt_off[s], obs_off[s]};
+  }
+  memcpy(hs + sz_tab, cam_off.data(), 4 * (S + 1));
+  memcpy(hs + sz_tab + sz_co, bin_off.data(), sz_bo);
+  memcpy(hs + sz_tab + sz_co + sz_bo, a_off.data(), sz_ao);
+  memcpy(hs + sz_tab + sz_co + sz_bo + sz_ao, a_ld.data(), sz_ld);
+
+  UCOV_TRY(ensure(c, c->b_tab, total));
+  UCOV_TRY(ensure(c, c->b_cams, 8 * 9 * n));
+  UCOV_TRY(ensure(c, c->b_pts, 8 * 3 * m));
+  UCOV_TRY(ensure(c, c->b_oc, 4 * t));
+  UCOV_TRY(ensure(c, c->b_op, 4 * t));
+  UCOV_TRY(ensure(c, c->b_cam_scene, 4 * n));
+  UCOV_TRY(ensure(c, c->b_ds, sizeof(DevStatus) * S));
+  if (any_info) UCOV_TRY(ensure(c, c->b_info, 8 * 3 * t));
+  char *dt = static_cast<char *>(c->b_tab.p);
+  hipEventRecord(c->ev[6], st);
+  hipMemcpyAsync(dt, hs, total, hipMemcpyHostToDevice, st);
+  clear_status(c);
+  launch_concat_scenes(S, reinterpret_cast<const BatchEntry *>(dt), max_elems,
+                       as<double>(c->b_cams), as<double>(c->b_pts),
+                       any_info ? as<double>(c->b_info) : nullptr, as<int32_t>(c->b_oc),
+                       as<int32_t>(c->b_op), as<int32_t>(c->b_cam_scene), c->ds, st);
+  SceneDev sc;
+  sc.n = (int)n;
+  sc.m = (int)m;
+  sc.t = t;
+  sc.cams = as<double>(c->b_cams);
+  sc.pts = as<double>(c->b_pts);
+  sc.info = any_info ? as<double>(c->b_info) : nullptr;
+  sc.oc = as<int32_t>(c->b_oc);
+  sc.op = as<int32_t>(c->b_op);
+  sc.n_scenes = S;
+  sc.cam_scene = as<int32_t>(c->b_cam_scene);
+  sc.cam_off = reinterpret_cast<const int32_t *>(dt + sz_tab);
+  sc.bin_off = reinterpret_cast<const int64_t *>(dt + sz_tab + sz_co);
+  sc.a_off = reinterpret_cast<const int64_t *>(dt + sz_tab + sz_co + sz_bo);
+  sc.a_ld = reinterpret_cast<const int64_t *>(dt + sz_tab + sz_co + sz_bo + sz_ao);
+
+  // a failure of the scene stage names a global observation, point or camera:
+  // translate it into (scene, local index)
+  auto localize = [&](int rc) {
+    if (rc == UCOV_OK || !rep || rep->bad_index < 0) return rc;
+    const int64_t g = rep->bad_index;
+    int s = 0;
+    int64_t base = 0;
+    if (rc == UCOV_EINVAL) {
+      s = (int)(std::upper_bound(obs_off.begin(), obs_off.end(), g) - obs_off.begin()) - 1;
+      base = obs_off[s];
+    } else if (rc == UCOV_EPOINT) {
+      s = (int)(std::upper_bound(pt_off.begin(), pt_off.end(), (int32_t)g) - pt_off.begin()) - 1;
+      base = pt_off[s];
+    } else if (rc == UCOV_EGAUGE) {
+      s = (int)(std::upper_bound(cam_off.begin(), cam_off.end(), (int32_t)g) - cam_off.begin()) - 1;
+      base = cam_off[s];
+    } else {
+      return rc;
+    }
+    s = std::min(std::max(s, 0), S - 1);
+    rep->bad_scene = s;
+    rep->bad_index = (int32_t)(g - base);
+    c->last_error += " in scene " + std::to_string(s) + ", local index " +
+                     std::to_string(g - base);
+    return rc;
+  };
+  {
+    const int rc = run_scene_stage(c, sc, bin_off[S], nullptr, nullptr, false, rep);
+    if (rc != UCOV_OK) return localize(rc);
+  }
+  UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
+  UCOV_TRY(ensure(c, c->s, 8 * N));
+  UCOV_TRY(ensure(c, c->alpha, 8 * S));
+  UCOV_TRY(ensure(c, c->amat, 8 * std::max<int64_t>(1, a_off[S])));
+  SceneWork w = scene_work(c);
+  hipEventRecord(c->ev[2], st);
+  launch_gauge_scenes(sc, w.hc, w.q, w.zdiag, o.alpha, w.s, w.alpha, c->ds, st);
+  launch_assemble(sc, w, 1, as<double>(c->amat), 0, c->n_nonzero, st);
+  UCOV_TRY(check_hip(c, "batched assemble"));
+  {
+    const int rc = sync_status(c, rep, "batched gauge");
+    if (rc != UCOV_OK) return localize(rc);
+  }
+
+  // dense stage: longest-processing-time assignment of scenes to workers
+  const int K = std::min(S, (int)ucov_ctx::kWorkers);
+  std::vector<int> order(S);
+  for (int s = 0; s < S; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return a_ld[x] > a_ld[y]; });
+  std::vector<double> load(K, 0.0);
+  std::vector<std::vector<int>> plan(K);
+  std::vector<int64_t> scratch(K, 1);
+  for (int s : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    const double np = (double)a_ld[s];
+    load[k] += np * np * np + 2.0e6;  // flops plus a latency term per scene
+    plan[k].push_back(s);
+    scratch[k] = std::max(scratch[k], spd_lower_inverse_scratch(a_ld[s]));
+  }
+  for (int k = 0; k < K; ++k) UCOV_TRY(ensure(c, c->wtmp[k], 8 * scratch[k]));
+  DevStatus *bds = as<DevStatus>(c->b_ds);
+  fill_i32(reinterpret_cast<int32_t *>(bds), 0, 2 * (int64_t)S, st);
+  hipEventRecord(c->ev[3], st);
+  double *amat = as<double>(c->amat);
+  for (int k = 0; k < K; ++k) {
+    hipStream_t ws = c->workers[k];
+    hipStreamWaitEvent(ws, c->ev[3], 0);
+    for (int s : plan[k]) {
+      const int64_t Ns = 9 * (int64_t)(cam_off[s + 1] - cam_off[s]), Np = a_ld[s];
+      double *A = amat + a_off[s];
+      const int64_t r0 = 9 * (int64_t)cam_off[s];
+      launch_pad_identity(Ns, Np, A, Np, ws);
+      spd_lower_inverse_fp64(A, Np, Np, as<double>(c->wtmp[k]), bds + s, ws);
+      launch_extract(Ns, A, Np, w.s + r0, w.q + r0, N, w.alpha + s, cov_out + 81 * cam_off[s],
+                     ws);
+    }
+    hipEventRecord(c->wev[k], ws);
+    hipStreamWaitEvent(st, c->wev[k], 0);
+  }
+  hipEventRecord(c->ev[4], st);
+  UCOV_TRY(check_hip(c, "batched dense kernels"));
+  // per-scene status of the dense stage
+  if (c->h_ds_cap < (size_t)S) {
+    if (c->h_ds) hipHostFree(c->h_ds);
+    c->h_ds = nullptr;
+    c->h_ds_cap = 0;
+    if (hipHostMalloc(&c->h_ds, sizeof(DevStatus) * S) != hipSuccess) {
+      hipGetLastError();
+      hipStreamSynchronize(st);
+      return c->fail(UCOV_ENOMEM, "pinned status buffer");
+    }
+    c->h_ds_cap = S;
+  }
+  hipMemcpyAsync(c->h_ds, bds, sizeof(DevStatus) * S, hipMemcpyDeviceToHost, st);
+  UCOV_TRY(sync_status(c, rep, "batched dense inverse"));
+  for (int s = 0; s < S; ++s) {
+    if (c->h_ds[s].code != 0) {
+      if (rep) {
+        rep->bad_scene = s;
+        rep->bad_index = c->h_ds[s].index;
+      }
+      char buf[160];
+      snprintf(buf, sizeof buf, "dense inverse of scene %d (camera %d)", s, c->h_ds[s].index);
+      return c->fail(c->h_ds[s].code, buf);
+    }
+  }
+  if (alphas) hipMemcpy(alphas, c->alpha.p, 8 * (size_t)S, hipMemcpyDeviceToHost);
+  if (rep) {
+    hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
+    hipEventElapsedTime(&rep->ms_structure, c->ev[6], c->ev[1]);
+    hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
+    hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
+    rep->ms_extract = 0.0f;
+  }
   return UCOV_OK;
 }
 

@@ -33,10 +33,29 @@ constexpr int kRecY = 24;
 
 // ---- scene stage (scene_kernels.hip) ---------------------------------------
 struct SceneDev {
-  int n, m;
-  int64_t t;
+  int n = 0, m = 0;
+  int64_t t = 0;
+  const double *cams = nullptr, *pts = nullptr, *info = nullptr;
+  const int32_t *oc = nullptr, *op = nullptr;
+  // Several independent scenes concatenated (cameras, points and observations
+  // of scene s follow those of scene s-1); all null for a single scene.
+  int n_scenes = 1;
+  const int32_t *cam_scene = nullptr;  // n: scene of each camera
+  const int32_t *cam_off = nullptr;    // n_scenes + 1: first camera of each scene
+  const int64_t *bin_off = nullptr;    // n_scenes + 1: first camera-pair bin of each scene
+  const int64_t *a_off = nullptr;      // n_scenes + 1: offset of each scene's dense matrix
+  const int64_t *a_ld = nullptr;       // n_scenes: leading dimension of each scene's matrix
+};
+
+// One scene of a batch as the caller passed it (local indices) and where it
+// goes in the concatenation.
+struct BatchEntry {
   const double *cams, *pts, *info;
   const int32_t *oc, *op;
+  int32_t n, m;
+  int64_t t;
+  int32_t cam0, pt0;
+  int64_t obs0;
 };
 
 struct SceneWork {
@@ -69,6 +88,14 @@ void exclusive_scan(const int32_t *in, int64_t *out, int64_t len, int64_t *tmp,
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 void fill_f64(double *p, double v, int64_t n, hipStream_t st);
 
+// Gathers the scenes of a batch into one concatenation (cams, pts, oc, op and,
+// when info is not null, the information blocks; identity for a scene without
+// them).  Local indices outside their own scene are reported as UCOV_EINVAL
+// (index: observation in the concatenation) and replaced by index 0 of the
+// scene, so that no later kernel leaves the scene.  Also fills cam_scene.
+void launch_concat_scenes(int n_scenes, const BatchEntry *tab, int64_t max_elems, double *cams,
+                          double *pts, double *info, int32_t *oc, int32_t *op,
+                          int32_t *cam_scene, DevStatus *ds, hipStream_t st);
 void launch_count_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 void launch_group_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *jx_out,
@@ -83,8 +110,14 @@ void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStre
 void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
                   const double *zdense, int64_t ldz, double user_alpha, double *s,
                   double *alpha, DevStatus *ds, hipStream_t st);
+// The same for every scene of a concatenation (one workgroup per scene; hc, q
+// are N_total x 7 with leading dimension N_total; alpha has one entry per scene).
+void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const double *zdiag,
+                         double user_alpha, double *s, double *alpha, DevStatus *ds,
+                         hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
-// S (Z + a QQ^T) S into out.  n_nonzero is the number of non-empty bins.
+// S (Z + a QQ^T) S into out (per scene at out + a_off[s] with leading dimension
+// a_ld[s] for a concatenation).  n_nonzero is the number of non-empty bins.
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
                      int64_t n_nonzero, hipStream_t st);
 
@@ -100,12 +133,15 @@ void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStrea
 int64_t spd_lower_inverse_scratch(int64_t Np);
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st);
-// cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha
+// cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha (q: N x 7, leading
+// dimension ldq)
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
-                    const double *q, const double *alpha, double *cov, hipStream_t st);
+                    const double *q, int64_t ldq, const double *alpha, double *cov,
+                    hipStream_t st);
 // cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X
 void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                         const double *q, const double *alpha, double *cov, hipStream_t st);
+                         const double *q, int64_t ldq, const double *alpha, double *cov,
+                         hipStream_t st);
 
 // Mixed precision (all matrices Np x Np, leading dimension Np):
 // X0 = L^-T L^-1 of the FP32 Cholesky factor of the lower triangle of a;

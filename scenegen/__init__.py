@@ -2,10 +2,12 @@
 
 This module produces the *inputs* of the camera-covariance computation:
 cameras, points and the observation index set S (paper, Sec. 4, "Problem
-formulation").  It holds none of the method's arithmetic: no projection, no
-Jacobian, no normal equations.  Camera orientations are built as look-at
-frames and converted to angle-axis with SciPy; visibility uses only camera
-centres and viewing directions.
+formulation").  It holds none of the method's arithmetic: no projection
+model, no Jacobian, no normal equations.  Camera orientations are built as
+look-at frames and converted to angle-axis with SciPy; visibility is a
+field-of-view test on those frames (a point is seen when it lies in front of
+the camera within the 640 x 480 frame's viewing cone), with no focal length,
+distortion or derivative involved.
 
 Both the CPU oracle (through the tests) and the GPU library (through the
 Python binding) consume the same ``Scene`` objects, so neither side generates
@@ -27,18 +29,23 @@ Recipes (all distributions are seeded with numpy's PCG64 ``default_rng``):
   point is seen by 3..6 distinct random cameras; f = 1000*U[0.95,1.05];
   k1, k2 ~ N(0, 0.1^2).  Z is 90 x 90.
 * ``spiral_slab``   n cameras (default 500) on an Archimedean spiral of three
-  turns at height 8 above the slab [-10,10]^2 x [-2.5,2.5] (radius 2 -> 12,
+  turns at height 8 above the slab [-10,10]^2 x [-2.5,2.5] (radius 1.5 -> 7.4,
   per-axis jitter N(0, 0.2^2)), nadir-looking with a N(0, (2 deg)^2) tilt;
-  m points (default 50 000) uniform in the slab; track length
-  t = 1 + Geometric(p) (mean 6 for p = 0.2, minimum 2, capped at 30), the
-  track's cameras drawn at random from the 2t cameras nearest the point.
-  Z is 9n x 9n (4500 x 4500 by default).
+  m points (default 50 000) in the slab, each drawn on the viewing ray of a
+  random pixel of a random camera at a height uniform in the slab and kept
+  when at least two cameras see it; track length t = 1 + Geometric(p) (mean
+  6 for p = 0.2, minimum 2, capped at 30 and at the number of cameras that
+  see the point), the track's cameras drawn at random from the 2t nearest
+  cameras that see the point.  Z is 9n x 9n (4500 x 4500 by default).
 * ``clustered``     10 clusters of 300 cameras on a ring of radius 40 and
   500 000 points, Zipf(1.5) track lengths on [2, 30], 2 % of the tracks
   spanning two adjacent clusters and 5 % of the points placed so far away
   that their triangulation angle is about 1e-4 rad (near-zero baseline).
 * ``batch_scenes``  256 independent spiral scenes with camera counts
-  log-uniform in [20, 400], 100 points per camera and mean track length 5.
+  log-uniform in [20, 400], 100 points per camera and mean track length 5;
+  scene s is a stretch of 3 n_s / 500 turns of the spiral above, so that the
+  camera spacing and the overlap of neighbouring views are those of the
+  500-camera scene.
 
 The observed image coordinates (and their 1 px noise) are not generated: a
 first-order covariance does not depend on the residuals (Sec. 4, the normal
@@ -174,45 +181,112 @@ def tiny_circle(seed: int = 0, n: int = 10, m: int = 200, radius: float = 10.0,
     return _finish(rng, cams, pts, tracks, "tiny_circle", seed, with_info)
 
 
-def _spiral_cameras(rng, n, scale):
-    # Archimedean spiral r = scale*(0.2 + theta/(6 pi)), three turns, cameras at
-    # equal arc-length spacing along it
-    fine = np.linspace(0.0, 6 * np.pi, 20001)
-    r_f = scale * (0.2 + fine / (6 * np.pi))
-    arc = np.concatenate([[0.0], np.cumsum(0.5 * (r_f[1:] + r_f[:-1]) * np.diff(fine))])
+def _look_at_axes(forward: np.ndarray, up: np.ndarray) -> np.ndarray:
+    """Rows x, y, z of look-at camera frames (z = viewing direction)."""
+    z = forward / np.linalg.norm(forward, axis=1, keepdims=True)
+    x = np.cross(z, up)
+    bad = np.linalg.norm(x, axis=1) < 1e-9
+    if bad.any():
+        x[bad] = np.cross(z[bad], np.array([1.0, 0.0, 0.0]))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return np.stack([x, np.cross(z, x), z], axis=1)
+
+
+def _spiral_cameras(rng, n, scale, turns=3.0):
+    # Archimedean spiral r = scale*(0.15 + 0.59 theta/(2 pi turns)), cameras at
+    # equal arc-length spacing along it; the outer end (0.74 scale) keeps every
+    # camera's ground footprint (half-width 0.26 scale) inside the slab
+    fine = np.linspace(0.0, 2 * np.pi * turns, 20001)
+    r_f = scale * (0.15 + 0.59 * fine / (2 * np.pi * turns))
+    ds = np.hypot(np.diff(r_f), 0.5 * (r_f[1:] + r_f[:-1]) * np.diff(fine))
+    arc = np.concatenate([[0.0], np.cumsum(ds)])
     theta = np.interp(np.linspace(0.0, arc[-1], n), arc, fine)
-    rad = scale * (0.2 + theta / (6 * np.pi))
+    rad = scale * (0.15 + 0.59 * theta / (2 * np.pi * turns))
     centres = np.column_stack([rad * np.cos(theta), rad * np.sin(theta),
                                np.full(n, 0.8 * scale)])
     centres += rng.normal(0.0, 0.02 * scale, (n, 3))
     tilt = Rotation.from_rotvec(rng.normal(0.0, np.deg2rad(2.0), (n, 3)))
     forward = tilt.apply(np.array([0.0, 0.0, -1.0]))
     up = np.column_stack([np.cos(theta), np.sin(theta), np.zeros(n)])  # radial direction
-    rot = _look_at_rotvec(centres, forward, up)
-    return np.column_stack([rot, centres, _intrinsics(rng, n)])
+    axes = _look_at_axes(forward, up)
+    rot = Rotation.from_matrix(axes).as_rotvec()
+    return np.column_stack([rot, centres, _intrinsics(rng, n)]), axes
+
+
+# Field of view used for visibility: a point is seen by a camera when it lies
+# in front of it inside the 640 x 480 frame of a 1000 px focal length
+# (half-angle tangents 0.32 and 0.24, kept slightly inside the frame).
+_FOV_TAN = (0.30, 0.22)
+
+
+def _in_view(axes, centres, pts, cand, chunk=4096):
+    """(m, K) mask: candidate camera cand[j, k] sees point j."""
+    cen = [np.ascontiguousarray(centres[:, c]) for c in range(3)]
+    ax = [[np.ascontiguousarray(axes[:, i, c]) for c in range(3)] for i in range(3)]
+    out = np.empty(cand.shape, dtype=bool)
+    for j0 in range(0, cand.shape[0], chunk):
+        cj = cand[j0:j0 + chunk]
+        d = [pts[j0:j0 + chunk, None, c] - cen[c][cj] for c in range(3)]   # (chunk, K) each
+        xc = [sum(ax[i][c][cj] * d[c] for c in range(3)) for i in range(3)]
+        z = xc[2]
+        out[j0:j0 + chunk] = ((z > 0) & (np.abs(xc[0]) <= _FOV_TAN[0] * z)
+                              & (np.abs(xc[1]) <= _FOV_TAN[1] * z))
+    return out
 
 
 def spiral_slab(seed: int = 0, n: int = 500, m: int = 50_000, p_geom: float = 0.2,
-                scale: float = 10.0, with_info: bool = False, max_track: int = 30) -> Scene:
+                scale: float = 10.0, with_info: bool = False, max_track: int = 30,
+                turns: float = 3.0) -> Scene:
     """Cameras on a noisy spiral above a slab of points (nadir views).
 
-    With the default ``scale`` of 10 the spiral radius runs 2 -> 12 at height
-    8 and the slab is [-10,10]^2 x [-2.5,2.5].
+    With the default ``scale`` of 10 the spiral radius runs 1.5 -> 7.4 at
+    height 8 and the slab is [-10,10]^2 x [-2.5,2.5].  Every point lies in the view of
+    at least two cameras; its track is drawn among the cameras that see it.
     """
     rng = np.random.default_rng(seed)
-    cams = _spiral_cameras(rng, n, scale)
+    cams, axes = _spiral_cameras(rng, n, scale, turns)
     centres = cams[:, 3:6]
-    pts = np.column_stack([rng.uniform(-scale, scale, (m, 2)),
-                           rng.uniform(-0.25 * scale, 0.25 * scale, m)])
-    t = np.minimum(1 + rng.geometric(p_geom, m), min(max_track, n))
-    kmax = int(min(n, 2 * t.max()))
     tree = cKDTree(centres)
-    _, near = tree.query(pts, k=kmax)
-    near = np.atleast_2d(near)
-    tracks = []
-    for j in range(m):
-        cand = near[j, :min(n, 2 * t[j])]
-        tracks.append(rng.choice(cand, size=t[j], replace=False))
+    K = int(min(n, 2 * max_track + 20))
+    pts_l, cand_l, vis_l = [], [], []
+    have = 0
+    while have < m:
+        b = int(1.3 * (m - have)) + 64
+        # a ray through a random pixel of a random camera, cut at a random
+        # height of the slab
+        a = rng.integers(0, n, b)
+        ray = np.column_stack([rng.uniform(-_FOV_TAN[0], _FOV_TAN[0], b),
+                               rng.uniform(-_FOV_TAN[1], _FOV_TAN[1], b), np.ones(b)])
+        ray = (axes[a] * ray[:, :, None]).sum(axis=1)          # R^T ray: to world coordinates
+        zt = rng.uniform(-0.25 * scale, 0.25 * scale, b)
+        p = centres[a] + ray * ((zt - centres[a, 2]) / ray[:, 2])[:, None]
+        ok = (np.abs(p[:, 0]) <= scale) & (np.abs(p[:, 1]) <= scale)
+        p = p[ok]
+        _, cand = tree.query(p, k=K, workers=-1)
+        cand = np.atleast_2d(cand).reshape(p.shape[0], K)
+        vis = _in_view(axes, centres, p, cand)
+        keep = vis.sum(axis=1) >= 2
+        pts_l.append(p[keep])
+        cand_l.append(cand[keep])
+        vis_l.append(vis[keep])
+        have += int(keep.sum())
+    pts = np.concatenate(pts_l)[:m]
+    cand = np.concatenate(cand_l)[:m]
+    vis = np.concatenate(vis_l)[:m]
+    nvis = vis.sum(axis=1)
+    t = np.minimum(np.minimum(1 + rng.geometric(p_geom, m), max_track), nvis)
+    # t_j distinct cameras uniformly among the 2 t_j nearest cameras that see
+    # the point: random keys, every other candidate masked out, the t_j
+    # smallest keys kept
+    rank = np.cumsum(vis, axis=1) - 1                          # rank among the visible ones
+    allowed = vis & (rank < 2 * t[:, None])
+    keys = rng.random((m, K))
+    keys[~allowed] = np.inf
+    tmax = int(t.max())
+    part = np.argpartition(keys, tmax - 1, axis=1)[:, :tmax]    # the tmax smallest, unordered
+    part = np.take_along_axis(part, np.argsort(np.take_along_axis(keys, part, axis=1), axis=1), axis=1)
+    picked = np.take_along_axis(cand, part, axis=1)
+    tracks = [picked[j, :t[j]] for j in range(m)]
     return _finish(rng, cams, pts, tracks, f"spiral_slab_n{n}", seed, with_info)
 
 
@@ -258,7 +332,7 @@ def clustered(seed: int = 0, n_clusters: int = 10, per_cluster: int = 300,
         if sel.size == 0:
             continue
         kmax = int(min(per_cluster, 2 * t[sel].max()))
-        _, near = trees[c].query(pts[sel], k=kmax)
+        _, near = trees[c].query(pts[sel], k=kmax, workers=-1)
         near = np.atleast_2d(near)
         for row, j in enumerate(sel):
             cand = near[row, :min(per_cluster, 2 * t[j])]
@@ -291,9 +365,10 @@ def batch_scenes(seed: int = 1000, count: int = 256, lo: int = 20, hi: int = 400
     sizes = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(int)
     out = []
     for s, n in enumerate(sizes):
-        scale = 10.0 * math.sqrt(n / 500.0)
+        # a stretch of the 500-camera spiral: the same camera spacing and
+        # height, so neighbouring views overlap as much as there
         out.append(spiral_slab(seed + 1 + s, n=int(n), m=int(pts_per_cam * n),
-                               p_geom=p_geom, scale=scale))
+                               p_geom=p_geom, turns=3.0 * n / 500.0))
     return out
 
 
