@@ -1,0 +1,202 @@
+"""Learned-screener reference (oracle; test infrastructure only).
+
+The screener predicts a camera's 9x9 covariance from cheap per-camera
+features, for fast screening of reconstructions.  Screening cameras by their
+uncertainty, e.g. to drop mostly unconstrained ones before bundle adjustment,
+is one of the uses the paper motivates (Sec. 1).  The network itself is not
+part of the paper; the exact covariance (Sec. 5) is its training label and
+the judge of its error.
+
+Everything here is plain FP64 numpy, written for checking, not speed:
+
+* ``camera_features``  55 values per camera:
+    - 45: the diagonal block Z_ii of the reduced camera matrix (Sec. 5.2),
+      Z_ii = U_i - sum over camera i's observations o of W_o V_j^-1 W_o^T,
+      as log10 of its 9 diagonal entries and its 36 correlations
+      Z_ab / sqrt(Z_aa Z_bb), in row-major upper-triangular order;
+    - 8: log(1 + count) of the camera's observations whose track length falls
+      in the bins 2, 3, 4, 5, 6-7, 8-10, 11-15, >= 16;
+    - 1: the mean over the camera's observations of the largest angle (rad)
+      between its viewing ray to the point and the ray of any other camera of
+      that point's track;
+    - 1: log(1 + number of other cameras that share a point with it).
+* ``log_cholesky`` / ``from_log_cholesky``: Sigma~ = D^-1 Sigma D^-1 = L L^T,
+  parameters (log L_aa on the diagonal, L_ab below it) in row-major
+  lower-triangular order.
+* ``mlp_forward`` / ``mlp_backward``: 55 -> 256 -> 256 -> 256 -> 45, ReLU
+  between layers, linear output, mean squared error over batch and outputs.
+  Parameters are one flat vector: for each layer W (out x in, row-major)
+  then b (out).
+* ``adam_step``: Adam with bias correction.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import camera, schur
+
+LAYERS = (55, 256, 256, 256, 45)
+N_FEATURES = LAYERS[0]
+N_OUT = LAYERS[-1]
+TRACK_BINS = (2, 3, 4, 5, 6, 8, 11, 16)  # lower edges; the last bin is open
+
+
+def param_count(layers=LAYERS) -> int:
+    return sum(o * i + o for i, o in zip(layers[:-1], layers[1:]))
+
+
+def split_params(p, layers=LAYERS):
+    """Views (W_l, b_l) of the flat parameter vector."""
+    out, k = [], 0
+    for i, o in zip(layers[:-1], layers[1:]):
+        W = p[k:k + o * i].reshape(o, i)
+        k += o * i
+        b = p[k:k + o]
+        k += o
+        out.append((W, b))
+    assert k == p.size
+    return out
+
+
+# ---------------------------------------------------------------------------
+# features
+# ---------------------------------------------------------------------------
+
+def z_diagonal_blocks(scene) -> np.ndarray:
+    """Z_ii for every camera, straight from its observations' terms."""
+    oc, op = scene.obs_cam.astype(np.int64), scene.obs_pt.astype(np.int64)
+    n, m = scene.n_cams, scene.n_pts
+    JP, JX = camera.jacobians(scene.cams, scene.pts, oc, op)
+    Lam = schur.information_blocks(scene.obs_info, oc.size)
+    U, V, W = schur.normal_blocks(JP, JX, Lam, oc, op, n, m)
+    Z = U.copy()
+    Vinv = np.linalg.inv(V)
+    for o in range(oc.size):
+        Z[oc[o]] -= W[o] @ Vinv[op[o]] @ W[o].T
+    return Z
+
+
+def track_bin(length: int) -> int:
+    b = 0
+    for k, lo in enumerate(TRACK_BINS):
+        if length >= lo:
+            b = k
+    return b
+
+
+def camera_features(scene) -> np.ndarray:
+    n = scene.n_cams
+    oc, op = scene.obs_cam.astype(np.int64), scene.obs_pt.astype(np.int64)
+    F = np.zeros((n, N_FEATURES))
+    Zd = z_diagonal_blocks(scene)
+    for i in range(n):
+        d = np.diag(Zd[i])
+        k = 0
+        for a in range(9):
+            for b in range(a, 9):
+                F[i, k] = np.log10(d[a]) if a == b else Zd[i, a, b] / np.sqrt(d[a] * d[b])
+                k += 1
+    track = {}
+    for o in range(oc.size):
+        track.setdefault(int(op[o]), []).append(int(oc[o]))
+    hist = np.zeros((n, 8))
+    ang_sum = np.zeros(n)
+    cnt = np.zeros(n)
+    covis = [set() for _ in range(n)]
+    C = scene.cams[:, 3:6]
+    for j, cams_j in track.items():
+        X = scene.pts[j]
+        rays = {c: (X - C[c]) / np.linalg.norm(X - C[c]) for c in cams_j}
+        for c in cams_j:
+            hist[c, track_bin(len(cams_j))] += 1
+            best = 0.0
+            for c2 in cams_j:
+                if c2 != c:
+                    best = max(best, float(np.arccos(np.clip(rays[c] @ rays[c2], -1.0, 1.0))))
+                    covis[c].add(c2)
+            ang_sum[c] += best
+            cnt[c] += 1
+    F[:, 45:53] = np.log1p(hist)
+    F[:, 53] = ang_sum / np.maximum(cnt, 1)
+    F[:, 54] = np.log1p([len(s) for s in covis])
+    return F
+
+
+# ---------------------------------------------------------------------------
+# covariance <-> log-Cholesky parameters
+# ---------------------------------------------------------------------------
+
+def log_cholesky(S: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """(k, 9, 9) covariances -> (k, 45) parameters of D^-1 S D^-1."""
+    St = S / (D[None, :, None] * D[None, None, :])
+    L = np.linalg.cholesky(St)
+    out = np.zeros((S.shape[0], N_OUT))
+    k = 0
+    for a in range(9):
+        for b in range(a + 1):
+            out[:, k] = np.log(L[:, a, a]) if a == b else L[:, a, b]
+            k += 1
+    return out
+
+
+def from_log_cholesky(P: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """(k, 45) parameters -> (k, 9, 9) covariances D L L^T D."""
+    L = np.zeros((P.shape[0], 9, 9))
+    k = 0
+    for a in range(9):
+        for b in range(a + 1):
+            L[:, a, b] = np.exp(P[:, k]) if a == b else P[:, k]
+            k += 1
+    St = L @ np.transpose(L, (0, 2, 1))
+    return St * (D[None, :, None] * D[None, None, :])
+
+
+# ---------------------------------------------------------------------------
+# MLP, loss, Adam
+# ---------------------------------------------------------------------------
+
+def mlp_forward(p, x):
+    """Returns the output and the list of layer inputs (for the backward pass)."""
+    h = np.asarray(x, np.float64)
+    inputs = []
+    layers = split_params(p)
+    for li, (W, b) in enumerate(layers):
+        inputs.append(h)
+        a = h @ W.T + b
+        h = np.maximum(a, 0.0) if li + 1 < len(layers) else a
+    return h, inputs
+
+
+def mse(y, t) -> float:
+    return float(np.mean((y - t) ** 2))
+
+
+def mlp_backward(p, x, t):
+    """Loss and its gradient with respect to the flat parameter vector."""
+    y, inputs = mlp_forward(p, x)
+    loss = mse(y, t)
+    g = np.zeros_like(p)
+    gl = split_params(g)
+    layers = split_params(p)
+    dy = 2.0 * (y - t) / y.size
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        h = inputs[li]
+        gl[li][0][...] = dy.T @ h
+        gl[li][1][...] = dy.sum(axis=0)
+        if li > 0:
+            dh = dy @ W
+            dy = dh * (h > 0)  # h = relu(a): d relu / d a = [a > 0] = [h > 0]
+    return loss, g
+
+
+ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(p, g, m, v, step: int, lr: float):
+    """One Adam update (step counts from 1); returns new (p, m, v)."""
+    m = ADAM_B1 * m + (1 - ADAM_B1) * g
+    v = ADAM_B2 * v + (1 - ADAM_B2) * g * g
+    mh = m / (1 - ADAM_B1 ** step)
+    vh = v / (1 - ADAM_B2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + ADAM_EPS), m, v

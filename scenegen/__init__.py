@@ -380,3 +380,14 @@ def by_name(name: str, seed: int = 0) -> Scene:
     if name == "clustered":
         return clustered(seed)
     raise KeyError(name)
+
+
+def mlp_init(seed: int, layers=(55, 256, 256, 256, 45)) -> np.ndarray:
+    """Initial parameters of a ReLU MLP as one flat float64 vector: for each
+    layer W (out x in, row-major, N(0, 2/in)) followed by b (zeros)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in zip(layers[:-1], layers[1:]):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / i), o * i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts)

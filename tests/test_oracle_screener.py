@@ -1,0 +1,129 @@
+"""Pins of the screener oracle (CPU): features, log-Cholesky, MLP, Adam."""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import scenegen as sg
+from oracle import screener
+from oracle.pipeline import camera_covariance as oracle_cov
+
+
+def test_z_diagonal_blocks_match_the_dense_schur_complement():
+    s = sg.tiny_circle(3, with_info=True)
+    Zd = screener.z_diagonal_blocks(s)
+    Z = oracle_cov(s, keep=True)["Z"]
+    for i in range(s.n_cams):
+        blk = Z[9 * i:9 * i + 9, 9 * i:9 * i + 9]
+        assert np.abs(Zd[i] - blk).max() <= 1e-12 * np.abs(blk).max()
+
+
+def test_features_track_histogram_and_covisibility_brute_force():
+    s = sg.spiral_slab(4, n=20, m=600)
+    F = screener.camera_features(s)
+    tl = np.bincount(s.obs_pt, minlength=s.n_pts)[s.obs_pt]
+    edges = np.array(screener.TRACK_BINS)
+    for i in range(s.n_cams):
+        lens = tl[s.obs_cam == i]
+        counts = [np.sum((lens >= lo) & (lens < hi)) for lo, hi in zip(edges, list(edges[1:]) + [10 ** 9])]
+        assert np.allclose(F[i, 45:53], np.log1p(counts))
+    A = np.zeros((s.n_cams, s.n_pts))
+    A[s.obs_cam, s.obs_pt] = 1
+    co = (A @ A.T) > 0
+    np.fill_diagonal(co, False)
+    assert np.allclose(F[:, 54], np.log1p(co.sum(axis=1)))
+    # Z-block part: unit diagonal correlations are excluded, |corr| <= 1
+    iu = [k for k, (a, b) in enumerate((a, b) for a in range(9) for b in range(a, 9)) if a != b]
+    assert np.all(np.abs(F[:, iu]) <= 1 + 1e-12)
+
+
+def test_triangulation_angle_hand_example():
+    """Two cameras at (+-1, 0, 0) looking along +y, one point at (0, 1, 0):
+    the rays meet at a right angle."""
+    rows = np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]])  # camera z axis = world +y
+    r = Rotation.from_matrix(rows).as_rotvec()
+    cams = np.array([[*r, -1.0, 0, 0, 1000.0, 0, 0], [*r, 1.0, 0, 0, 1000.0, 0, 0]])
+    pts = np.array([[0.0, 1.0, 0.0], [0.2, 2.0, 0.3]])
+    s = sg.Scene(cams, pts, np.array([0, 1, 0, 1], np.int32), np.array([0, 0, 1, 1], np.int32))
+    with np.errstate(all="ignore"):
+        F = screener.camera_features(s)
+    second = np.arccos(np.dot(pts[1] - cams[0, 3:6], pts[1] - cams[1, 3:6])
+                       / np.linalg.norm(pts[1] - cams[0, 3:6]) / np.linalg.norm(pts[1] - cams[1, 3:6]))
+    assert F[0, 53] == pytest.approx(0.5 * (np.pi / 2 + second), rel=1e-12)
+    assert F[1, 53] == pytest.approx(F[0, 53], rel=1e-12)
+    assert np.allclose(F[:, 54], np.log(2.0))
+    assert np.allclose(F[:, 45], np.log(3.0)) and np.allclose(F[:, 46:53], 0.0)
+
+
+def test_log_cholesky_closed_form_and_round_trip():
+    D = np.linspace(0.5, 2.0, 9)
+    s = np.linspace(1.0, 3.0, 9)
+    S = np.diag((D * s) ** 2)[None]
+    P = screener.log_cholesky(S, D)
+    diag_idx = [a * (a + 1) // 2 + a for a in range(9)]
+    assert np.allclose(P[0, diag_idx], np.log(s), atol=1e-14)
+    assert np.allclose(np.delete(P[0], diag_idx), 0.0, atol=1e-14)
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(5, 9, 9))
+    S = A @ np.transpose(A, (0, 2, 1)) + 0.1 * np.eye(9)
+    back = screener.from_log_cholesky(screener.log_cholesky(S, D), D)
+    assert np.abs(back - S).max() <= 1e-12 * np.abs(S).max()
+
+
+def torch_mlp(p):
+    mods = []
+    for li, (W, b) in enumerate(screener.split_params(p)):
+        lin = torch.nn.Linear(W.shape[1], W.shape[0]).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(W))
+            lin.bias.copy_(torch.from_numpy(b))
+        mods.append(lin)
+        if li + 1 < 4:
+            mods.append(torch.nn.ReLU())
+    return torch.nn.Sequential(*mods)
+
+
+def test_mlp_forward_and_backward_match_torch_autograd():
+    p = sg.mlp_init(5)
+    p[200:300] += 0.05  # some nonzero biases
+    assert p.size == screener.param_count() == 157485
+    rng = np.random.default_rng(1)
+    x, t = rng.normal(size=(33, 55)), rng.normal(size=(33, 45))
+    y, _ = screener.mlp_forward(p, x)
+    net = torch_mlp(p)
+    yt = net(torch.from_numpy(x))
+    assert np.abs(y - yt.detach().numpy()).max() <= 1e-12 * np.abs(y).max()
+    loss, g = screener.mlp_backward(p, x, t)
+    lt = torch.mean((yt - torch.from_numpy(t)) ** 2)
+    lt.backward()
+    gt = np.concatenate([np.concatenate([m.weight.grad.numpy().ravel(), m.bias.grad.numpy()])
+                         for m in net if isinstance(m, torch.nn.Linear)])
+    assert loss == pytest.approx(lt.item(), rel=1e-13)
+    assert np.abs(g - gt).max() <= 1e-12 * np.abs(gt).max()
+
+
+def test_mlp_backward_central_differences():
+    p = sg.mlp_init(6)
+    rng = np.random.default_rng(2)
+    x, t = rng.normal(size=(7, 55)), rng.normal(size=(7, 45))
+    _, g = screener.mlp_backward(p, x, t)
+    idx = rng.choice(p.size, 40, replace=False)
+    idx = np.concatenate([idx, [0, p.size - 1, 55 * 256 + 3]])  # W1, last bias, b1
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (screener.mse(screener.mlp_forward(p + e, x)[0], t)
+              - screener.mse(screener.mlp_forward(p - e, x)[0], t)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-9, k
+
+
+def test_adam_first_steps_closed_form():
+    g = np.array([0.5, -2.0, 1e-3])
+    p0 = np.array([1.0, 2.0, 3.0])
+    p1, m, v = screener.adam_step(p0, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    # first step: bias-corrected moments are g and g^2
+    assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    # second step with the same gradient: again the moments are g and g^2
+    p2, _, _ = screener.adam_step(p1, g, m, v, 2, 0.01)
+    assert np.allclose(p2, p1 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
