@@ -177,6 +177,71 @@ int ucov_pinv_blocks(ucov_ctx *ctx, int64_t n, const double *z, int64_t ldz,
                      const double *q, const ucov_options *opt, double *cov_out,
                      ucov_report *rep);
 
+/* ---- learned screener -----------------------------------------------------
+ * A small network that predicts a camera's 9x9 covariance from 55 cheap
+ * features, for screening cameras by their uncertainty (the paper's Sec. 1
+ * names filtering weakly constrained cameras as a use of the covariance).  It
+ * is not part of the paper's method: its labels come from
+ * ucov_camera_covariance, which stays the reference for its error.
+ *
+ * Network: 55 -> 256 -> 256 -> 256 -> 45, ReLU between layers, linear
+ * output.  Parameters are one float32 vector of ucov_mlp_param_count()
+ * values: for each layer W (out x in, row-major) then b (out).  Products
+ * round their operands to bfloat16 and accumulate in float32; hidden
+ * activations are stored in bfloat16.  Inputs are standardised as
+ * (x - in_mean) / in_std per feature when both are given.  All arrays are
+ * device arrays, row-major per sample. */
+#define UCOV_SCREENER_FEATURES 55
+#define UCOV_SCREENER_OUTPUTS  45
+
+int64_t ucov_mlp_param_count(void);
+
+/* Per-camera features (n_cams x 55 float32): 45 from the diagonal block Z_ii
+ * of the reduced camera matrix (Sec. 5.2; log10 of its 9 diagonal entries,
+ * then its 36 correlations, row-major upper triangle), log(1 + count) of the
+ * camera's observations in the track-length bins 2, 3, 4, 5, 6-7, 8-10, 11-15,
+ * >= 16, the mean over its observations of the largest angle (rad) between
+ * its ray and another track camera's ray to the point, and log(1 + number of
+ * cameras sharing a point with it).  Input rules as ucov_camera_covariance. */
+int ucov_screener_features(ucov_ctx *ctx, const ucov_scene *scene, float *feat);
+
+/* y (batch x 45) = network(x (batch x 55)).  in_mean / in_std: 55 values each,
+ * or both NULL. */
+int ucov_mlp_forward(ucov_ctx *ctx, const float *params, int64_t batch, const float *x,
+                     const float *in_mean, const float *in_std, float *y);
+
+/* Gradient (ucov_mlp_param_count() values) of the mean squared error
+ * mean((network(x) - target)^2) over batch x 45 outputs; loss: device scalar
+ * or NULL. */
+int ucov_mlp_gradient(ucov_ctx *ctx, const float *params, int64_t batch, const float *x,
+                      const float *in_mean, const float *in_std, const float *target,
+                      float *grad, float *loss);
+
+/* n_batches Adam steps (beta1 0.9, beta2 0.999, eps 1e-8; step counts start
+ * at step0 >= 1 for the bias correction) on consecutive batches of x and
+ * target (n_batches * batch rows each), updating params and the moment
+ * vectors adam_m, adam_v (zero before the first step) in place.  losses:
+ * n_batches device floats (the loss of each batch before its step) or NULL. */
+int ucov_mlp_train(ucov_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t step0,
+                   float lr, int64_t batch, int64_t n_batches, const float *x,
+                   const float *in_mean, const float *in_std, const float *target,
+                   float *losses);
+
+/* Training labels: for each of n covariance blocks (n x 81 float64,
+ * row-major) the 45 log-Cholesky parameters of D^-1 Sigma D^-1 = L L^T (log
+ * L_aa on the diagonal, L_ab below it, row-major lower triangle), D = scale
+ * (9 float64), standardised as (p - out_mean) / out_std.  UCOV_EINVAL if a
+ * block is not positive definite (bad_index: the block). */
+int ucov_screener_labels(ucov_ctx *ctx, int64_t n, const double *cov, const double *scale,
+                         const float *out_mean, const float *out_std, float *labels);
+
+/* The inverse map: network outputs y (n x 45) -> covariance blocks D L L^T D
+ * (n x 81, may be NULL) and the spread trace(L L^T) of the normalised
+ * covariance (n, may be NULL). */
+int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const double *scale,
+                             const float *out_mean, const float *out_std, double *cov,
+                             double *spread);
+
 /* Text for an error code; description of the last failure on this context. */
 const char *ucov_strerror(int code);
 const char *ucov_last_error(const ucov_ctx *ctx);

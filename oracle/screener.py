@@ -28,6 +28,14 @@ Everything here is plain FP64 numpy, written for checking, not speed:
   Parameters are one flat vector: for each layer W (out x in, row-major)
   then b (out).
 * ``adam_step``: Adam with bias correction.
+
+``mlp_forward`` and ``mlp_backward`` also run in a ``bf16`` mode that rounds
+every product operand (layer input, weights, output gradient) and every stored
+hidden activation to bfloat16 and accumulates in FP64.  A network whose
+products run in BF16 decides each ReLU on a pre-activation computed from
+rounded operands; near zero that decision can differ from the FP64 one and
+reroute a whole unit's gradient, so gradients of a BF16 network are compared
+with this mode, in which the decisions are taken in the same precision.
 """
 from __future__ import annotations
 
@@ -155,14 +163,24 @@ def from_log_cholesky(P: np.ndarray, D: np.ndarray) -> np.ndarray:
 # MLP, loss, Adam
 # ---------------------------------------------------------------------------
 
-def mlp_forward(p, x):
+def bf16(a) -> np.ndarray:
+    """Round to bfloat16 (the top 16 bits of an IEEE float32; round to
+    nearest, ties to even), returned as float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_forward(p, x, bf16_ops=False):
     """Returns the output and the list of layer inputs (for the backward pass)."""
+    r = bf16 if bf16_ops else (lambda a: a)
     h = np.asarray(x, np.float64)
     inputs = []
     layers = split_params(p)
     for li, (W, b) in enumerate(layers):
+        h = r(h)
         inputs.append(h)
-        a = h @ W.T + b
+        a = h @ r(W).T + b
         h = np.maximum(a, 0.0) if li + 1 < len(layers) else a
     return h, inputs
 
@@ -171,9 +189,10 @@ def mse(y, t) -> float:
     return float(np.mean((y - t) ** 2))
 
 
-def mlp_backward(p, x, t):
+def mlp_backward(p, x, t, bf16_ops=False):
     """Loss and its gradient with respect to the flat parameter vector."""
-    y, inputs = mlp_forward(p, x)
+    r = bf16 if bf16_ops else (lambda a: a)
+    y, inputs = mlp_forward(p, x, bf16_ops)
     loss = mse(y, t)
     g = np.zeros_like(p)
     gl = split_params(g)
@@ -182,11 +201,12 @@ def mlp_backward(p, x, t):
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
         h = inputs[li]
-        gl[li][0][...] = dy.T @ h
         gl[li][1][...] = dy.sum(axis=0)
+        dy = r(dy)
+        gl[li][0][...] = dy.T @ h
         if li > 0:
-            dh = dy @ W
-            dy = dh * (h > 0)  # h = relu(a): d relu / d a = [a > 0] = [h > 0]
+            dh = dy @ r(W)
+            dy = r(dh * (h > 0))  # h = relu(a): d relu / d a = [a > 0] = [h > 0]
     return loss, g
 
 

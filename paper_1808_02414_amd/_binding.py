@@ -47,7 +47,12 @@ class Report(ctypes.Structure):
 EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covariance",
            "ucov_camera_covariance_batched",
            "ucov_jacobians", "ucov_reduced_camera_matrix", "ucov_gauge_basis",
-           "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error"]
+           "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error",
+           "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
+           "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
+           "ucov_screener_covariance"]
+
+N_FEATURES, N_OUTPUTS = 55, 45
 
 _lib = None
 
@@ -77,6 +82,14 @@ def load(path: str = LIB_PATH):
         "ucov_gauge_basis": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
         "ucov_pinv_blocks": (ctypes.c_int, [P, I64, P, I64, P, ctypes.POINTER(Options), P,
                                             ctypes.POINTER(Report)]),
+        "ucov_mlp_param_count": (I64, []),
+        "ucov_screener_features": (ctypes.c_int, [P, ctypes.POINTER(Scene), P]),
+        "ucov_mlp_forward": (ctypes.c_int, [P, P, I64, P, P, P, P]),
+        "ucov_mlp_gradient": (ctypes.c_int, [P, P, I64, P, P, P, P, P, P]),
+        "ucov_mlp_train": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_float, I64, I64, P, P, P,
+                                          P, P]),
+        "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
+        "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
         "ucov_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ucov_last_error": (ctypes.c_char_p, [P]),
     }
@@ -253,3 +266,93 @@ class Context:
         self._check(self.lib.ucov_pinv_blocks(self.h, N, zc.data_ptr(), N, qc.data_ptr(),
                                               ctypes.byref(opt), out.data_ptr(), ctypes.byref(rep)), rep)
         return out, rep.as_dict()
+
+    # ---- learned screener ---------------------------------------------------
+
+    def mlp_param_count(self) -> int:
+        return int(self.lib.ucov_mlp_param_count())
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else t.data_ptr()
+
+    def _dev(self, t, dtype):
+        assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+        return t.data_ptr()
+
+    def screener_features(self, scene: DeviceScene):
+        """(n, 55) float32 features of every camera."""
+        torch = self.torch
+        f = torch.empty((scene.n_cams, N_FEATURES), dtype=torch.float32, device=scene.cams.device)
+        self._stream()
+        sc = scene.struct()
+        self._check(self.lib.ucov_screener_features(self.h, ctypes.byref(sc), f.data_ptr()))
+        return f
+
+    def mlp_forward(self, params, x, in_mean=None, in_std=None):
+        torch = self.torch
+        f32 = torch.float32
+        y = torch.empty((x.shape[0], N_OUTPUTS), dtype=f32, device=x.device)
+        self._stream()
+        self._check(self.lib.ucov_mlp_forward(
+            self.h, self._dev(params, f32), x.shape[0], self._dev(x, f32),
+            None if in_mean is None else self._dev(in_mean, f32),
+            None if in_std is None else self._dev(in_std, f32), y.data_ptr()))
+        return y
+
+    def mlp_gradient(self, params, x, target, in_mean=None, in_std=None):
+        torch = self.torch
+        f32 = torch.float32
+        g = torch.empty_like(params)
+        loss = torch.zeros(1, dtype=f32, device=x.device)
+        self._stream()
+        self._check(self.lib.ucov_mlp_gradient(
+            self.h, self._dev(params, f32), x.shape[0], self._dev(x, f32),
+            None if in_mean is None else self._dev(in_mean, f32),
+            None if in_std is None else self._dev(in_std, f32), self._dev(target, f32),
+            g.data_ptr(), loss.data_ptr()))
+        return g, float(loss.item())
+
+    def mlp_train(self, params, adam_m, adam_v, step0, lr, batch, x, target,
+                  in_mean=None, in_std=None):
+        """Adam steps over consecutive batches of (x, target) (rows beyond the
+        last whole batch are not used); returns the per-batch losses."""
+        torch = self.torch
+        f32 = torch.float32
+        nb = x.shape[0] // batch
+        losses = torch.zeros(nb, dtype=f32, device=x.device)
+        self._stream()
+        self._check(self.lib.ucov_mlp_train(
+            self.h, self._dev(params, f32), self._dev(adam_m, f32), self._dev(adam_v, f32),
+            int(step0), float(lr), int(batch), int(nb), self._dev(x, f32),
+            None if in_mean is None else self._dev(in_mean, f32),
+            None if in_std is None else self._dev(in_std, f32), self._dev(target, f32),
+            losses.data_ptr()))
+        return losses
+
+    def screener_labels(self, cov, scale, out_mean, out_std):
+        torch = self.torch
+        n = cov.shape[0]
+        lab = torch.empty((n, N_OUTPUTS), dtype=torch.float32, device=cov.device)
+        self._stream()
+        rep = Report()
+        rep.bad_index = -1
+        rc = self.lib.ucov_screener_labels(self.h, n, self._dev(cov, torch.float64),
+                                           self._dev(scale, torch.float64),
+                                           self._dev(out_mean, torch.float32),
+                                           self._dev(out_std, torch.float32), lab.data_ptr())
+        self._check(rc)
+        return lab
+
+    def screener_covariance(self, y, scale, out_mean, out_std):
+        """Predicted (n, 9, 9) covariances and (n,) spreads from network outputs."""
+        torch = self.torch
+        n = y.shape[0]
+        cov = torch.empty((n, 9, 9), dtype=torch.float64, device=y.device)
+        spread = torch.empty(n, dtype=torch.float64, device=y.device)
+        self._stream()
+        self._check(self.lib.ucov_screener_covariance(
+            self.h, n, self._dev(y, torch.float32), self._dev(scale, torch.float64),
+            self._dev(out_mean, torch.float32), self._dev(out_std, torch.float32),
+            cov.data_ptr(), spread.data_ptr()))
+        return cov, spread

@@ -58,6 +58,8 @@ struct ucov_ctx {
   size_t h_stage_cap = 0;
   DevStatus *h_ds = nullptr;  // pinned host copy of the per-scene status
   size_t h_ds_cap = 0;
+  // learned screener
+  Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
 
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
@@ -406,7 +408,8 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
-                 &c->b_cam_scene, &c->b_tab, &c->b_ds};
+                 &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->f_hist, &c->f_ang, &c->f_covis,
+                 &c->mlp_ws, &c->mlp_grad};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   for (int k = 0; k < ucov_ctx::kWorkers; ++k) {
@@ -763,6 +766,115 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
     hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
     rep->ms_extract = 0.0f;
   }
+  return UCOV_OK;
+}
+
+// ---- learned screener -------------------------------------------------------
+
+int64_t ucov_mlp_param_count(void) { return mlp_param_count(); }
+
+int ucov_screener_features(ucov_ctx *c, const ucov_scene *scene, float *feat) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_scene(c, scene));
+  if (!feat) return c->fail(UCOV_EINVAL, "NULL output");
+  hipSetDevice(c->device);
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, single_bins(sc), nullptr, nullptr, false, nullptr));
+  const int64_t n = sc.n;
+  UCOV_TRY(ensure(c, c->f_hist, 4 * 8 * n));
+  UCOV_TRY(ensure(c, c->f_ang, 8 * n));
+  UCOV_TRY(ensure(c, c->f_covis, 4 * n));
+  launch_screener_features(sc, scene_work(c), as<int32_t>(c->f_hist), as<double>(c->f_ang),
+                           as<int32_t>(c->f_covis), feat, c->stream);
+  UCOV_TRY(check_hip(c, "screener features"));
+  return sync_status(c, nullptr, "screener features");
+}
+
+namespace {
+int check_mlp_args(ucov_ctx *c, const float *params, int64_t batch, const float *x,
+                   const float *mean, const float *stdv) {
+  if (!params || !x || batch < 1 || batch > ((int64_t)1 << 24))
+    return c->fail(UCOV_EINVAL, "bad MLP arguments (batch must be in [1, 2^24])");
+  if ((mean == nullptr) != (stdv == nullptr))
+    return c->fail(UCOV_EINVAL, "in_mean and in_std must both be given or both be NULL");
+  return UCOV_OK;
+}
+}  // namespace
+
+int ucov_mlp_forward(ucov_ctx *c, const float *params, int64_t batch, const float *x,
+                     const float *in_mean, const float *in_std, float *y) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_mlp_args(c, params, batch, x, in_mean, in_std));
+  if (!y) return c->fail(UCOV_EINVAL, "NULL output");
+  hipSetDevice(c->device);
+  UCOV_TRY(ensure(c, c->mlp_ws, mlp_workspace_bytes(batch)));
+  mlp_forward(params, batch, x, in_mean, in_std, y, c->mlp_ws.p, c->stream);
+  UCOV_TRY(check_hip(c, "MLP forward"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "MLP forward");
+  return UCOV_OK;
+}
+
+int ucov_mlp_gradient(ucov_ctx *c, const float *params, int64_t batch, const float *x,
+                      const float *in_mean, const float *in_std, const float *target,
+                      float *grad, float *loss) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_mlp_args(c, params, batch, x, in_mean, in_std));
+  if (!target || !grad) return c->fail(UCOV_EINVAL, "NULL target or gradient");
+  hipSetDevice(c->device);
+  UCOV_TRY(ensure(c, c->mlp_ws, mlp_workspace_bytes(batch)));
+  mlp_gradient(params, batch, x, in_mean, in_std, target, grad, loss, c->mlp_ws.p, c->stream);
+  UCOV_TRY(check_hip(c, "MLP gradient"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "MLP gradient");
+  return UCOV_OK;
+}
+
+int ucov_mlp_train(ucov_ctx *c, float *params, float *adam_m, float *adam_v, int64_t step0,
+                   float lr, int64_t batch, int64_t n_batches, const float *x,
+                   const float *in_mean, const float *in_std, const float *target,
+                   float *losses) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_mlp_args(c, params, batch, x, in_mean, in_std));
+  if (!adam_m || !adam_v || !target || n_batches < 1 || step0 < 1 || !(lr > 0.f))
+    return c->fail(UCOV_EINVAL, "bad training arguments");
+  hipSetDevice(c->device);
+  const int64_t P = mlp_param_count();
+  UCOV_TRY(ensure(c, c->mlp_ws, mlp_workspace_bytes(batch)));
+  UCOV_TRY(ensure(c, c->mlp_grad, 4 * P));
+  float *g = as<float>(c->mlp_grad);
+  for (int64_t i = 0; i < n_batches; ++i) {
+    mlp_gradient(params, batch, x + i * batch * UCOV_SCREENER_FEATURES, in_mean, in_std,
+                 target + i * batch * UCOV_SCREENER_OUTPUTS, g, losses ? losses + i : nullptr,
+                 c->mlp_ws.p, c->stream);
+    mlp_adam(P, params, g, adam_m, adam_v, lr, step0 + i, c->stream);
+  }
+  UCOV_TRY(check_hip(c, "MLP training"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "MLP training");
+  return UCOV_OK;
+}
+
+int ucov_screener_labels(ucov_ctx *c, int64_t n, const double *cov, const double *scale,
+                         const float *out_mean, const float *out_std, float *labels) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 1 || !cov || !scale || !out_mean || !out_std || !labels)
+    return c->fail(UCOV_EINVAL, "bad label arguments");
+  hipSetDevice(c->device);
+  clear_status(c);
+  launch_labels(n, cov, scale, out_mean, out_std, labels, c->ds, c->stream);
+  UCOV_TRY(check_hip(c, "screener labels"));
+  return sync_status(c, nullptr, "screener labels (covariance not positive definite)");
+}
+
+int ucov_screener_covariance(ucov_ctx *c, int64_t n, const float *y, const double *scale,
+                             const float *out_mean, const float *out_std, double *cov,
+                             double *spread) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 1 || !y || !scale || !out_mean || !out_std || (!cov && !spread))
+    return c->fail(UCOV_EINVAL, "bad screener covariance arguments");
+  hipSetDevice(c->device);
+  launch_predicted_cov(n, y, scale, out_mean, out_std, cov, spread, c->stream);
+  UCOV_TRY(check_hip(c, "screener covariance"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "screener covariance");
   return UCOV_OK;
 }
 

@@ -121,6 +121,28 @@ void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const 
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
                      int64_t n_nonzero, hipStream_t st);
 
+// ---- learned screener (screener_kernels.hip) -------------------------------
+// Per-camera features (n x 55 FP32) from the scene stage's data; hist (8 n),
+// ang (n) and covis (n) are scratch.
+void launch_screener_features(const SceneDev &sc, const SceneWork &w, int32_t *hist,
+                              double *ang, int32_t *covis, float *feat, hipStream_t st);
+int64_t mlp_param_count();
+size_t mlp_workspace_bytes(int64_t batch);
+// y = MLP((x - mean) / std); mean, std may be null
+void mlp_forward(const float *params, int64_t batch, const float *x, const float *mean,
+                 const float *stdv, float *y, void *ws, hipStream_t st);
+// gradient of the mean squared error against target (batch x 45); loss (device
+// scalar) may be null
+void mlp_gradient(const float *params, int64_t batch, const float *x, const float *mean,
+                  const float *stdv, const float *target, float *grad, float *loss, void *ws,
+                  hipStream_t st);
+void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr,
+              int64_t step, hipStream_t st);
+void launch_labels(int64_t n, const double *cov, const double *D, const float *mean,
+                   const float *stdv, float *lab, DevStatus *ds, hipStream_t st);
+void launch_predicted_cov(int64_t n, const float *y, const double *D, const float *mean,
+                          const float *stdv, double *cov, double *spread, hipStream_t st);
+
 // ---- dense stage (dense_kernels.hip) ---------------------------------------
 // Scaled positive-definite matrix a = S (Z + alpha QQ^T) S from a caller's Z.
 void launch_scale_dense(int64_t N, const double *z, int64_t ldz, const double *q,

@@ -1,0 +1,226 @@
+"""GPU parity of the learned screener against its FP64 oracle, and what the
+trained network gains over screening without it.
+
+Tolerances: features are computed in FP64 and stored in FP32 (1e-5); the
+network rounds every product operand to BF16 (8 significant bits, relative
+rounding 2^-9) and accumulates in FP32, so its outputs are held to 3e-2 in
+relative norm against the FP64 oracle.  Its gradients are compared with the
+oracle's BF16 mode (1e-2 per tensor), which takes the ReLU decisions in the
+same precision: a pre-activation near zero may switch sign between BF16 and
+FP64 operands and then reroutes that unit's gradient entirely.  Adam and the
+label transforms run in FP32/FP64 arithmetic (1e-5).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import screener as osc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ucov():
+    import torch
+    import paper_1808_02414_amd as u
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = u.Context(0)
+    yield u, ctx
+    ctx.close()
+
+
+def cuda(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(3, with_info=True),
+                                   lambda: sg.spiral_slab(4, n=20, m=600),
+                                   lambda: sg.spiral_slab(8, n=70, m=5000)])
+def test_features_match_oracle(ucov, maker):
+    u, ctx = ucov
+    s = maker()
+    print(f"features {s.name} n={s.n_cams}", flush=True)
+    got = ctx.screener_features(u.DeviceScene.from_scene(s)).cpu().numpy()
+    ref = osc.camera_features(s)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-6), np.abs(got - ref).max(axis=0)
+
+
+def mlp_case(seed, batch):
+    import torch
+    rng = np.random.default_rng(seed)
+    p = sg.mlp_init(seed)
+    p[np.arange(p.size) % 97 == 0] += 0.05  # some nonzero biases
+    mean = rng.normal(0, 1, 55)
+    std = rng.uniform(0.5, 2.0, 55)
+    x = mean + std * rng.normal(size=(batch, 55))
+    t = rng.normal(size=(batch, 45))
+    p32 = p.astype(np.float32)
+    xs = (x.astype(np.float32).astype(np.float64) - mean.astype(np.float32)) / std.astype(np.float32)
+    return (p32, mean.astype(np.float32), std.astype(np.float32), x.astype(np.float32),
+            t.astype(np.float32), xs)
+
+
+@pytest.mark.parametrize("batch", [1, 37, 300, 1024])
+def test_mlp_forward_matches_oracle(ucov, batch):
+    import torch
+    u, ctx = ucov
+    p, mean, std, x, t, xs = mlp_case(11, batch)
+    y = ctx.mlp_forward(cuda(p, torch.float32), cuda(x, torch.float32),
+                        cuda(mean, torch.float32), cuda(std, torch.float32)).cpu().numpy()
+    ref, _ = osc.mlp_forward(p.astype(np.float64), xs)
+    assert rel(y, ref) < 3e-2, rel(y, ref)
+
+
+@pytest.mark.parametrize("batch", [5, 300, 2048])
+def test_mlp_gradient_matches_oracle(ucov, batch):
+    """Against the oracle's BF16 mode, which takes every ReLU decision in the
+    kernel's precision (operands rounded to bfloat16); the loss also against
+    plain FP64."""
+    import torch
+    u, ctx = ucov
+    p, mean, std, x, t, xs = mlp_case(12, batch)
+    g, loss = ctx.mlp_gradient(cuda(p, torch.float32), cuda(x, torch.float32),
+                               cuda(t, torch.float32), cuda(mean, torch.float32),
+                               cuda(std, torch.float32))
+    g = g.cpu().numpy()
+    l64, _ = osc.mlp_backward(p.astype(np.float64), xs, t.astype(np.float64))
+    assert loss == pytest.approx(l64, rel=3e-2)
+    lref, gref = osc.mlp_backward(p.astype(np.float64), xs, t.astype(np.float64), bf16_ops=True)
+    assert loss == pytest.approx(lref, rel=1e-3)
+    for li, ((Wg, bg), (Wr, br)) in enumerate(zip(osc.split_params(g.astype(np.float64)),
+                                                  osc.split_params(gref))):
+        print(f"  layer {li}: dW {rel(Wg, Wr):.2e} db {rel(bg, br):.2e}")
+        assert rel(Wg, Wr) < 1e-2 and rel(bg, br) < 1e-2, li
+
+
+def test_train_step_is_gradient_plus_adam(ucov):
+    """One training step equals the library's gradient followed by the
+    oracle's Adam update (first step, zero moments), to FP32 rounding."""
+    import torch
+    u, ctx = ucov
+    p, mean, std, x, t, xs = mlp_case(13, 256)
+    args = (cuda(x, torch.float32), cuda(t, torch.float32), cuda(mean, torch.float32),
+            cuda(std, torch.float32))
+    g, _ = ctx.mlp_gradient(cuda(p, torch.float32), *args)
+    g = g.cpu().numpy().astype(np.float64)
+    pt = cuda(p, torch.float32)
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    ctx.mlp_train(pt, m, v, 1, 1e-3, 256, args[0], args[1], args[2], args[3])
+    ref, mref, vref = osc.adam_step(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    assert np.abs(pt.cpu().numpy() - ref).max() <= 1e-6
+    assert np.allclose(m.cpu().numpy(), mref, rtol=1e-5, atol=1e-12)
+    assert np.allclose(v.cpu().numpy(), vref, rtol=1e-5, atol=1e-16)
+
+
+def test_label_transforms_match_oracle(ucov):
+    import torch
+    u, ctx = ucov
+    from oracle.pipeline import camera_covariance as oracle_cov
+    S = oracle_cov(sg.tiny_circle(7))["blocks"]
+    D = np.sqrt(np.median(np.diagonal(S, axis1=1, axis2=2), axis=0))
+    raw = osc.log_cholesky(S, D)
+    mean, std = raw.mean(0).astype(np.float32), raw.std(0).astype(np.float32) + 0.1
+    lab = ctx.screener_labels(cuda(S, torch.float64), cuda(D, torch.float64),
+                              cuda(mean, torch.float32), cuda(std, torch.float32)).cpu().numpy()
+    ref = (raw - mean) / std
+    assert np.abs(lab - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    cov, spread = ctx.screener_covariance(cuda(lab, torch.float32), cuda(D, torch.float64),
+                                          cuda(mean, torch.float32), cuda(std, torch.float32))
+    back = osc.from_log_cholesky(mean + std * lab.astype(np.float64), D)
+    assert rel(cov.cpu().numpy(), back) < 1e-12
+    assert rel(cov.cpu().numpy(), S) < 1e-4
+    Dm = D[None, :, None] * D[None, None, :]
+    assert np.allclose(spread.cpu().numpy(), np.trace(S / Dm, axis1=1, axis2=2), rtol=1e-4)
+
+
+def block_rel_errors(got, ref):
+    return np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+
+
+def zii_from_features(F):
+    """Rebuild Z_ii from its 45 features (log10 diagonal, correlations)."""
+    n = F.shape[0]
+    Z = np.zeros((n, 9, 9))
+    k = 0
+    for a in range(9):
+        for b in range(a, 9):
+            Z[:, a, b] = F[:, k]
+            k += 1
+    d = 10.0 ** np.stack([Z[:, a, a] for a in range(9)], 1)
+    for a in range(9):
+        for b in range(a + 1, 9):
+            Z[:, a, b] = Z[:, b, a] = Z[:, a, b] * np.sqrt(d[:, a] * d[:, b])
+        Z[:, a, a] = d[:, a]
+    return Z
+
+
+def test_trained_screener_gains_over_screening_without_it(ucov):
+    """Train on about 20k cameras of the tiny, spiral and batch recipes with
+    the library's own kernels, then on held-out scenes compare the network
+    with what screening has without it: the training-mean covariance and the
+    block-diagonal estimate (Z_ii)^-1, which needs no inverse of Z but ignores
+    the other cameras' uncertainty.  The network must be about three times
+    more accurate than both (median relative Frobenius error per camera
+    block), rank cameras by uncertainty like the exact path (Spearman > 0.9),
+    and answer faster than the exact path."""
+    import torch
+    from paper_1808_02414_amd import screener as scr
+    u, ctx = ucov
+    t0 = time.time()
+    train = (sg.batch_scenes(seed=10000, count=110, lo=20, hi=300)
+             + [sg.tiny_circle(10000 + k) for k in range(300)]
+             + [sg.spiral_slab(10500 + k) for k in range(6)])
+    held = (sg.batch_scenes(seed=90000, count=25, lo=20, hi=300)
+            + [sg.tiny_circle(90000 + k) for k in range(40)] + [sg.spiral_slab(90500)])
+    print(f"  scenes generated in {time.time() - t0:.1f}s", flush=True)
+    F, S = scr.training_set(ctx, train)
+    print(f"  training cameras {F.shape[0]}", flush=True)
+    model, hist = scr.fit(ctx, F, S, sg.mlp_init(1), epochs=40, batch=512, seed=1)
+    print(f"  loss first {hist[0]:.4f} last {hist[-1]:.4f}", flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+
+    Fh, Sh = scr.training_set(ctx, held)
+    pred, spread = model.predict(ctx, Fh)
+    ref = Sh.cpu().numpy()
+    err_net = block_rel_errors(pred.cpu().numpy(), ref)
+    # network output 0 is the training mean of every standardised parameter
+    zero = torch.zeros((Fh.shape[0], 45), dtype=torch.float32, device="cuda")
+    mcov, _ = ctx.screener_covariance(zero, model.scale, model.out_mean, model.out_std)
+    err_mean = block_rel_errors(mcov.cpu().numpy(), ref)
+    err_zii = block_rel_errors(np.linalg.inv(zii_from_features(Fh.cpu().numpy().astype(np.float64))), ref)
+    med = {k: float(np.median(e)) for k, e in (("net", err_net), ("mean", err_mean), ("zii", err_zii))}
+    print(f"  held-out cameras {ref.shape[0]}: median relative error {med}", flush=True)
+
+    D = model.scale.cpu().numpy()
+    true_spread = np.trace(ref / (D[None, :, None] * D[None, None, :]), axis1=1, axis2=2)
+    from scipy.stats import spearmanr
+    rho = spearmanr(spread.cpu().numpy(), true_spread).correlation
+    print(f"  spread rank correlation {rho:.3f}", flush=True)
+
+    # time: screening (features + network) against the exact path, per camera
+    dev_held = [u.DeviceScene.from_scene(s) for s in held]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d in dev_held:
+        model.predict(ctx, ctx.screener_features(d))
+    torch.cuda.synchronize()
+    t_screen = time.perf_counter() - t
+    t = time.perf_counter()
+    for d in dev_held:
+        ctx.camera_covariance(d)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t
+    print(f"  screening {ref.shape[0] / t_screen:.0f} cams/s, exact {ref.shape[0] / t_exact:.0f} cams/s",
+          flush=True)
+
+    assert med["net"] < 0.35 * min(med["mean"], med["zii"]), med
+    assert rho > 0.9
+    assert t_screen < t_exact

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "ucov.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(ucov_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char \*)\s*(ucov_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_binding_exports():

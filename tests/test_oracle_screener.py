@@ -127,3 +127,48 @@ def test_adam_first_steps_closed_form():
     # second step with the same gradient: again the moments are g and g^2
     p2, _, _ = screener.adam_step(p1, g, m, v, 2, 0.01)
     assert np.allclose(p2, p1 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(3)
+    a = np.concatenate([rng.normal(size=1000) * 10.0 ** rng.integers(-20, 20, 1000),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.0 - 2.0 ** -8, 0.0, 1.0]])
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(screener.bf16(a), ref)
+    assert screener.bf16([1.0 + 2.0 ** -8])[0] == 1.0          # tie to even (down)
+    assert screener.bf16([1.0 + 3 * 2.0 ** -8])[0] == 1.0 + 2.0 ** -6  # tie to even (up)
+
+
+def test_bf16_mode_exact_on_representable_networks():
+    """Weights in {-1, 0, 1} with one nonzero per row after the first layer,
+    inputs in {0, 1}, integer biases: every value stays a small integer, which
+    bfloat16 holds exactly, so the BF16 mode must equal the FP64 one."""
+    rng = np.random.default_rng(8)
+    p = np.zeros(screener.param_count())
+    for li, (W, b) in enumerate(screener.split_params(p)):
+        if li == 0:
+            W[...] = rng.integers(-1, 2, W.shape)
+        else:
+            W[np.arange(W.shape[0]), rng.integers(0, W.shape[1], W.shape[0])] = rng.choice([-1.0, 1.0], W.shape[0])
+        b[...] = rng.integers(-2, 3, b.shape)
+    x = rng.integers(0, 2, (16, 55)).astype(np.float64)
+    y64, _ = screener.mlp_forward(p, x)
+    y16, _ = screener.mlp_forward(p, x, bf16_ops=True)
+    assert np.abs(y64).max() < 256 and np.array_equal(y16, y64)
+
+
+def test_bf16_mode_gradient_within_rounding_when_no_relu_can_flip():
+    """All weights and inputs positive: every pre-activation is positive, no
+    ReLU decision can change, and the BF16-mode gradient differs from the
+    pinned FP64 gradient only by operand rounding."""
+    p = np.abs(sg.mlp_init(7)) * 0.3
+    rng = np.random.default_rng(4)
+    x, t = np.abs(rng.normal(size=(64, 55))), rng.normal(size=(64, 45))
+    y64, _ = screener.mlp_forward(p, x)
+    y16, _ = screener.mlp_forward(p, x, bf16_ops=True)
+    assert np.linalg.norm(y16 - y64) / np.linalg.norm(y64) < 1e-2
+    _, g64 = screener.mlp_backward(p, x, t)
+    _, g16 = screener.mlp_backward(p, x, t, bf16_ops=True)
+    for (W1, b1), (W2, b2) in zip(screener.split_params(g16), screener.split_params(g64)):
+        assert np.linalg.norm(W1 - W2) / np.linalg.norm(W2) < 2e-2
+        assert np.linalg.norm(b1 - b2) / np.linalg.norm(b2) < 2e-2
