@@ -139,8 +139,8 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
  * scene s - 1, each as in ucov_camera_covariance.
  * alphas: HOST array receiving the gauge weight of every scene, or NULL.
  * opt->precision must be UCOV_FP64 (else UCOV_EINVAL).
- * rep: ms_inverse covers the dense stage of all scenes (factorisation,
- * inversion and block extraction overlap across scenes), ms_extract is 0,
+ * rep: ms_inverse covers the dense stage of all scenes (identity padding,
+ * the batched factorisation and inversion, block extraction), ms_extract is 0,
  * alpha is scene 0's; on failure bad_scene names the scene and bad_index the
  * observation, point or camera within it.
  * Limits: at most 2^27 cameras and 2^31 - 1 points and observations in total. */

@@ -21,6 +21,9 @@
 // Newton-Schulz steps with FP64 residuals then refine (see ucov_api.hip).
 #include <algorithm>
 
+#include <string>
+#include <vector>
+
 #include "ucov_internal.h"
 #include "../../include/ucov.h"
 
@@ -239,7 +242,7 @@ __device__ inline float rsqrt_nr(float x) {
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_leaf_mfma(T *A, int64_t lda, int64_t o, DevStatus *ds) {
+__device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatus *ds) {
   typedef Mfma<T> MF;
   typedef typename MF::vec2 V2;
   constexpr int LD = NB + kLP;
@@ -420,6 +423,52 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(T *A, int64_t lda, int64_t o,
   }
 }
 
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_leaf_mfma(T *A, int64_t lda, int64_t o, DevStatus *ds) {
+  leaf_body<T, NB>(A, lda, o, ds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms for many independent matrices: one launch serves one node of
+// the recursion for every matrix that reaches it, blockIdx.z selecting the
+// matrix's arguments from a device table (workgroups beyond a smaller
+// matrix's tiles return at once).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LeafArg {
+  T *A;
+  int64_t lda, o;
+  DevStatus *ds;
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_leaf_mfma_b(const LeafArg<T> *tab) {
+  const LeafArg<T> a = tab[blockIdx.x];
+  leaf_body<T, NB>(a.A, a.lda, a.o, a.ds);
+}
+
+template <typename T, bool AT, bool BT, bool LOWER>
+__global__ __launch_bounds__(256) void k_gemm64_b(const GemmArgs<T> *tab) {
+  const GemmArgs<T> g = tab[blockIdx.z];
+  if ((int64_t)blockIdx.x * 64 >= g.M || (int64_t)blockIdx.y * 64 >= g.N) return;
+  gemm_tile<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm64_pair_b(const GemmArgs<T> *stab,
+                                                       const GemmArgs<T> *ttab) {
+  const GemmArgs<T> sg = stab[blockIdx.z];
+  const int ms = (int)(sg.M / 64), nblk_s = ms * ms, b = blockIdx.x;
+  if (b < nblk_s) {
+    gemm_tile<T, false, true, true>(sg, b % ms, b / ms);
+  } else {
+    const GemmArgs<T> tg = ttab[blockIdx.z];
+    const int mt = (int)(tg.M / 64), bb = b - nblk_s;
+    if (bb >= mt * (int)(tg.N / 64)) return;
+    gemm_tile<T, false, false, false>(tg, bb % mt, bb / mt);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // elementwise helpers
 // ---------------------------------------------------------------------------
@@ -562,6 +611,68 @@ __global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const dou
   cov[81 * i + t] = s[r] * xs * s[c] - g / (*alpha);
 }
 
+// Every scene of a concatenation: grid (column c, scene s); rows r >= max(c,
+// N_s) of column c of scene s's padded matrix set to the identity.
+__global__ void k_pad_identity_scenes(const int32_t *cam_off, const int64_t *a_off,
+                                      const int64_t *a_ld, double *amat) {
+  const int s = blockIdx.y;
+  const int64_t N = 9 * (int64_t)(cam_off[s + 1] - cam_off[s]), Np = a_ld[s];
+  const int64_t c = blockIdx.x;
+  if (c >= Np) return;
+  double *a = amat + a_off[s];
+  const int64_t r0 = c > N ? c : N;
+  for (int64_t r = r0 + threadIdx.x; r < Np; r += blockDim.x) a[r + c * Np] = (r == c) ? 1.0 : 0.0;
+}
+
+// Blocks of every camera of a concatenation (one workgroup per camera): as
+// k_extract with the scene's matrix, scaling, basis rows and gauge weight.
+__global__ __launch_bounds__(256) void k_extract_scenes(const int32_t *cam_scene,
+                                                       const int32_t *cam_off,
+                                                       const int64_t *a_off, const int64_t *a_ld,
+                                                       const double *amat, int64_t Ntot,
+                                                       const double *s, const double *q,
+                                                       const double *alpha, double *cov) {
+  const int64_t gi = blockIdx.x;
+  const int sc = cam_scene[gi];
+  const int64_t r0 = 9 * (int64_t)cam_off[sc];
+  const int64_t N = 9 * (int64_t)(cam_off[sc + 1] - cam_off[sc]);
+  const int64_t ld = a_ld[sc];
+  const double *linv = amat + a_off[sc];
+  const int64_t c0 = 9 * gi - r0;
+  double acc[45];
+#pragma unroll
+  for (int k = 0; k < 45; ++k) acc[k] = 0.0;
+  for (int64_t r = c0 + threadIdx.x; r < N; r += blockDim.x) {
+    double v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = r >= c0 + c ? linv[r + (c0 + c) * ld] : 0.0;
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int b = a; b < 9; ++b) acc[idx++] += v[a] * v[b];
+  }
+  __shared__ double part[4][45];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 45; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) part[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 81) {
+    const int a0 = threadIdx.x / 9, b0 = threadIdx.x % 9;
+    const int a = a0 < b0 ? a0 : b0, b = a0 < b0 ? b0 : a0;
+    const int idx = a * 9 - a * (a - 1) / 2 + (b - a);
+    const double x = part[0][idx] + part[1][idx] + part[2][idx] + part[3][idx];
+    const int64_t ra = 9 * gi + a0, rb = 9 * gi + b0;  // global rows of s and q
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) g += q[k * Ntot + ra] * q[k * Ntot + rb];
+    cov[81 * gi + threadIdx.x] = s[ra] * x * s[rb] - g / alpha[sc];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -625,6 +736,316 @@ void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hip
   gemm<T, false, false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, mone, zero, kLeM, st);
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched inverse Cholesky factors of many SPD matrices of different sizes.
+//
+// Every matrix is embedded in the leading block of one virtual matrix of the
+// largest size P, whose recursion tree (the same splits as recurse()) is
+// walked once.  A node (o, n) involves the matrices that extend past o; one
+// whose extent ends inside the left half only takes part in the left
+// subtree (its off-diagonal and trailing blocks would be zero and identity).
+// Each matrix keeps its own scratch: at a node with a trailing extent m the
+// products T (m x n1) and T2 (m x n1) sit at its current scratch offset, the
+// right subtree continues past T2, the left one at the same offset.
+// ---------------------------------------------------------------------------
+namespace {
+
+enum PlanKind { kPlanLeaf64 = 0, kPlanLeaf128 = 1, kPlanGemmT = 2, kPlanPair = 3, kPlanFinal = 4 };
+
+struct PlanLaunch {
+  int kind;
+  int64_t first, second;  // table offsets (pair: Schur and T2 entries)
+  int count;
+  unsigned gx, gy;
+};
+
+struct WalkMat {
+  int64_t np;
+  int64_t need;  // scratch high-water mark (elements)
+};
+
+template <typename T>
+struct PlanBuilder {
+  const SpdMat *mats;
+  std::vector<GemmArgs<T>> gemms;
+  std::vector<int> gemm_owner;  // matrix of each product (for the bounds check)
+  std::vector<int> gemm_bt;     // 1 when B is used transposed
+  std::vector<LeafArg<T>> leaves;
+  std::vector<int> leaf_owner, leaf_nb;
+  std::vector<PlanLaunch> launches;
+  std::vector<int64_t> need;
+
+  void add(const GemmArgs<T> &g, int owner, int bt) {
+    gemms.push_back(g);
+    gemm_owner.push_back(owner);
+    gemm_bt.push_back(bt);
+  }
+
+  void walk(int64_t o, int64_t n, const std::vector<int> &act, const std::vector<int64_t> &off) {
+    if (act.empty()) return;
+    if (n <= 128) {
+      for (int nb : {128, 64}) {
+        PlanLaunch L{nb == 128 ? kPlanLeaf128 : kPlanLeaf64, (int64_t)leaves.size(), 0, 0, 0, 1};
+        for (int s : act) {
+          const int64_t e = std::min(n, mats[s].np - o);
+          if (e != nb) continue;
+          leaves.push_back(LeafArg<T>{static_cast<T *>(mats[s].A), mats[s].lda, o, mats[s].ds});
+          leaf_owner.push_back(s);
+          leaf_nb.push_back(nb);
+          ++L.count;
+        }
+        if (L.count) {
+          L.gx = (unsigned)L.count;
+          launches.push_back(L);
+        }
+      }
+      return;
+    }
+    const int64_t n1 = (n / 64 / 2) * 64, n2 = n - n1;
+    walk(o, n1, act, off);
+    std::vector<int> F;
+    std::vector<int64_t> m, offR;
+    for (size_t q = 0; q < act.size(); ++q) {
+      const int s = act[q];
+      const int64_t e = std::min(n, mats[s].np - o);
+      if (e <= n1) continue;
+      F.push_back(s);
+      m.push_back(e - n1);
+      offR.push_back(off[q] + (e - n1) * n1);
+      need[s] = std::max(need[s], off[q] + 2 * (e - n1) * n1);
+    }
+    if (F.empty()) return;
+    const T one = T(1), zero = T(0), mone = T(-1);
+    int64_t mmax = 0;
+    for (int64_t x : m) mmax = std::max(mmax, x);
+    const unsigned mt = (unsigned)(mmax / 64), nt1 = (unsigned)(n1 / 64);
+    // T = A21 L11^-T
+    PlanLaunch LT{kPlanGemmT, (int64_t)gemms.size(), 0, (int)F.size(), mt, nt1};
+    for (size_t q = 0; q < F.size(); ++q) {
+      const SpdMat &M = mats[F[q]];
+      T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
+      T *Tm = T2 + m[q] * n1;
+      add(make_args<T>(m[q], n1, n1, A + (o + n1) + o * M.lda, M.lda, A + o + o * M.lda, M.lda,
+                       Tm, m[q], one, zero, kLeN), F[q], 1);
+    }
+    launches.push_back(LT);
+    // A22 -= T T^T  and  T2 = T L11^-1
+    PlanLaunch LP{kPlanPair, (int64_t)gemms.size(), (int64_t)(gemms.size() + F.size()),
+                  (int)F.size(), mt * mt + mt * nt1, 1};
+    for (size_t q = 0; q < F.size(); ++q) {
+      const SpdMat &M = mats[F[q]];
+      T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
+      T *Tm = T2 + m[q] * n1;
+      add(make_args<T>(m[q], m[q], n1, Tm, m[q], Tm, m[q], A + (o + n1) + (o + n1) * M.lda,
+                       M.lda, mone, one, kFull), F[q], 1);
+    }
+    for (size_t q = 0; q < F.size(); ++q) {
+      const SpdMat &M = mats[F[q]];
+      T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
+      T *Tm = T2 + m[q] * n1;
+      add(make_args<T>(m[q], n1, n1, Tm, m[q], A + o + o * M.lda, M.lda, T2, m[q], one, zero,
+                       kGeN), F[q], 0);
+    }
+    launches.push_back(LP);
+    walk(o + n1, n2, F, offR);
+    // A21 = -L22^-1 T2
+    PlanLaunch LF{kPlanFinal, (int64_t)gemms.size(), 0, (int)F.size(), mt, nt1};
+    for (size_t q = 0; q < F.size(); ++q) {
+      const SpdMat &M = mats[F[q]];
+      T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
+      add(make_args<T>(m[q], n1, m[q], A + (o + n1) + (o + n1) * M.lda, M.lda, T2, m[q],
+                       A + (o + n1) + o * M.lda, M.lda, mone, zero, kLeM), F[q], 0);
+    }
+    launches.push_back(LF);
+  }
+};
+
+// Every product and leaf of a plan must stay inside its own matrix (lda x np
+// elements from A) or its own scratch (need elements from tmp); the kernels
+// assume it, so a plan that breaks it is refused.
+template <typename T>
+bool plan_in_bounds(const PlanBuilder<T> &b, const SpdMat *mats, std::string *why) {
+  auto inside = [&](const T *p, int64_t span, int s) {
+    const T *A = static_cast<const T *>(mats[s].A), *tmp = static_cast<const T *>(mats[s].tmp);
+    if (p >= A && p + span <= A + mats[s].lda * mats[s].np) return true;
+    return tmp && p >= tmp && p + span <= tmp + b.need[s];
+  };
+  for (size_t e = 0; e < b.gemms.size(); ++e) {
+    const GemmArgs<T> &g = b.gemms[e];
+    const int s = b.gemm_owner[e];
+    const bool bt = b.gemm_bt[e] != 0;
+    const bool ok = g.M > 0 && g.N > 0 && g.K > 0 && g.M % 64 == 0 && g.N % 64 == 0 &&
+                    g.K % 64 == 0 && g.lda >= g.M && g.ldc >= g.M &&
+                    g.ldb >= (bt ? g.N : g.K) &&
+                    inside(g.A, (g.K - 1) * g.lda + g.M, s) &&
+                    inside(g.B, bt ? (g.K - 1) * g.ldb + g.N : (g.N - 1) * g.ldb + g.K, s) &&
+                    inside(g.C, (g.N - 1) * g.ldc + g.M, s);
+    if (!ok) {
+      if (why) *why = "product " + std::to_string(e) + " of matrix " + std::to_string(s);
+      return false;
+    }
+  }
+  for (size_t e = 0; e < b.leaves.size(); ++e) {
+    const LeafArg<T> &l = b.leaves[e];
+    const int s = b.leaf_owner[e], nb = b.leaf_nb[e];
+    if (l.o < 0 || l.o + nb > mats[s].np || !inside(l.A + l.o + l.o * l.lda, (nb - 1) * l.lda + nb, s)) {
+      if (why) *why = "leaf " + std::to_string(e) + " of matrix " + std::to_string(s);
+      return false;
+    }
+  }
+  return true;
+}
+
+template <typename T>
+PlanBuilder<T> make_plan(const SpdMat *mats, int count) {
+  int64_t P = 0;
+  for (int s = 0; s < count; ++s) P = std::max(P, mats[s].np);
+  PlanBuilder<T> b;
+  b.mats = mats;
+  b.need.assign(count, 0);
+  std::vector<int> act(count);
+  for (int s = 0; s < count; ++s) act[s] = s;
+  b.walk(0, P, act, std::vector<int64_t>(count, 0));
+  return b;
+}
+
+}  // namespace
+
+int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t *n_launches) {
+  // disjoint fake address ranges: matrix s at slot 2s, its scratch at 2s + 1
+  std::vector<int64_t> need(count);
+  spd_batch_scratch(np, count, need.data());
+  std::vector<SpdMat> mats(count);
+  uintptr_t base = 1 << 20;
+  for (int s = 0; s < count; ++s) {
+    const uintptr_t a = base;
+    base += (uintptr_t)(np[s] * np[s] + 64) * 8;
+    const uintptr_t t = base;
+    base += (uintptr_t)(need[s] + 64) * 8;
+    mats[s] = SpdMat{reinterpret_cast<void *>(a), np[s], np[s], reinterpret_cast<void *>(t), nullptr};
+  }
+  PlanBuilder<double> b = make_plan<double>(mats.data(), count);
+  if (n_launches) *n_launches = (int64_t)b.launches.size();
+  // every column block of every matrix must be factored by exactly one leaf
+  std::vector<std::vector<int>> covered(count);
+  for (int s = 0; s < count; ++s) covered[s].assign(np[s] / 64, 0);
+  for (size_t e = 0; e < b.leaves.size(); ++e) {
+    const int s = b.leaf_owner[e];
+    for (int k = 0; k < b.leaf_nb[e] / 64; ++k) covered[s][b.leaves[e].o / 64 + k]++;
+  }
+  for (int s = 0; s < count; ++s)
+    for (int c : covered[s])
+      if (c != 1) {
+        if (why) *why = "matrix " + std::to_string(s) + " column blocks not covered exactly once";
+        return -1;
+      }
+  return plan_in_bounds(b, mats.data(), why) ? 0 : -1;
+}
+
+namespace {
+}  // namespace
+
+struct SpdPlan {
+  std::vector<SpdMat> key;
+  std::vector<GemmArgs<double>> gemms;
+  std::vector<LeafArg<double>> leaves;
+  std::vector<PlanLaunch> launches;
+  void *dev = nullptr;
+  size_t dev_cap = 0;
+};
+
+void spd_batch_scratch(const int64_t *np, int count, int64_t *out) {
+  std::vector<SpdMat> mats(count);
+  int64_t P = 0;
+  for (int s = 0; s < count; ++s) {
+    mats[s] = SpdMat{nullptr, np[s], np[s], nullptr, nullptr};
+    P = std::max(P, np[s]);
+  }
+  (void)P;
+  PlanBuilder<double> b = make_plan<double>(mats.data(), count);
+  for (int s = 0; s < count; ++s) out[s] = b.need[s];
+}
+
+SpdPlan *spd_plan_create() { return new SpdPlan(); }
+
+void spd_plan_destroy(SpdPlan *p) {
+  if (!p) return;
+  if (p->dev) hipFree(p->dev);
+  delete p;
+}
+
+static bool same_mats(const std::vector<SpdMat> &a, const SpdMat *b, int count) {
+  if ((int)a.size() != count) return false;
+  for (int s = 0; s < count; ++s)
+    if (a[s].A != b[s].A || a[s].lda != b[s].lda || a[s].np != b[s].np || a[s].tmp != b[s].tmp ||
+        a[s].ds != b[s].ds)
+      return false;
+  return true;
+}
+
+int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st) {
+  if (same_mats(p->key, mats, count)) return 0;
+  PlanBuilder<double> b = make_plan<double>(mats, count);
+  if (!plan_in_bounds(b, mats, nullptr)) return -2;
+  const size_t bytes = sizeof(GemmArgs<double>) * b.gemms.size() +
+                       sizeof(LeafArg<double>) * b.leaves.size() + 64;
+  if (p->dev_cap < bytes) {
+    if (p->dev) hipFree(p->dev);
+    p->dev = nullptr;
+    p->dev_cap = 0;
+    if (hipMalloc(&p->dev, bytes) != hipSuccess) return -1;
+    p->dev_cap = bytes;
+  }
+  p->gemms.swap(b.gemms);
+  p->leaves.swap(b.leaves);
+  p->launches.swap(b.launches);
+  char *d = static_cast<char *>(p->dev);
+  const size_t gb = sizeof(GemmArgs<double>) * p->gemms.size();
+  if (gb && hipMemcpyAsync(d, p->gemms.data(), gb, hipMemcpyHostToDevice, st) != hipSuccess)
+    return -1;
+  if (!p->leaves.empty() &&
+      hipMemcpyAsync(d + gb, p->leaves.data(), sizeof(LeafArg<double>) * p->leaves.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  p->key.assign(mats, mats + count);
+  return 0;
+}
+
+void spd_plan_run(const SpdPlan *p, hipStream_t st) {
+  const GemmArgs<double> *g = static_cast<const GemmArgs<double> *>(p->dev);
+  const LeafArg<double> *lv =
+      reinterpret_cast<const LeafArg<double> *>(static_cast<const char *>(p->dev) +
+                                                sizeof(GemmArgs<double>) * p->gemms.size());
+  for (const PlanLaunch &L : p->launches) {
+    switch (L.kind) {
+      case kPlanLeaf64:
+        hipLaunchKernelGGL((k_leaf_mfma_b<double, 64>), dim3(L.gx), dim3(256), 0, st, lv + L.first);
+        break;
+      case kPlanLeaf128:
+        hipLaunchKernelGGL((k_leaf_mfma_b<double, 128>), dim3(L.gx), dim3(256), 0, st,
+                           lv + L.first);
+        break;
+      case kPlanGemmT:
+        hipLaunchKernelGGL((k_gemm64_b<double, false, true, false>), dim3(L.gx, L.gy, L.count),
+                           dim3(256), 0, st, g + L.first);
+        break;
+      case kPlanPair:
+        hipLaunchKernelGGL((k_gemm64_pair_b<double>), dim3(L.gx, 1, L.count), dim3(256), 0, st,
+                           g + L.first, g + L.second);
+        break;
+      case kPlanFinal:
+        hipLaunchKernelGGL((k_gemm64_b<double, false, false, false>), dim3(L.gx, L.gy, L.count),
+                           dim3(256), 0, st, g + L.first);
+        break;
+    }
+  }
+}
+
+namespace {
+
 inline dim3 grid2(int64_t n) { return dim3((unsigned)((n + 255) / 256), (unsigned)n); }
 
 }  // namespace
@@ -645,6 +1066,21 @@ int64_t spd_lower_inverse_scratch(int64_t Np) { return recurse_scratch(Np); }
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st) {
   recurse<double>(a, lda, 0, Np, tmp, ds, st);
+}
+
+void launch_pad_identity_scenes(int n_scenes, int64_t max_np, const int32_t *cam_off,
+                                const int64_t *a_off, const int64_t *a_ld, double *amat,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_pad_identity_scenes, dim3((unsigned)max_np, (unsigned)n_scenes), dim3(64),
+                     0, st, cam_off, a_off, a_ld, amat);
+}
+
+void launch_extract_scenes(int64_t n_cams, const int32_t *cam_scene, const int32_t *cam_off,
+                           const int64_t *a_off, const int64_t *a_ld, const double *amat,
+                           const double *s, const double *q, const double *alpha, double *cov,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_extract_scenes, dim3((unsigned)n_cams), dim3(256), 0, st, cam_scene,
+                     cam_off, a_off, a_ld, amat, 9 * n_cams, s, q, alpha, cov);
 }
 
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,

@@ -47,13 +47,9 @@ struct ucov_ctx {
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount;
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
-  // batched calls: the concatenated scenes, their tables, per-scene status and
-  // the worker streams that run the dense stages of the scenes side by side
-  static constexpr int kWorkers = 8;
-  hipStream_t workers[kWorkers] = {};
-  hipEvent_t wev[kWorkers] = {};
-  Buf b_cams, b_pts, b_info, b_oc, b_op, b_cam_scene, b_tab, b_ds;
-  Buf wtmp[kWorkers];
+  // batched calls: the concatenated scenes, their tables and per-scene status
+  Buf b_cams, b_pts, b_info, b_oc, b_op, b_cam_scene, b_tab, b_ds, b_scratch;
+  SpdPlan *plan = nullptr;  // batched inverse plan, kept while the batch is unchanged
   void *h_stage = nullptr;  // pinned host staging of the scene tables
   size_t h_stage_cap = 0;
   DevStatus *h_ds = nullptr;  // pinned host copy of the per-scene status
@@ -375,15 +371,6 @@ int ucov_create(ucov_ctx **ctx, int device) {
     return UCOV_ENOMEM;
   }
   for (auto &e : c->ev) hipEventCreate(&e);
-  for (int k = 0; k < ucov_ctx::kWorkers; ++k) {
-    // default priority, non-blocking with respect to the null stream
-    if (hipStreamCreateWithFlags(&c->workers[k], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->wev[k], hipEventDisableTiming) != hipSuccess) {
-      hipGetLastError();
-      ucov_destroy(c);
-      return UCOV_EDEVICE;
-    }
-  }
   if (ensure(c, c->alpha, 8) != UCOV_OK) {
     ucov_destroy(c);
     return UCOV_ENOMEM;
@@ -408,17 +395,13 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
-                 &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->f_hist, &c->f_ang, &c->f_covis,
+                 &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
                  &c->mlp_ws, &c->mlp_grad};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
-  for (int k = 0; k < ucov_ctx::kWorkers; ++k) {
-    if (c->wtmp[k].p) hipFree(c->wtmp[k].p);
-    if (c->workers[k]) hipStreamDestroy(c->workers[k]);
-    if (c->wev[k]) hipEventDestroy(c->wev[k]);
-  }
   if (c->h_stage) hipHostFree(c->h_stage);
   if (c->h_ds) hipHostFree(c->h_ds);
+  spd_plan_destroy(c->plan);
   if (c->ds) hipFree(c->ds);
   if (c->ds_host) hipHostFree(c->ds_host);
   if (c->i64_host) hipHostFree(c->i64_host);
@@ -536,9 +519,9 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
 
 // Several independent scenes in one call.  The scene stage runs once over the
 // concatenation (one launch per kernel for all scenes: camera-pair bins, the
-// gauge basis and the dense matrices are kept per scene); the dense inverse of
-// each scene then runs on one of the worker streams, largest scenes first, so
-// that small inverses fill the GPU beside the large ones.
+// gauge basis and the dense matrices are kept per scene); the dense inverses
+// of all scenes then run as one batched recursion whose every launch serves a
+// node of the recursion for all the scenes that reach it.
 int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_scene *scenes,
                                    const ucov_options *opt, double *cov_out, double *alphas,
                                    ucov_report *rep) {
@@ -695,41 +678,36 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
     if (rc != UCOV_OK) return localize(rc);
   }
 
-  // dense stage: longest-processing-time assignment of scenes to workers
-  const int K = std::min(S, (int)ucov_ctx::kWorkers);
-  std::vector<int> order(S);
-  for (int s = 0; s < S; ++s) order[s] = s;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return a_ld[x] > a_ld[y]; });
-  std::vector<double> load(K, 0.0);
-  std::vector<std::vector<int>> plan(K);
-  std::vector<int64_t> scratch(K, 1);
-  for (int s : order) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    const double np = (double)a_ld[s];
-    load[k] += np * np * np + 2.0e6;  // flops plus a latency term per scene
-    plan[k].push_back(s);
-    scratch[k] = std::max(scratch[k], spd_lower_inverse_scratch(a_ld[s]));
-  }
-  for (int k = 0; k < K; ++k) UCOV_TRY(ensure(c, c->wtmp[k], 8 * scratch[k]));
+  // dense stage: one batched recursion over all scenes (each launch serves a
+  // node of the recursion for every scene that reaches it)
+  std::vector<int64_t> need(S);
+  spd_batch_scratch(a_ld.data(), S, need.data());
+  std::vector<int64_t> tmp_off(S + 1, 0);
+  for (int s = 0; s < S; ++s) tmp_off[s + 1] = tmp_off[s] + round_up(std::max<int64_t>(need[s], 1), 32);
+  UCOV_TRY(ensure(c, c->b_scratch, 8 * (size_t)tmp_off[S]));
   DevStatus *bds = as<DevStatus>(c->b_ds);
+  double *amat = as<double>(c->amat);
+  std::vector<SpdMat> mats(S);
+  int64_t max_np = 0;
+  for (int s = 0; s < S; ++s) {
+    mats[s] = SpdMat{amat + a_off[s], a_ld[s], a_ld[s], as<double>(c->b_scratch) + tmp_off[s], bds + s};
+    max_np = std::max(max_np, a_ld[s]);
+  }
+  if (!c->plan) c->plan = spd_plan_create();
+  {
+    const int rc = spd_plan_build(c->plan, mats.data(), S, st);
+    if (rc == -2) return c->fail(UCOV_EDEVICE, "internal error: batched inverse plan out of bounds");
+    if (rc != 0) {
+      hipGetLastError();
+      return c->fail(UCOV_ENOMEM, "batched inverse plan tables");
+    }
+  }
   fill_i32(reinterpret_cast<int32_t *>(bds), 0, 2 * (int64_t)S, st);
   hipEventRecord(c->ev[3], st);
-  double *amat = as<double>(c->amat);
-  for (int k = 0; k < K; ++k) {
-    hipStream_t ws = c->workers[k];
-    hipStreamWaitEvent(ws, c->ev[3], 0);
-    for (int s : plan[k]) {
-      const int64_t Ns = 9 * (int64_t)(cam_off[s + 1] - cam_off[s]), Np = a_ld[s];
-      double *A = amat + a_off[s];
-      const int64_t r0 = 9 * (int64_t)cam_off[s];
-      launch_pad_identity(Ns, Np, A, Np, ws);
-      spd_lower_inverse_fp64(A, Np, Np, as<double>(c->wtmp[k]), bds + s, ws);
-      launch_extract(Ns, A, Np, w.s + r0, w.q + r0, N, w.alpha + s, cov_out + 81 * cam_off[s],
-                     ws);
-    }
-    hipEventRecord(c->wev[k], ws);
-    hipStreamWaitEvent(st, c->wev[k], 0);
-  }
+  launch_pad_identity_scenes(S, max_np, sc.cam_off, sc.a_off, sc.a_ld, amat, st);
+  spd_plan_run(c->plan, st);
+  launch_extract_scenes(n, sc.cam_scene, sc.cam_off, sc.a_off, sc.a_ld, amat, w.s, w.q, w.alpha,
+                        cov_out, st);
   hipEventRecord(c->ev[4], st);
   UCOV_TRY(check_hip(c, "batched dense kernels"));
   // per-scene status of the dense stage

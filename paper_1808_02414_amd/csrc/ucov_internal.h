@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include <cstdint>
 
 namespace ucov {
@@ -153,8 +155,37 @@ void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStrea
 // In-place L^-1 of the Cholesky factor of the lower triangle of a (Np x Np),
 // using tmp (spd_lower_inverse_scratch(Np) doubles) as workspace.
 int64_t spd_lower_inverse_scratch(int64_t Np);
+// Batched form for many matrices of different padded sizes np (multiples of
+// 64): each matrix's lower triangle is replaced by its inverse Cholesky
+// factor; tmp is the matrix's own scratch of spd_batch_scratch() elements.
+struct SpdMat {
+  void *A;
+  int64_t lda, np;
+  void *tmp;
+  DevStatus *ds;
+};
+void spd_batch_scratch(const int64_t *np, int count, int64_t *out);
+struct SpdPlan;  // launch plan with its argument tables in device memory
+SpdPlan *spd_plan_create();
+void spd_plan_destroy(SpdPlan *p);
+// Builds the plan for these matrices (kept when they are the same as in the
+// last build); returns 0 or -1 on a HIP failure.
+int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st);
+void spd_plan_run(const SpdPlan *p, hipStream_t st);
+// Host-only check of the plan for matrices of sizes np: every access inside
+// its matrix or scratch, every column block factored once.  0 when it holds.
+int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t *n_launches);
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st);
+// Concatenated scenes: identity padding of every scene's matrix, and the
+// blocks of every camera (cov: n_cams x 81 in concatenation order).
+void launch_pad_identity_scenes(int n_scenes, int64_t max_np, const int32_t *cam_off,
+                                const int64_t *a_off, const int64_t *a_ld, double *amat,
+                                hipStream_t st);
+void launch_extract_scenes(int64_t n_cams, const int32_t *cam_scene, const int32_t *cam_off,
+                           const int64_t *a_off, const int64_t *a_ld, const double *amat,
+                           const double *s, const double *q, const double *alpha, double *cov,
+                           hipStream_t st);
 // cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha (q: N x 7, leading
 // dimension ldq)
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
