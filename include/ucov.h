@@ -242,6 +242,14 @@ int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const dou
                              const float *out_mean, const float *out_std, double *cov,
                              double *spread);
 
+/* Diagnostic, host only (no device needed): builds the launch plan that the
+ * batched entry point uses for matrices of padded sizes np[0..count)
+ * (multiples of 64) and checks that every product and leaf stays inside its
+ * matrix or scratch and that every 64-column block is factored exactly once.
+ * UCOV_OK when it holds, UCOV_EDEVICE when not, UCOV_EINVAL for bad sizes.
+ * n_launches (may be NULL) receives the number of kernel launches. */
+int ucov_plan_check(const int64_t *np, int32_t count, int64_t *n_launches);
+
 /* Text for an error code; description of the last failure on this context. */
 const char *ucov_strerror(int code);
 const char *ucov_last_error(const ucov_ctx *ctx);

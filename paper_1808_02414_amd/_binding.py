@@ -50,7 +50,7 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error",
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
-           "ucov_screener_covariance"]
+           "ucov_screener_covariance", "ucov_plan_check"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
                                           P, P]),
         "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
         "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
+        "ucov_plan_check": (ctypes.c_int, [P, I32, P]),
         "ucov_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ucov_last_error": (ctypes.c_char_p, [P]),
     }
@@ -97,9 +98,21 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    del I32, D
+    del D
     _lib = lib
     return lib
+
+
+def plan_check(np_sizes):
+    """Host-only check of the batched inverse plan (see ucov_plan_check):
+    returns (ok, number of launches)."""
+    lib = load()
+    arr = (ctypes.c_int64 * len(np_sizes))(*[int(x) for x in np_sizes])
+    nl = ctypes.c_int64(0)
+    rc = lib.ucov_plan_check(arr, len(np_sizes), ctypes.byref(nl))
+    if rc == EINVAL:
+        raise ValueError("sizes must be positive multiples of 64")
+    return rc == OK, int(nl.value)
 
 
 class UcovError(RuntimeError):

@@ -856,6 +856,14 @@ int ucov_screener_covariance(ucov_ctx *c, int64_t n, const float *y, const doubl
   return UCOV_OK;
 }
 
+int ucov_plan_check(const int64_t *np, int32_t count, int64_t *n_launches) {
+  if (!np || count < 1) return UCOV_EINVAL;
+  for (int32_t s = 0; s < count; ++s)
+    if (np[s] < 64 || np[s] % 64 != 0) return UCOV_EINVAL;
+  std::string why;
+  return spd_plan_check_host(np, count, &why, n_launches) == 0 ? UCOV_OK : UCOV_EDEVICE;
+}
+
 const char *ucov_strerror(int code) { return code_name(code); }
 
 const char *ucov_last_error(const ucov_ctx *c) { return c ? c->last_error.c_str() : "no context"; }
