@@ -241,28 +241,29 @@ __device__ inline float rsqrt_nr(float x) {
   return y;
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NT>
 __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatus *ds) {
   typedef Mfma<T> MF;
   typedef typename MF::vec2 V2;
   constexpr int LD = NB + kLP;
   constexpr int NPAN = NB / 16;
+  constexpr int NW = NT / 64;  // waves
   __shared__ T S[NB * LD];
   __shared__ T Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   T *G = A + o + o * lda;
   // whole columns with paired loads (the upper part is read and discarded)
-  constexpr int NL = NB * NB / 2 / 256;
+  constexpr int NL = NB * NB / 2 / NT;
   V2 ld2[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int e = 2 * (tid + 256 * k);
+    const int e = 2 * (tid + NT * k);
     const int r = e % NB, c = e / NB;
     ld2[k] = *reinterpret_cast<const V2 *>(G + r + (int64_t)c * lda);
   }
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int e = 2 * (tid + 256 * k);
+    const int e = 2 * (tid + NT * k);
     const int r = e % NB, c = e / NB;
     S[c * LD + r] = r >= c ? ld2[k].x : T(0);
     S[c * LD + r + 1] = r + 1 >= c ? ld2[k].y : T(0);
@@ -316,7 +317,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     }
     __syncthreads();
     // ---- 2. panel: L_ip = A_ip L_pp^-T ----
-    for (int i = p + 1 + wid; i < NPAN; i += 4) {
+    for (int i = p + 1 + wid; i < NPAN; i += NW) {
       typename MF::acc_t acc = MF::zero();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -333,7 +334,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     {
       const int m = NPAN - 1 - p;  // trailing block rows
       const int nblk = m * (m + 1) / 2;
-      for (int b = wid; b < nblk; b += 4) {
+      for (int b = wid; b < nblk; b += NW) {
         int jj = 0, rem = b;  // b -> (ii, jj) in the lower triangle of m x m blocks
         while (rem >= m - jj) {
           rem -= m - jj;
@@ -361,14 +362,14 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
     // a. stage L(i, p), i > p, in block (p, i) (upper, unused); Y(p, c)
-    for (int i = p + 1 + wid; i < NPAN; i += 4) {
+    for (int i = p + 1 + wid; i < NPAN; i += NW) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = MF::row(lane, v);  // (row r, col lr) of L_ip
         S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
       }
     }
-    for (int c = wid; c <= p; c += 4) {
+    for (int c = wid; c <= p; c += NW) {
       if (c == p) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -393,7 +394,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     {
       const int m = NPAN - 1 - p;
       const int nblk = m * (p + 1);
-      for (int b = wid; b < nblk; b += 4) {
+      for (int b = wid; b < nblk; b += NW) {
         const int i = p + 1 + b % m, c = b / m;
         typename MF::acc_t acc;
 #pragma unroll
@@ -414,7 +415,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   }
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int e = 2 * (tid + 256 * k);
+    const int e = 2 * (tid + NT * k);
     const int r = e % NB, c = e / NB;
     V2 x;
     x.x = r >= c ? S[c * LD + r] : T(0);
@@ -423,9 +424,17 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   }
 }
 
+// Threads of a leaf workgroup: 8 waves for 128 (more block products per
+// barrier; 16 waves leave too few registers), 4 for 64.
+template <int NB>
+struct LeafThreads {
+  static constexpr int value = NB == 128 ? 512 : 256;
+};
+
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_leaf_mfma(T *A, int64_t lda, int64_t o, DevStatus *ds) {
-  leaf_body<T, NB>(A, lda, o, ds);
+__global__ __launch_bounds__(LeafThreads<NB>::value) void k_leaf_mfma(T *A, int64_t lda, int64_t o,
+                                                                     DevStatus *ds) {
+  leaf_body<T, NB, LeafThreads<NB>::value>(A, lda, o, ds);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,9 +451,9 @@ struct LeafArg {
 };
 
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_leaf_mfma_b(const LeafArg<T> *tab) {
+__global__ __launch_bounds__(LeafThreads<NB>::value) void k_leaf_mfma_b(const LeafArg<T> *tab) {
   const LeafArg<T> a = tab[blockIdx.x];
-  leaf_body<T, NB>(a.A, a.lda, a.o, a.ds);
+  leaf_body<T, NB, LeafThreads<NB>::value>(a.A, a.lda, a.o, a.ds);
 }
 
 template <typename T, bool AT, bool BT, bool LOWER>
@@ -708,15 +717,19 @@ int64_t recurse_scratch(int64_t n) {
 
 // In-place L^-1 of the n x n block at offset o.  tmp[0, n2*n1) holds this
 // level's T2 = L21 L11^-1 across the recursion into A22; the rest is scratch
-// for T = L21 and for the children.
+// for T = L21 and for the children.  (Running T2 on a second stream beside
+// the right subtree was measured slower at every node size: the concurrent
+// products slow each other and the cross-stream waits add latency.)
 template <typename T>
 void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hipStream_t st) {
   if (n == 64) {
-    hipLaunchKernelGGL((k_leaf_mfma<T, 64>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<T, 64>), dim3(1), dim3(LeafThreads<64>::value), 0, st, A, lda,
+                       o, ds);
     return;
   }
   if (n == 128) {
-    hipLaunchKernelGGL((k_leaf_mfma<T, 128>), dim3(1), dim3(256), 0, st, A, lda, o, ds);
+    hipLaunchKernelGGL((k_leaf_mfma<T, 128>), dim3(1), dim3(LeafThreads<128>::value), 0, st, A,
+                       lda, o, ds);
     return;
   }
   const int64_t tiles = n / 64;
@@ -1022,10 +1035,11 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
   for (const PlanLaunch &L : p->launches) {
     switch (L.kind) {
       case kPlanLeaf64:
-        hipLaunchKernelGGL((k_leaf_mfma_b<double, 64>), dim3(L.gx), dim3(256), 0, st, lv + L.first);
+        hipLaunchKernelGGL((k_leaf_mfma_b<double, 64>), dim3(L.gx), dim3(LeafThreads<64>::value), 0,
+                           st, lv + L.first);
         break;
       case kPlanLeaf128:
-        hipLaunchKernelGGL((k_leaf_mfma_b<double, 128>), dim3(L.gx), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_leaf_mfma_b<double, 128>), dim3(L.gx), dim3(LeafThreads<128>::value), 0, st,
                            lv + L.first);
         break;
       case kPlanGemmT:
