@@ -178,6 +178,113 @@ __device__ inline void gemm_tile(const GemmArgs<T> &g, int tm, int tn) {
     }
 }
 
+// The same product on 32 x 32 tiles with one wave per workgroup, for
+// products too small to occupy every compute unit with 64 x 64 tiles: a
+// tile's K loop takes about as long as a 64 x 64 tile's, so four times the
+// workgroups finish about four times sooner while the GPU has room for them.
+// K ranges of triangular operands are cut at 32-granular bounds; the parts
+// they read above a diagonal lie inside leaf blocks, which hold zeros there.
+template <typename T, bool AT, bool BT, bool LOWER>
+__device__ inline void gemm_tile32(const GemmArgs<T> &g, int tm, int tn) {
+  typedef Mfma<T> MF;
+  typedef typename MF::vec2 V2;
+  if (LOWER && tn > tm) return;
+  const int64_t K = g.K, lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+  const T *__restrict__ A = g.A;
+  const T *__restrict__ B = g.B;
+  T *__restrict__ C = g.C;
+  const int kmode = g.kmode;
+  int64_t kb = 0, ke = K;
+  if (kmode == kLeN) ke = min(K, (int64_t)(tn + 1) * 32);
+  else if (kmode == kGeN) kb = (int64_t)tn * 32;
+  else if (kmode == kLeM) ke = min(K, (int64_t)(tm + 1) * 32);
+  else if (kmode == kGeMN) kb = (int64_t)max(tm, tn) * 32;
+
+  __shared__ T As[kKc][32 + kPad];
+  __shared__ T Bs[kKc][32 + kPad];
+  const int lane = threadIdx.x;
+  typename MF::acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = MF::zero();
+  // loaders: 8 consecutive elements per lane per chunk
+  const int lt_k = lane >> 2, lt_m = (lane & 3) * 8;  // K-major tile (M contiguous)
+  const int lc_m = lane >> 1, lc_k = (lane & 1) * 8;  // M-major tile (K contiguous)
+  const T *pa = AT ? A + lc_k + ((int64_t)tm * 32 + lc_m) * lda
+                   : A + (int64_t)tm * 32 + lt_m + lt_k * lda;
+  const T *pb = BT ? B + (int64_t)tn * 32 + lt_m + lt_k * ldb
+                   : B + lc_k + ((int64_t)tn * 32 + lc_m) * ldb;
+  T ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    const T *qa = AT ? pa + k0 : pa + k0 * lda;
+    const T *qb = BT ? pb + k0 * ldb : pb + k0;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const V2 a = *reinterpret_cast<const V2 *>(qa + 2 * h);
+      const V2 b = *reinterpret_cast<const V2 *>(qb + 2 * h);
+      ra[2 * h] = a.x;
+      ra[2 * h + 1] = a.y;
+      rb[2 * h] = b.x;
+      rb[2 * h + 1] = b.y;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kKc) {
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      if (AT) As[lc_k + v][lc_m] = ra[v];
+      else As[lt_k][lt_m + v] = ra[v];
+      if (BT) Bs[lt_k][lt_m + v] = rb[v];
+      else Bs[lc_k + v][lc_m] = rb[v];
+    }
+    __syncthreads();
+    if (k0 + kKc < ke) load(k0 + kKc);
+#pragma unroll
+    for (int kk = 0; kk < kKc / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const int c = lane & 15;
+      const T a0 = As[kr][c], a1 = As[kr][16 + c];
+      const T b0 = Bs[kr][c], b1 = Bs[kr][16 + c];
+      acc[0][0] = MF::mma(a0, b0, acc[0][0]);
+      acc[0][1] = MF::mma(a0, b1, acc[0][1]);
+      acc[1][0] = MF::mma(a1, b0, acc[1][0]);
+      acc[1][1] = MF::mma(a1, b1, acc[1][1]);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int64_t col = (int64_t)tn * 32 + bj * 16 + (lane & 15);
+      const int64_t row0 = (int64_t)tm * 32 + bi * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T *pc = C + row0 + MF::row(lane, v) + col * ldc;
+        const T x = g.alpha * acc[bi][bj][v];
+        *pc = g.beta == T(0) ? x : x + g.beta * (*pc);
+      }
+    }
+}
+
+template <typename T, bool AT, bool BT, bool LOWER>
+__global__ __launch_bounds__(64) void k_gemm32(GemmArgs<T> g) {
+  gemm_tile32<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_gemm32_pair(GemmArgs<T> s, GemmArgs<T> t, int nblk_s) {
+  const int b = blockIdx.x;
+  if (b < nblk_s) {
+    const int mt = (int)(s.M / 32);
+    gemm_tile32<T, false, true, true>(s, b % mt, b / mt);
+  } else {
+    const int mt = (int)(t.M / 32), bb = b - nblk_s;
+    gemm_tile32<T, false, false, false>(t, bb % mt, bb / mt);
+  }
+}
+
 // One product; grid (M/64, N/64), tile rows fastest.
 template <typename T, bool AT, bool BT, bool LOWER>
 __global__ __launch_bounds__(256) void k_gemm64(GemmArgs<T> g) {
@@ -694,10 +801,18 @@ GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, 
   return g;
 }
 
+// Products with fewer 64 x 64 tiles than this run on 32 x 32 tiles.
+constexpr int64_t kSmallTiles = 256;
+
 template <typename T, bool AT, bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
           T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st) {
   GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
+  if ((M / 64) * (N / 64) < kSmallTiles) {
+    hipLaunchKernelGGL((k_gemm32<T, AT, BT, LOWER>), dim3((unsigned)(M / 32), (unsigned)(N / 32)),
+                       dim3(64), 0, st, g);
+    return;
+  }
   hipLaunchKernelGGL((k_gemm64<T, AT, BT, LOWER>), dim3((unsigned)(M / 64), (unsigned)(N / 64)),
                      dim3(256), 0, st, g);
 }
@@ -705,6 +820,12 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
 template <typename T>
 void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st) {
   const unsigned a = (unsigned)((s.M / 64) * (s.N / 64)), b = (unsigned)((t.M / 64) * (t.N / 64));
+  if (a + b < kSmallTiles) {
+    const unsigned a32 = (unsigned)((s.M / 32) * (s.N / 32)),
+                   b32 = (unsigned)((t.M / 32) * (t.N / 32));
+    hipLaunchKernelGGL((k_gemm32_pair<T>), dim3(a32 + b32), dim3(64), 0, st, s, t, (int)a32);
+    return;
+  }
   hipLaunchKernelGGL((k_gemm64_pair<T>), dim3(a + b), dim3(256), 0, st, s, t, (int)a);
 }
 
