@@ -23,6 +23,9 @@ Modules, in the order of the paper's method:
 * ``covariance`` Moore-Penrose camera covariance Z^+ = (Z + a Q Q^T)^-1 - Q Q^T / a
                  with Jacobi conditioning (Sec. 4 gauge, Sec. 5.2 conditioning)
 * ``pipeline``   end to end, plus the input checks shared by the error tests
+* ``paper_gauge`` the paper's own gauge, (M^+)_cc: the definition on the dense
+                 M, and the points eliminated with the full nullspace
+                 (Sec. 4, Sec. 5.2)
 * ``screener``   the learned screener's reference: per-camera features, the
                  log-Cholesky label transform, an FP64 MLP with its gradient,
                  and Adam (not part of the paper; its labels are the exact
