@@ -88,11 +88,26 @@ typedef struct {
   const double *obs_info;  /* n_obs x 3 or NULL */
 } ucov_scene;
 
+/* Gauge of the covariance.
+ * UCOV_GAUGE_CAMERA: Z^+, the Moore-Penrose inverse of the reduced camera
+ *   matrix (camera parameters orthogonal to the similarity nullspace).
+ * UCOV_GAUGE_PAPER: (M^+)_cc, the camera block of the Moore-Penrose inverse
+ *   of the full information matrix (Sec. 4: the whole parameter vector,
+ *   points included, orthogonal to the nullspace; Sec. 5.2: the points
+ *   eliminated by block inversion).  Evaluated as (Z + G F^-1 G^T)^-1 with
+ *   G = H_c - W V^-1 H_p and F = H_p^T V^-1 H_p, H_p the point rows of the
+ *   nullspace.  The two agree after projection: Z^+ = P_c (M^+)_cc P_c with
+ *   P_c the projector onto the complement of range(H_c); their intrinsics
+ *   blocks coincide. */
+#define UCOV_GAUGE_CAMERA 0
+#define UCOV_GAUGE_PAPER  1
+
 typedef struct {
   int32_t precision;  /* UCOV_FP64 or UCOV_FP32_NS */
   int32_t max_iter;   /* Newton-Schulz iterations allowed (UCOV_FP32_NS); 0 = default 6 */
   double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-10 */
-  double alpha;       /* gauge weight a; 0 = balanced automatic choice */
+  double alpha;       /* gauge weight a; 0 = balanced automatic choice (UCOV_GAUGE_CAMERA only) */
+  int32_t gauge;      /* UCOV_GAUGE_CAMERA (default) or UCOV_GAUGE_PAPER */
 } ucov_options;
 
 typedef struct {
@@ -122,7 +137,8 @@ void ucov_destroy(ucov_ctx *ctx);
 
 /* Per-camera covariance blocks, the whole hot path (steps a1-a4).
  * cov_out: n_cams x 81 float64, block i row-major at cov_out + 81*i; it is
- * the diagonal block of Z^+ for the parameters (r, C, f, k1, k2) of camera i.
+ * the diagonal block of Z^+ (or of (M^+)_cc with UCOV_GAUGE_PAPER) for the
+ * parameters (r, C, f, k1, k2) of camera i.
  * opt may be NULL (defaults); rep may be NULL. */
 int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
                            const ucov_options *opt, double *cov_out,
@@ -138,7 +154,8 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
  * cov_out: (sum of n_cams) x 81 float64; the blocks of scene s follow those of
  * scene s - 1, each as in ucov_camera_covariance.
  * alphas: HOST array receiving the gauge weight of every scene, or NULL.
- * opt->precision must be UCOV_FP64 (else UCOV_EINVAL).
+ * opt->precision must be UCOV_FP64 and opt->gauge UCOV_GAUGE_CAMERA (else
+ * UCOV_EINVAL).
  * rep: ms_inverse covers the dense stage of all scenes (identity padding,
  * the batched factorisation and inversion, block extraction), ms_extract is 0,
  * alpha is scene 0's; on failure bad_scene names the scene and bad_index the

@@ -18,6 +18,7 @@ OK, EINVAL, EPOINT, EGAUGE, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 ERROR_NAMES = {EINVAL: "EINVAL", EPOINT: "EPOINT", EGAUGE: "EGAUGE", ENOCONV: "ENOCONV",
                EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
 FP64, FP32_NS = 0, 1
+GAUGE_CAMERA, GAUGE_PAPER = 0, 1
 
 
 class Scene(ctypes.Structure):
@@ -29,7 +30,7 @@ class Scene(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("alpha", ctypes.c_double), ("gauge", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -196,13 +197,13 @@ class Context:
                             rep.bad_scene if rep is not None else -1)
 
     def camera_covariance(self, scene: DeviceScene, precision=FP64, alpha=0.0, tol=0.0,
-                          max_iter=0, out=None):
+                          max_iter=0, out=None, gauge=GAUGE_CAMERA):
         """(n, 9, 9) float64 covariance blocks on the device, and the report."""
         torch = self.torch
         n = scene.n_cams
         if out is None:
             out = torch.empty((n, 9, 9), dtype=torch.float64, device=scene.cams.device)
-        opt = Options(precision, max_iter, tol, alpha)
+        opt = Options(precision, max_iter, tol, alpha, gauge)
         rep = Report()
         self._stream()
         sc = scene.struct()
@@ -222,7 +223,7 @@ class Context:
             out = torch.empty((total, 9, 9), dtype=torch.float64, device=scenes[0].cams.device)
         arr = (Scene * len(scenes))(*[s.struct() for s in scenes])
         alphas = (ctypes.c_double * len(scenes))()
-        opt = Options(FP64, 0, 0.0, alpha)
+        opt = Options(FP64, 0, 0.0, alpha, GAUGE_CAMERA)
         rep = Report()
         self._stream()
         rc = self.lib.ucov_camera_covariance_batched(self.h, len(scenes), arr, ctypes.byref(opt),
@@ -273,7 +274,7 @@ class Context:
         zc = z.contiguous()  # symmetric: row-major storage is its own column-major form
         qc = q.T.contiguous()
         out = torch.empty((N // 9, 9, 9), dtype=torch.float64, device=z.device)
-        opt = Options(precision, 0, 0.0, alpha)
+        opt = Options(precision, 0, 0.0, alpha, GAUGE_CAMERA)
         rep = Report()
         self._stream()
         self._check(self.lib.ucov_pinv_blocks(self.h, N, zc.data_ptr(), N, qc.data_ptr(),

@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *a, int64
 // products of row r of L^-1 restricted to the camera's 9 columns.
 __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, int64_t ld,
                                                 const double *s, const double *q, int64_t ldq,
-                                                const double *alpha, double *cov) {
+                                                const double *alpha, int subtract, double *cov) {
   const int64_t i = blockIdx.x;
   const int64_t c0 = 9 * i;
   double acc[45];
@@ -708,14 +708,15 @@ __global__ __launch_bounds__(256) void k_extract(int64_t N, const double *linv, 
     double g = 0.0;
 #pragma unroll
     for (int k = 0; k < 7; ++k) g += q[k * ldq + c0 + a0] * q[k * ldq + c0 + b0];
-    cov[81 * i + threadIdx.x] = s[c0 + a0] * x * s[c0 + b0] - g / (*alpha);
+    cov[81 * i + threadIdx.x] = s[c0 + a0] * x * s[c0 + b0] - (subtract ? g / (*alpha) : 0.0);
   }
 }
 
 // cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X (81 threads
 // per camera)
 __global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                               const double *q, int64_t ldq, const double *alpha, double *cov) {
+                               const double *q, int64_t ldq, const double *alpha, int subtract,
+                               double *cov) {
   const int64_t i = blockIdx.x;
   const int t = threadIdx.x;
   if (t >= 81) return;
@@ -724,7 +725,7 @@ __global__ void k_extract_full(int64_t N, const double *x, int64_t ld, const dou
   double g = 0.0;
 #pragma unroll
   for (int k = 0; k < 7; ++k) g += q[k * ldq + r] * q[k * ldq + c];
-  cov[81 * i + t] = s[r] * xs * s[c] - g / (*alpha);
+  cov[81 * i + t] = s[r] * xs * s[c] - (subtract ? g / (*alpha) : 0.0);
 }
 
 // Every scene of a concatenation: grid (column c, scene s); rows r >= max(c,
@@ -802,7 +803,7 @@ GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, 
 }
 
 // Products with fewer 64 x 64 tiles than this run on 32 x 32 tiles.
-constexpr int64_t kSmallTiles = 256;
+constexpr int64_t kSmallTiles = 1024;
 
 template <typename T, bool AT, bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
@@ -1219,17 +1220,17 @@ void launch_extract_scenes(int64_t n_cams, const int32_t *cam_scene, const int32
 }
 
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
-                    const double *q, int64_t ldq, const double *alpha, double *cov,
+                    const double *q, int64_t ldq, const double *alpha, bool subtract, double *cov,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_extract, dim3((unsigned)(N / 9)), dim3(256), 0, st, N, linv, ld, s, q,
-                     ldq, alpha, cov);
+                     ldq, alpha, (int)subtract, cov);
 }
 
 void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                         const double *q, int64_t ldq, const double *alpha, double *cov,
-                         hipStream_t st) {
+                         const double *q, int64_t ldq, const double *alpha, bool subtract,
+                         double *cov, hipStream_t st) {
   hipLaunchKernelGGL(k_extract_full, dim3((unsigned)(N / 9)), dim3(128), 0, st, N, x, ld, s, q,
-                     ldq, alpha, cov);
+                     ldq, alpha, (int)subtract, cov);
 }
 
 void mixed_initial_inverse(int64_t Np, const double *a, int64_t lda, float *a32, float *x32,

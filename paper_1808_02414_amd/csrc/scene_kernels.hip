@@ -793,6 +793,176 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge_scenes(SceneDev sc, con
 }
 
 // ---------------------------------------------------------------------------
+// The paper's gauge: (M^+)_cc = (Z + G F^-1 G^T)^-1 with G = H_c - W V^-1 H_p
+// and F = H_p^T V^-1 H_p, H_p the point rows [I, [X_j]x, X_j] of the
+// similarity nullspace (Sec. 4, Sec. 5.2: the points eliminated with the full
+// nullspace; the term vanishes from the inverse as the constraint weight
+// grows).  Written as P P^T with P = G L_F^-T, it takes the place of a Q Q^T.
+// ---------------------------------------------------------------------------
+
+// F += H_p^T V_j^-1 H_p per point (V_j from the point's whitened J_X rows),
+// 28 upper-triangle values reduced per workgroup and added to f.
+__global__ __launch_bounds__(256) void k_paper_f(SceneDev sc, const int64_t *ptr_p,
+                                                const double *rec, double *f) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) acc[k] = 0.0;
+  if (j < sc.m && ptr_p[j + 1] - ptr_p[j] >= 2) {
+    double v00 = 0, v01 = 0, v02 = 0, v11 = 0, v12 = 0, v22 = 0;
+    for (int64_t a = ptr_p[j]; a < ptr_p[j + 1]; ++a) {
+      const double *x = rec + a * kRec + kRecJX;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const double u = x[3 * p], v = x[3 * p + 1], w = x[3 * p + 2];
+        v00 += u * u; v01 += u * v; v02 += u * w;
+        v11 += v * v; v12 += v * w; v22 += w * w;
+      }
+    }
+    // V = L L^T (its pivots were checked by the point blocks), M = L^-1
+    const double L00 = sqrt(v00), L10 = v01 / L00, L20 = v02 / L00;
+    const double L11 = sqrt(v11 - L10 * L10), L21 = (v12 - L20 * L10) / L11;
+    const double L22 = sqrt(v22 - L20 * L20 - L21 * L21);
+    const double M00 = 1.0 / L00, M11 = 1.0 / L11, M22 = 1.0 / L22;
+    const double M10 = -L10 * M00 * M11, M21 = -L21 * M11 * M22;
+    const double M20 = -(L20 * M00 + L21 * M10) * M22;
+    const double X0 = sc.pts[3 * (int64_t)j], X1 = sc.pts[3 * (int64_t)j + 1],
+                 X2 = sc.pts[3 * (int64_t)j + 2];
+    // H_p rows: [I, [X]x, X]
+    const double H[3][7] = {{1, 0, 0, 0, -X2, X1, X0},
+                            {0, 1, 0, X2, 0, -X0, X1},
+                            {0, 0, 1, -X1, X0, 0, X2}};
+    const double M[3][3] = {{M00, 0, 0}, {M10, M11, 0}, {M20, M21, M22}};
+    double R[3][7];  // M H_p, so F_j = R^T R
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) R[r][c] = M[r][0] * H[0][c] + M[r][1] * H[1][c] + M[r][2] * H[2][c];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a)
+#pragma unroll
+      for (int b = a; b < 7; ++b) acc[k++] = R[0][a] * R[0][b] + R[1][a] * R[1][b] + R[2][a] * R[2][b];
+  }
+  __shared__ double part[4][28];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 28; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) part[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    const int k = threadIdx.x;
+    atomicAdd(&f[k], part[0][k] + part[1][k] + part[2][k] + part[3][k]);
+  }
+}
+
+// G_i = H_c,i - sum over camera i's observations of J_P^T (Y H_p,j) (Y =
+// J_X V^-1 from the slot record), one workgroup per camera over the slots of
+// its diagonal camera-pair bin; written to q (N x 7, leading dimension N).
+__global__ __launch_bounds__(256) void k_paper_g(SceneDev sc, const int64_t *bin_ptr,
+                                                const int2 *pairs, const double *rec,
+                                                const int32_t *slot_pt, const double *hc,
+                                                double *q) {
+  const int i = blockIdx.x;
+  const int64_t bin = bin_of(sc, i, i);
+  const int64_t N = 9 * (int64_t)sc.n;
+  double acc[63];
+#pragma unroll
+  for (int k = 0; k < 63; ++k) acc[k] = 0.0;
+  for (int64_t e = bin_ptr[bin] + threadIdx.x; e < bin_ptr[bin + 1]; e += blockDim.x) {
+    const int a = pairs[e].x;
+    const double *r = rec + (int64_t)a * kRec;
+    const int j = slot_pt[a];
+    const double X0 = sc.pts[3 * (int64_t)j], X1 = sc.pts[3 * (int64_t)j + 1],
+                 X2 = sc.pts[3 * (int64_t)j + 2];
+    double yh[2][7];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const double y0 = r[kRecY + 3 * p], y1 = r[kRecY + 3 * p + 1], y2 = r[kRecY + 3 * p + 2];
+      yh[p][0] = y0;
+      yh[p][1] = y1;
+      yh[p][2] = y2;
+      yh[p][3] = y1 * X2 - y2 * X1;  // y [X]x
+      yh[p][4] = -y0 * X2 + y2 * X0;
+      yh[p][5] = y0 * X1 - y1 * X0;
+      yh[p][6] = y0 * X0 + y1 * X1 + y2 * X2;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 9; ++rr) {
+      const double p0 = r[kRecJP + rr], p1 = r[kRecJP + 9 + rr];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) acc[7 * rr + c] += p0 * yh[0][c] + p1 * yh[1][c];
+    }
+  }
+  __shared__ double part[4][63];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 63; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) part[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 63) {
+    const int rr = threadIdx.x / 7, c = threadIdx.x % 7;
+    const int64_t row = 9 * (int64_t)i + rr;
+    const double g = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                     part[3][threadIdx.x];
+    q[c * N + row] = hc[c * N + row] - g;
+  }
+}
+
+// F = L_F L_F^T (one thread), then every row of q replaced by L_F^-1 applied
+// to it (P = G L_F^-T); the gauge weight is 1.
+__global__ __launch_bounds__(1024) void k_paper_p(int64_t N, const double *f, double *q,
+                                                 double *alpha, DevStatus *ds) {
+  __shared__ double L[7][7];
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    double F[7][7];
+    int k = 0;
+    for (int a = 0; a < 7; ++a)
+      for (int b = a; b < 7; ++b, ++k) F[a][b] = F[b][a] = f[k];
+    double tr = 0.0;
+    for (int a = 0; a < 7; ++a) tr += F[a][a];
+    ok = 1;
+    for (int a = 0; a < 7; ++a) {
+      for (int b = 0; b <= a; ++b) {
+        double s = F[a][b];
+        for (int c = 0; c < b; ++c) s -= L[a][c] * L[b][c];
+        if (a == b) {
+          if (!(s > 1e-14 * tr)) {
+            ok = 0;
+            s = 1.0;
+          }
+          L[a][a] = sqrt(s);
+        } else {
+          L[a][b] = s / L[b][b];
+        }
+      }
+      for (int b = a + 1; b < 7; ++b) L[a][b] = 0.0;
+    }
+    if (!ok) report_error(ds, UCOV_EGAUGE, -1);
+    alpha[0] = 1.0;
+  }
+  __syncthreads();
+  if (!ok) return;
+  for (int64_t p = threadIdx.x; p < N; p += blockDim.x) {
+    double x[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      double s = q[a * N + p];
+#pragma unroll
+      for (int c = 0; c < a; ++c) s -= L[a][c] * x[c];
+      x[a] = s / L[a][a];
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) q[a * N + p] = x[a];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1)
 //
 // k_fill_empty writes the camera blocks without Schur terms (Z_ik = 0): zeros
@@ -1026,6 +1196,17 @@ void launch_concat_scenes(int n_scenes, const BatchEntry *tab, int64_t max_elems
   const unsigned bx = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (max_elems + 255) / 256), 1024);
   hipLaunchKernelGGL(k_concat, dim3(bx, (unsigned)n_scenes), dim3(256), 0, st, tab, cams, pts,
                      info, oc, op, cam_scene, ds);
+}
+
+void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *ds,
+                        hipStream_t st) {
+  const int64_t N = 9 * (int64_t)sc.n;
+  fill_f64(f, 0.0, 28, st);
+  hipLaunchKernelGGL(k_paper_f, dim3(blocks_for(sc.m, 256)), dim3(256), 0, st, sc, w.ptr_p, w.rec,
+                     f);
+  hipLaunchKernelGGL(k_paper_g, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs, w.rec,
+                     w.slot_pt, w.hc, w.q);
+  hipLaunchKernelGGL(k_paper_p, dim3(1), dim3(1024), 0, st, N, f, w.q, w.alpha, ds);
 }
 
 void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const double *zdiag,

@@ -56,6 +56,7 @@ struct ucov_ctx {
   size_t h_ds_cap = 0;
   // learned screener
   Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
+  Buf pg_f;  // the paper gauge's 7 x 7 F (28 values)
 
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
@@ -256,11 +257,13 @@ void fill_defaults(const ucov_options *opt, ucov_options &o) {
   o.max_iter = 6;
   o.tol = 1e-10;
   o.alpha = 0.0;
+  o.gauge = UCOV_GAUGE_CAMERA;
   if (opt) {
     o.precision = opt->precision;
     if (opt->max_iter > 0) o.max_iter = opt->max_iter;
     if (opt->tol > 0) o.tol = opt->tol;
     o.alpha = opt->alpha;
+    o.gauge = opt->gauge;
   }
 }
 
@@ -318,7 +321,7 @@ int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double 
   }
   hipEventRecord(c->ev[4], st);
   launch_extract_full(N, as<double>(c->m_x64), Np, as<double>(c->s), as<double>(c->q), N,
-                      as<double>(c->alpha), cov_out, st);
+                      as<double>(c->alpha), o.gauge != UCOV_GAUGE_PAPER, cov_out, st);
   return UCOV_OK;
 }
 
@@ -335,7 +338,7 @@ int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_o
     spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
     hipEventRecord(c->ev[4], st);
     launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), N, as<double>(c->alpha),
-                   cov_out, st);
+                   o.gauge != UCOV_GAUGE_PAPER, cov_out, st);
   } else {
     UCOV_TRY(run_mixed(c, N, Np, o, cov_out, rep));
   }
@@ -396,7 +399,7 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
-                 &c->mlp_ws, &c->mlp_grad};
+                 &c->mlp_ws, &c->mlp_grad, &c->pg_f};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   if (c->h_stage) hipHostFree(c->h_stage);
@@ -464,6 +467,8 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   fill_defaults(opt, o);
   if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
+  if (o.gauge != UCOV_GAUGE_CAMERA && o.gauge != UCOV_GAUGE_PAPER)
+    return c->fail(UCOV_EINVAL, "unknown gauge");
   hipSetDevice(c->device);
   reset_report(rep);
   const SceneDev sc = scene_dev(scene);
@@ -476,7 +481,13 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   UCOV_TRY(ensure(c, c->amat, 8 * Np * Np));
   SceneWork w = scene_work(c);
   hipEventRecord(c->ev[2], c->stream);
-  launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, c->stream);
+  if (o.gauge == UCOV_GAUGE_PAPER) {
+    UCOV_TRY(ensure(c, c->pg_f, 8 * 28));
+    launch_paper_gauge(sc, w, as<double>(c->pg_f), c->ds, c->stream);
+    launch_gauge(N, nullptr, w.q, w.zdiag, nullptr, 0, 1.0, w.s, w.alpha, c->ds, c->stream);
+  } else {
+    launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, c->stream);
+  }
   launch_assemble(sc, w, 1, as<double>(c->amat), Np, c->n_nonzero, c->stream);
   UCOV_TRY(check_hip(c, "assemble"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
@@ -511,6 +522,7 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
                as<double>(c->alpha), c->ds, st);
   launch_scale_dense(N, z, ldz, as<double>(c->q), as<double>(c->s), as<double>(c->alpha),
                      as<double>(c->amat), Np, st);
+  o.gauge = UCOV_GAUGE_CAMERA;  // the caller's q is an orthonormal gauge basis
   UCOV_TRY(check_hip(c, "scale"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
   if (rep) hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
@@ -530,8 +542,8 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   if (n_scenes < 1 || !scenes || !cov_out) return c->fail(UCOV_EINVAL, "bad batch arguments");
   ucov_options o;
   fill_defaults(opt, o);
-  if (o.precision != UCOV_FP64)
-    return c->fail(UCOV_EINVAL, "batched calls support UCOV_FP64 only");
+  if (o.precision != UCOV_FP64 || o.gauge != UCOV_GAUGE_CAMERA)
+    return c->fail(UCOV_EINVAL, "batched calls support UCOV_FP64 with UCOV_GAUGE_CAMERA only");
   const int S = n_scenes;
   // host tables: offsets of every scene in the concatenation
   std::vector<int32_t> cam_off(S + 1), pt_off(S + 1);

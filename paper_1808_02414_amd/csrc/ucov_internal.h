@@ -117,6 +117,11 @@ void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
 void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const double *zdiag,
                          double user_alpha, double *s, double *alpha, DevStatus *ds,
                          hipStream_t st);
+// The paper's gauge (M^+)_cc: q <- G L_F^-T (N x 7) with G = H_c - W V^-1 H_p
+// and F = H_p^T V^-1 H_p = L_F L_F^T (f: 28 doubles of scratch), alpha <- 1,
+// so that (Z + q q^T)^-1 is the covariance.  Needs hc from the scene stage.
+void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *ds,
+                        hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
 // S (Z + a QQ^T) S into out (per scene at out + a_off[s] with leading dimension
 // a_ld[s] for a concatenation).  n_nonzero is the number of non-empty bins.
@@ -187,14 +192,14 @@ void launch_extract_scenes(int64_t n_cams, const int32_t *cam_scene, const int32
                            const double *s, const double *q, const double *alpha, double *cov,
                            hipStream_t st);
 // cov[i] = S_i (Linv^T Linv)_ii S_i - Q_i Q_i^T / alpha (q: N x 7, leading
-// dimension ldq)
+// dimension ldq; the last term only when subtract is set)
 void launch_extract(int64_t N, const double *linv, int64_t ld, const double *s,
-                    const double *q, int64_t ldq, const double *alpha, double *cov,
+                    const double *q, int64_t ldq, const double *alpha, bool subtract, double *cov,
                     hipStream_t st);
 // cov[i] = S_i X_ii S_i - Q_i Q_i^T / alpha from a full inverse X
 void launch_extract_full(int64_t N, const double *x, int64_t ld, const double *s,
-                         const double *q, int64_t ldq, const double *alpha, double *cov,
-                         hipStream_t st);
+                         const double *q, int64_t ldq, const double *alpha, bool subtract,
+                         double *cov, hipStream_t st);
 
 // Mixed precision (all matrices Np x Np, leading dimension Np):
 // X0 = L^-T L^-1 of the FP32 Cholesky factor of the lower triangle of a;
