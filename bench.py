@@ -17,8 +17,10 @@ timed on the host cores on (a bounded sample of) the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,26 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (MFMA and vector)
 PEAK_HBM_GBS = 8000.0
 
 METRIC = "cameras/s of exact covariance + MFMA util on Z^-1, at 1e-6 rel err vs FP64"
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_inverse_fp64_spiral500_hbm_counters.md")
+DENSE_SOURCE = os.path.join(ROOT, "paper_1808_02414_amd", "csrc", "dense_kernels.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per step of the dense stage from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
+    dense kernels have changed since they were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(DENSE_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    t = re.search(r"traffic_bytes_per_step: (\d+)", text)
+    h = re.search(r"dense_kernels_sha256: (\w+)", text)
+    if not (t and h) or h.group(1) != src:
+        return None
+    return int(t.group(1))
 
 
 def _threads():
@@ -105,7 +127,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cams", type=int, default=500)
     ap.add_argument("--n-pts", type=int, default=50_000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only copy a buffer of this many MiB 5 times (for scaling HBM counters)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
+                          "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is not part of this build", file=sys.stderr)
@@ -156,9 +191,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "dense inverse stage (k_leaf_mfma + k_gemm64 + k_gemm64_pair), "
-                               "2N^3/3 flops per scene"},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": (recorded_traffic() if args.workload == "spiral500"
+                                 and args.precision == "fp64" else None),
+                     "kernel": "dense inverse stage (k_leaf_mfma + k_gemm64/32 + k_gemm64/32_pair), "
+                               "2N^3/3 flops per scene; traffic in bytes per step"},
         "stages_ms": stages,
         "n_pairs": int(reps[-1]["n_pairs"]),
     }
