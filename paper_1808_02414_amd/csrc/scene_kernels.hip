@@ -418,19 +418,46 @@ __global__ void k_point_blocks(SceneDev sc, const int64_t *ptr_p, double *rec, D
 // The first pair that lands in a bin also appends (i, k) to the list of
 // non-empty bins.
 __global__ void k_pair_count(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
-                             const int32_t *slot_pt, int32_t *bin_cnt, int2 *nzlist,
-                             unsigned long long *nzcount) {
+                             const int32_t *slot_pt, int32_t *bin_cnt) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= ptr_p[sc.m]) return;
   const int64_t p0 = ptr_p[slot_pt[a]];
   const int ci = slot_cam[a];
-  for (int64_t b = p0; b <= a; ++b) {
-    const int ck = slot_cam[b];
-    if (atomicAdd(&bin_cnt[bin_of(sc, ci, ck)], 1) == 0) {
-      const unsigned long long pos = atomicAdd(nzcount, 1ull);
-      nzlist[pos] = make_int2(ci, ck);
+  for (int64_t b = p0; b <= a; ++b) atomicAdd(&bin_cnt[bin_of(sc, ci, slot_cam[b])], 1);
+}
+
+// Camera pair (i, k) of a bin (inverse of bin_of).
+__device__ inline int2 bin_pair(const SceneDev &sc, int64_t bin) {
+  int64_t local = bin;
+  int base = 0;
+  if (sc.cam_scene) {  // the scene: last s with bin_off[s] <= bin
+    int lo = 0, hi = sc.n_scenes;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (sc.bin_off[mid] <= bin) lo = mid;
+      else hi = mid;
     }
+    local = bin - sc.bin_off[lo];
+    base = sc.cam_off[lo];
   }
+  int64_t i = (int64_t)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+  while (tri(i + 1) <= local) ++i;
+  while (tri(i) > local) --i;
+  return make_int2(base + (int)i, base + (int)(local - tri(i)));
+}
+
+__global__ void k_nz_flag(int64_t nbins, const int32_t *bin_cnt, int32_t *flag) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbins) flag[b] = bin_cnt[b] > 0 ? 1 : 0;
+}
+
+// The non-empty bins in bin order (camera i major within a scene), so that
+// the waves of k_bin_blocks that run side by side share camera i's records.
+__global__ void k_nz_compact(SceneDev sc, int64_t nbins, const int32_t *bin_cnt,
+                             const int64_t *nzpos, int2 *nzlist, int64_t *nzcount) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) nzcount[0] = nzpos[nbins];
+  if (b < nbins && bin_cnt[b] > 0) nzlist[nzpos[b]] = bin_pair(sc, b);
 }
 
 __global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
@@ -1048,7 +1075,12 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
                                                    const double *zdiag, const double *q,
                                                    const double *s, const double *alpha,
                                                    int mode, double *out, int64_t ld) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // Workgroups go round-robin to the 8 dies (XCDs); give each die a
+  // contiguous run of the bin-ordered list (the grid is a multiple of 8), so
+  // one die's L2 keeps a camera's records while its bins are reduced.
+  const unsigned per = gridDim.x / 8;
+  const unsigned logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t w = (int64_t)logical * 4 + (threadIdx.x >> 6);
   if (w >= *nzcount) return;
   const int lane = threadIdx.x & 63;
   const int2 ik = nzlist[w];
@@ -1100,6 +1132,20 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
   }
   const double a = mode ? alpha[si] : 0.0;
   double *o = out + off;
+  // gauge block Q_i Q_k^T (9 x 7 times 7 x 9) as two more 4-deep MFMA steps:
+  // lane l supplies Q_i[l % 16][h] and Q_k[l % 16][h] with h = 4 t + l / 16
+  d4 g4 = {0.0, 0.0, 0.0, 0.0};
+  if (mode) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int h = 4 * t + (lane >> 4);
+      const bool in = col < 9 && h < 7;
+      const double qa = in ? q[h * N + 9 * (int64_t)i + col] : 0.0;
+      const double qb = in ? q[h * N + 9 * (int64_t)k + col] : 0.0;
+      g4 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa, qb, g4, 0, 0, 0);
+    }
+  }
+  const double sc_col = (mode && col < 9) ? s[9 * (int64_t)k + col] : 0.0;
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     const int row = 4 * v + (lane >> 4);
@@ -1111,10 +1157,7 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
       o[lr + lc * lds] = z;
       o[lc + lr * lds] = z;
     } else {
-      double g = 0.0;
-#pragma unroll
-      for (int h = 0; h < 7; ++h) g += q[h * N + pr] * q[h * N + pc];
-      o[lr + lc * lds] = s[pr] * (z + a * g) * s[pc];
+      o[lr + lc * lds] = s[pr] * (z + a * g4[v]) * sc_col;
     }
   }
 }
@@ -1169,8 +1212,16 @@ void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStr
 
 void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_count, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
-                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_cnt, w.nzlist,
-                     reinterpret_cast<unsigned long long *>(w.nzcount));
+                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_cnt);
+}
+
+void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStream_t st) {
+  hipLaunchKernelGGL(k_nz_flag, dim3(blocks_for(nbins, kBlk)), dim3(kBlk), 0, st, nbins, w.bin_cnt,
+                     w.bin_cur);
+  exclusive_scan(w.bin_cur, w.nzpos, nbins, w.scan_tmp, st);
+  hipLaunchKernelGGL(k_nz_compact, dim3(blocks_for(nbins, kBlk)), dim3(kBlk), 0, st, sc, nbins,
+                     w.bin_cnt, w.nzpos, w.nzlist, w.nzcount);
+  fill_i32(w.bin_cur, 0, nbins, st);
 }
 
 void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st) {
@@ -1222,7 +1273,7 @@ void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, in
   hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)N), dim3(256), 0, st, sc, w.bin_cnt, w.q, w.s,
                      w.alpha, mode, out, ld);
   if (n_nonzero > 0)
-    hipLaunchKernelGGL(k_bin_blocks, dim3(blocks_for(n_nonzero, 4)), dim3(256), 0, st, sc,
+    hipLaunchKernelGGL(k_bin_blocks, dim3((blocks_for(n_nonzero, 4) + 7) / 8 * 8), dim3(256), 0, st, sc,
                        w.nzlist, w.nzcount, w.bin_ptr, w.pairs, w.rec, w.zdiag, w.q, w.s,
                        w.alpha, mode, out, ld);
 }

@@ -44,7 +44,7 @@ struct ucov_ctx {
   hipEvent_t ev[8] = {};
   // workspace
   Buf cnt_p, ptr_p, cur_p, slot_obs, slot_cam, slot_pt, rec;
-  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount;
+  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos;
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
   // batched calls: the concatenated scenes, their tables and per-scene status
@@ -170,17 +170,18 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   UCOV_TRY(ensure(c, c->bin_cur, 4 * nbins));
   UCOV_TRY(ensure(c, c->nzlist, sizeof(int2) * nbins));  // at most one entry per bin
   UCOV_TRY(ensure(c, c->nzcount, 8));
+  UCOV_TRY(ensure(c, c->nzpos, 8 * (nbins + 1)));
   w.bin_cnt = as<int32_t>(c->bin_cnt);
   w.bin_ptr = as<int64_t>(c->bin_ptr);
   w.bin_cur = as<int32_t>(c->bin_cur);
   w.nzlist = as<int2>(c->nzlist);
   w.nzcount = as<int64_t>(c->nzcount);
+  w.nzpos = as<int64_t>(c->nzpos);
   launch_point_blocks(sc, w, c->ds, st);
   fill_i32(w.bin_cnt, 0, nbins, st);
-  fill_i32(w.bin_cur, 0, nbins, st);
-  fill_i32(reinterpret_cast<int32_t *>(w.nzcount), 0, 2, st);
   launch_pair_count(sc, w, st);
   exclusive_scan(w.bin_cnt, w.bin_ptr, nbins, w.scan_tmp, st);
+  launch_nonzero_bins(sc, w, nbins, st);
   UCOV_TRY(check_hip(c, "point kernels"));
   // the pair count sizes the next buffer: one host round trip
   hipMemcpyAsync(c->i64_host, w.bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, st);
@@ -217,6 +218,7 @@ SceneWork scene_work(ucov_ctx *c) {
   w.pairs = as<int2>(c->pairs);
   w.nzlist = as<int2>(c->nzlist);
   w.nzcount = as<int64_t>(c->nzcount);
+  w.nzpos = as<int64_t>(c->nzpos);
   w.zdiag = as<double>(c->zdiag);
   w.hc = as<double>(c->hc);
   w.q = as<double>(c->q);
@@ -394,7 +396,7 @@ void ucov_destroy(ucov_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_obs, &c->slot_cam, &c->slot_pt,
-                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount,
+                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount, &c->nzpos,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,

@@ -74,8 +74,9 @@ struct SceneWork {
   int64_t *bin_ptr;   // nbins + 1
   int32_t *bin_cur;   // nbins
   int2 *pairs;        // n_pairs (slot a of camera i, slot b of camera k)
-  int2 *nzlist;       // (i, k) of every non-empty bin, in arbitrary order
+  int2 *nzlist;       // (i, k) of every non-empty bin, in bin order
   int64_t *nzcount;   // [0]: number of non-empty bins
+  int64_t *nzpos;     // nbins + 1: exclusive scan of the non-empty flags
   // per camera
   double *zdiag;      // n x 81, diagonal blocks of Z (row-major)
   double *hc;         // N x 7 column-major (ld N)
@@ -104,6 +105,8 @@ void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *
                       DevStatus *ds, hipStream_t st);
 void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st);
+// nzlist / nzcount from bin_cnt (needs bin_cur as scratch; leaves it zero)
+void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStream_t st);
 void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st);
 void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 // Orthonormal Q (Cholesky-QR2 of hc; skipped when hc is null and q is given),
