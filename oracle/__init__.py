@@ -26,6 +26,8 @@ Modules, in the order of the paper's method:
 * ``paper_gauge`` the paper's own gauge, (M^+)_cc: the definition on the dense
                  M, and the points eliminated with the full nullspace
                  (Sec. 4, Sec. 5.2)
+* ``subrecon``   sub-reconstructions (Sec. 6): per-group sub-scenes, each solved
+                 exactly, the minimum-trace block per camera
 * ``screener``   the learned screener's reference: per-camera features, the
                  log-Cholesky label transform, an FP64 MLP with its gradient,
                  and Adam (not part of the paper; its labels are the exact

@@ -391,3 +391,54 @@ def mlp_init(seed: int, layers=(55, 256, 256, 256, 45)) -> np.ndarray:
         parts.append(rng.normal(0.0, math.sqrt(2.0 / i), o * i))
         parts.append(np.zeros(o))
     return np.concatenate(parts)
+
+
+def view_graph_partition(scene: Scene, k: int, seed: int) -> np.ndarray:
+    """Group ids (n_cams,) of a decomposition into connected groups of about
+    k cameras: breadth-first growth on the covisibility graph (cameras that
+    share a point) from seeded random start cameras; a last group smaller
+    than k / 2 joins the neighbouring group it shares most points with.
+    Used as the decomposition input of sub-reconstruction runs."""
+    n = scene.n_cams
+    by_pt = {}
+    for c, j in zip(scene.obs_cam.tolist(), scene.obs_pt.tolist()):
+        by_pt.setdefault(j, []).append(c)
+    adj = [dict() for _ in range(n)]
+    for cams in by_pt.values():
+        for a in cams:
+            for b in cams:
+                if a != b:
+                    adj[a][b] = adj[a].get(b, 0) + 1
+    rng = np.random.default_rng(seed)
+    group = np.full(n, -1, dtype=np.int64)
+    sizes = []
+    for start in rng.permutation(n):
+        if group[start] >= 0:
+            continue
+        gid = len(sizes)
+        group[start] = gid
+        members, head = [int(start)], 0
+        while head < len(members) and len(members) < k:
+            cur = members[head]
+            head += 1
+            # strongest links first, then camera id, for a deterministic order
+            for nb, _ in sorted(adj[cur].items(), key=lambda kv: (-kv[1], kv[0])):
+                if group[nb] < 0 and len(members) < k:
+                    group[nb] = gid
+                    members.append(nb)
+        sizes.append(len(members))
+    # small groups join the neighbouring group they share most points with
+    for gid, size in enumerate(sizes):
+        if size >= max(2, k // 2):
+            continue
+        mine = np.flatnonzero(group == gid)
+        links = {}
+        for a in mine.tolist():
+            for b, w in adj[a].items():
+                if group[b] != gid:
+                    links[group[b]] = links.get(group[b], 0) + w
+        if links:
+            target = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+            group[mine] = target
+    _, dense = np.unique(group, return_inverse=True)
+    return dense.astype(np.int32)
