@@ -165,6 +165,27 @@ int ucov_camera_covariance_batched(ucov_ctx *ctx, int32_t n_scenes, const ucov_s
                                    const ucov_options *opt, double *cov_out, double *alphas,
                                    ucov_report *rep);
 
+/* Sub-reconstructions (Sec. 6): each camera's covariance evaluated from
+ * sub-reconstructions around it instead of the whole scene.  A sub-
+ * reconstruction is a group of cameras with the points that at least two of
+ * its cameras observe and those observations; each is solved exactly on its
+ * own gauge (one batched call for all of them).  The scene is decomposed
+ * n_decomp times and every camera keeps the block with the smallest trace
+ * among the sub-reconstructions that contain it.
+ * groups: HOST array n_decomp x n_cams; groups[d * n_cams + i] is camera i's
+ * group in decomposition d (any ids in [0, n_cams)); every group needs at
+ * least two cameras and a connected, non-degenerate sub-scene, else the
+ * batched call's error is returned with rep->bad_scene naming the
+ * sub-reconstruction (in the order decomposition, then group by its first
+ * camera).
+ * cov_out: n_cams x 81 as in ucov_camera_covariance.  chosen: HOST array of
+ * n_cams receiving the decomposition whose block was kept, or NULL.  n_sub:
+ * HOST, receives the number of sub-reconstructions, or NULL.  opt as for
+ * ucov_camera_covariance_batched. */
+int ucov_subrecon_covariance(ucov_ctx *ctx, const ucov_scene *scene, int32_t n_decomp,
+                             const int32_t *groups, const ucov_options *opt, double *cov_out,
+                             int32_t *chosen, int32_t *n_sub, ucov_report *rep);
+
 /* Step a1 alone: per-observation Jacobian blocks of the projection (Sec. 5.1),
  * in the caller's observation order, unweighted by obs_info.
  * jp: n_obs x 18 (2x9 row-major per observation, columns r, C, f, k1, k2);

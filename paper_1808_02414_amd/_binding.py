@@ -51,7 +51,7 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error",
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
-           "ucov_screener_covariance", "ucov_plan_check"]
+           "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -92,6 +92,9 @@ def load(path: str = LIB_PATH):
         "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
         "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
         "ucov_plan_check": (ctypes.c_int, [P, I32, P]),
+        "ucov_subrecon_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), I32, P,
+                                                    ctypes.POINTER(Options), P, P, P,
+                                                    ctypes.POINTER(Report)]),
         "ucov_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ucov_last_error": (ctypes.c_char_p, [P]),
     }
@@ -234,6 +237,26 @@ class Context:
             views.append(out[o:o + n])
             o += n
         return views, list(alphas), rep.as_dict()
+
+    def subrecon_covariance(self, scene: DeviceScene, groups, alpha=0.0):
+        """Per-camera blocks from sub-reconstructions: groups is an
+        (n_decomp, n_cams) integer array of group ids; returns the (n, 9, 9)
+        minimum-trace blocks, the decomposition chosen per camera, the number of
+        sub-reconstructions and the report of the batched solve."""
+        torch = self.torch
+        g = np.ascontiguousarray(np.asarray(groups, dtype=np.int32).reshape(-1, scene.n_cams))
+        out = torch.empty((scene.n_cams, 9, 9), dtype=torch.float64, device=scene.cams.device)
+        chosen = np.zeros(scene.n_cams, dtype=np.int32)
+        n_sub = ctypes.c_int32(0)
+        opt = Options(FP64, 0, 0.0, alpha, GAUGE_CAMERA)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        rc = self.lib.ucov_subrecon_covariance(
+            self.h, ctypes.byref(sc), g.shape[0], g.ctypes.data, ctypes.byref(opt), out.data_ptr(),
+            chosen.ctypes.data, ctypes.byref(n_sub), ctypes.byref(rep))
+        self._check(rc, rep)
+        return out, chosen, int(n_sub.value), rep.as_dict()
 
     def jacobians(self, scene: DeviceScene):
         torch = self.torch

@@ -1260,6 +1260,60 @@ void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *
   hipLaunchKernelGGL(k_paper_p, dim3(1), dim3(1024), 0, st, N, f, w.q, w.alpha, ds);
 }
 
+// ---------------------------------------------------------------------------
+// sub-reconstructions (Sec. 6): gather sub-scenes out of a parent scene and
+// keep, per parent camera, the candidate block with the smallest trace
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void k_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam_src,
+                                   const int32_t *pt_src, const int32_t *obs_src,
+                                   const double *pcams, const double *ppts, const double *pinfo,
+                                   double *cams, double *pts, double *info) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 9 * n) cams[i] = pcams[9 * (int64_t)cam_src[i / 9] + i % 9];
+  if (i < 3 * m) pts[i] = ppts[3 * (int64_t)pt_src[i / 3] + i % 3];
+  if (pinfo && i < 3 * t) info[i] = pinfo[3 * (int64_t)obs_src[i / 3] + i % 3];
+}
+
+// pos[d * n + c]: row of parent camera c's block in decomposition d
+__global__ void k_min_trace(int64_t n, int n_decomp, const int32_t *pos, const double *cand,
+                            double *cov, int32_t *chosen) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int best = -1;
+  double bt = 0.0;
+  for (int d = 0; d < n_decomp; ++d) {
+    const double *b = cand + 81 * (int64_t)pos[(int64_t)d * n + c];
+    double tr = 0.0;
+    for (int a = 0; a < 9; ++a) tr += b[10 * a];
+    if (best < 0 || tr < bt) {
+      best = d;
+      bt = tr;
+    }
+  }
+  const double *b = cand + 81 * (int64_t)pos[(int64_t)best * n + c];
+  for (int k = 0; k < 81; ++k) cov[81 * c + k] = b[k];
+  if (chosen) chosen[c] = best;
+}
+
+}  // namespace
+
+void launch_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam_src,
+                             const int32_t *pt_src, const int32_t *obs_src, const double *pcams,
+                             const double *ppts, const double *pinfo, double *cams, double *pts,
+                             double *info, hipStream_t st) {
+  const int64_t len = std::max({9 * n, 3 * m, pinfo ? 3 * t : (int64_t)0});
+  hipLaunchKernelGGL(k_gather_subscenes, dim3(blocks_for(len, kBlk)), dim3(kBlk), 0, st, n, m, t,
+                     cam_src, pt_src, obs_src, pcams, ppts, pinfo, cams, pts, info);
+}
+
+void launch_min_trace(int64_t n, int n_decomp, const int32_t *pos, const double *cand,
+                      double *cov, int32_t *chosen, hipStream_t st) {
+  hipLaunchKernelGGL(k_min_trace, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, st, n, n_decomp, pos,
+                     cand, cov, chosen);
+}
+
 void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const double *zdiag,
                          double user_alpha, double *s, double *alpha, DevStatus *ds,
                          hipStream_t st) {

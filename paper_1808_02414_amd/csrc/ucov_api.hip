@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "ucov_internal.h"
@@ -57,6 +58,8 @@ struct ucov_ctx {
   // learned screener
   Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
   Buf pg_f;  // the paper gauge's 7 x 7 F (28 values)
+  // sub-reconstructions: index maps, the gathered sub-scenes and their blocks
+  Buf sr_idx, sr_cams, sr_pts, sr_info, sr_cand, sr_chosen;
 
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
@@ -401,7 +404,8 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
-                 &c->mlp_ws, &c->mlp_grad, &c->pg_f};
+                 &c->mlp_ws, &c->mlp_grad, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
+                 &c->sr_info, &c->sr_cand, &c->sr_chosen};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   if (c->h_stage) hipHostFree(c->h_stage);
@@ -758,6 +762,139 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
     hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
     rep->ms_extract = 0.0f;
   }
+  return UCOV_OK;
+}
+
+// ---- sub-reconstructions (Sec. 6) --------------------------------------------
+
+int ucov_subrecon_covariance(ucov_ctx *c, const ucov_scene *scene, int32_t n_decomp,
+                             const int32_t *groups, const ucov_options *opt, double *cov_out,
+                             int32_t *chosen, int32_t *n_sub, ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  reset_report(rep);
+  UCOV_TRY(check_scene(c, scene));
+  if (n_decomp < 1 || !groups || !cov_out) return c->fail(UCOV_EINVAL, "bad sub-reconstruction arguments");
+  const int64_t n = scene->n_cams, m = scene->n_pts, t = scene->n_obs;
+  for (int64_t k = 0; k < (int64_t)n_decomp * n; ++k)
+    if (groups[k] < 0 || groups[k] >= n) return c->fail(UCOV_EINVAL, "group id out of range");
+  hipSetDevice(c->device);
+  hipStream_t st = c->stream;
+  // the observation indices on the host, checked before any use
+  std::vector<int32_t> oc(t), op(t);
+  if (hipMemcpyAsync(oc.data(), scene->obs_cam, 4 * t, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(op.data(), scene->obs_pt, 4 * t, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_hip(c, "sub-reconstruction indices");
+  for (int64_t o = 0; o < t; ++o)
+    if (oc[o] < 0 || oc[o] >= n || op[o] < 0 || op[o] >= m) {
+      if (rep) rep->bad_index = (int32_t)o;
+      return c->fail(UCOV_EINVAL, "observation index out of range");
+    }
+  // sub-scenes in the order (decomposition, group by first appearance)
+  std::vector<int32_t> cam_src, pt_src, obs_src, loc_c, loc_p, pos((size_t)n_decomp * n);
+  std::vector<int64_t> cam_off{0}, pt_off{0}, obs_off{0};
+  std::vector<int32_t> slot(n), order(t);
+  for (int d = 0; d < n_decomp; ++d) {
+    const int32_t *g = groups + (int64_t)d * n;
+    std::vector<int32_t> gidx(n, -1), first;  // group id -> sub-scene of this decomposition
+    std::vector<std::vector<int32_t>> members;
+    for (int64_t cam = 0; cam < n; ++cam) {
+      if (gidx[g[cam]] < 0) {
+        gidx[g[cam]] = (int32_t)members.size();
+        members.emplace_back();
+      }
+      const int sub = gidx[g[cam]];
+      slot[cam] = (int32_t)members[sub].size();
+      members[sub].push_back((int32_t)cam);
+    }
+    // observations grouped by (sub-scene, point); a point is kept in a
+    // sub-scene when at least two of its observations fall inside it
+    for (int64_t o = 0; o < t; ++o) order[o] = (int32_t)o;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      const int gx = gidx[g[oc[x]]], gy = gidx[g[oc[y]]];
+      return gx != gy ? gx < gy : op[x] < op[y];
+    });
+    std::vector<std::vector<int32_t>> keep_obs(members.size()), keep_pts(members.size());
+    for (int64_t a = 0; a < t;) {
+      const int sub = gidx[g[oc[order[a]]]];
+      int64_t b = a;
+      while (b < t && gidx[g[oc[order[b]]]] == sub && op[order[b]] == op[order[a]]) ++b;
+      if (b - a >= 2) {
+        keep_pts[sub].push_back(op[order[a]]);
+        for (int64_t e = a; e < b; ++e) keep_obs[sub].push_back(order[e]);
+      }
+      a = b;
+    }
+    for (size_t sub = 0; sub < members.size(); ++sub) {
+      const int64_t c0 = (int64_t)cam_src.size();
+      for (int32_t cam : members[sub]) {
+        pos[(size_t)d * n + cam] = (int32_t)cam_src.size();
+        cam_src.push_back(cam);
+      }
+      std::unordered_map<int32_t, int32_t> lp;
+      lp.reserve(keep_pts[sub].size() * 2);
+      for (int32_t j : keep_pts[sub]) {
+        lp[j] = (int32_t)(pt_src.size() - pt_off.back());
+        pt_src.push_back(j);
+      }
+      for (int32_t o : keep_obs[sub]) {
+        obs_src.push_back(o);
+        loc_c.push_back(slot[oc[o]]);
+        loc_p.push_back(lp[op[o]]);
+      }
+      (void)c0;
+      cam_off.push_back((int64_t)cam_src.size());
+      pt_off.push_back((int64_t)pt_src.size());
+      obs_off.push_back((int64_t)obs_src.size());
+    }
+  }
+  const int S = (int)cam_off.size() - 1;
+  const int64_t nt = cam_off.back(), mt = pt_off.back(), tt = obs_off.back();
+  if (n_sub) *n_sub = S;
+  // index maps to the device in one buffer: cam_src | pt_src | obs_src | loc_c | loc_p | pos
+  const int64_t ni = nt + mt + 3 * tt + (int64_t)n_decomp * n;
+  UCOV_TRY(ensure(c, c->sr_idx, 4 * (size_t)ni));
+  int32_t *idx = as<int32_t>(c->sr_idx);
+  int32_t *d_cam_src = idx, *d_pt_src = d_cam_src + nt, *d_obs_src = d_pt_src + mt,
+          *d_loc_c = d_obs_src + tt, *d_loc_p = d_loc_c + tt, *d_pos = d_loc_p + tt;
+  const std::pair<const std::vector<int32_t> *, int32_t *> up[] = {
+      {&cam_src, d_cam_src}, {&pt_src, d_pt_src}, {&obs_src, d_obs_src},
+      {&loc_c, d_loc_c},     {&loc_p, d_loc_p},   {&pos, d_pos}};
+  for (const auto &u : up)
+    if (!u.first->empty() &&
+        hipMemcpyAsync(u.second, u.first->data(), 4 * u.first->size(), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+      return check_hip(c, "sub-reconstruction index upload");
+  UCOV_TRY(ensure(c, c->sr_cams, 8 * 9 * (size_t)nt));
+  UCOV_TRY(ensure(c, c->sr_pts, 8 * 3 * (size_t)mt));
+  if (scene->obs_info) UCOV_TRY(ensure(c, c->sr_info, 8 * 3 * (size_t)tt));
+  launch_gather_subscenes(nt, mt, tt, d_cam_src, d_pt_src, d_obs_src, scene->cams, scene->pts,
+                          scene->obs_info, as<double>(c->sr_cams), as<double>(c->sr_pts),
+                          scene->obs_info ? as<double>(c->sr_info) : nullptr, st);
+  UCOV_TRY(check_hip(c, "sub-scene gather"));
+  std::vector<ucov_scene> subs(S);
+  for (int k = 0; k < S; ++k) {
+    subs[k].n_cams = (int32_t)(cam_off[k + 1] - cam_off[k]);
+    subs[k].n_pts = (int32_t)(pt_off[k + 1] - pt_off[k]);
+    subs[k].n_obs = obs_off[k + 1] - obs_off[k];
+    subs[k].cams = as<double>(c->sr_cams) + 9 * cam_off[k];
+    subs[k].pts = as<double>(c->sr_pts) + 3 * pt_off[k];
+    subs[k].obs_cam = d_loc_c + obs_off[k];
+    subs[k].obs_pt = d_loc_p + obs_off[k];
+    subs[k].obs_info = scene->obs_info ? as<double>(c->sr_info) + 3 * obs_off[k] : nullptr;
+  }
+  UCOV_TRY(ensure(c, c->sr_cand, 8 * 81 * (size_t)nt));
+  UCOV_TRY(ucov_camera_covariance_batched(c, S, subs.data(), opt, as<double>(c->sr_cand),
+                                          nullptr, rep));
+  int32_t *d_chosen = nullptr;
+  if (chosen) {
+    UCOV_TRY(ensure(c, c->sr_chosen, 4 * (size_t)n));
+    d_chosen = as<int32_t>(c->sr_chosen);
+  }
+  launch_min_trace(n, n_decomp, d_pos, as<double>(c->sr_cand), cov_out, d_chosen, st);
+  if (chosen) hipMemcpyAsync(chosen, d_chosen, 4 * (size_t)n, hipMemcpyDeviceToHost, st);
+  UCOV_TRY(check_hip(c, "minimum-trace choice"));
+  if (hipStreamSynchronize(st) != hipSuccess) return check_hip(c, "sub-reconstructions");
   return UCOV_OK;
 }
 

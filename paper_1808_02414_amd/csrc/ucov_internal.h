@@ -131,6 +131,17 @@ void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
                      int64_t n_nonzero, hipStream_t st);
 
+// Sub-reconstructions: sub-scene arrays gathered from a parent scene through
+// index maps (camera, point and, when pinfo is set, observation of the parent
+// for every row of the concatenation), and the minimum-trace choice per parent
+// camera among n_decomp candidate blocks (pos: n_decomp x n rows of cand).
+void launch_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam_src,
+                             const int32_t *pt_src, const int32_t *obs_src, const double *pcams,
+                             const double *ppts, const double *pinfo, double *cams, double *pts,
+                             double *info, hipStream_t st);
+void launch_min_trace(int64_t n, int n_decomp, const int32_t *pos, const double *cand,
+                      double *cov, int32_t *chosen, hipStream_t st);
+
 // ---- learned screener (screener_kernels.hip) -------------------------------
 // Per-camera features (n x 55 FP32) from the scene stage's data; hist (8 n),
 // ang (n) and covis (n) are scratch.

@@ -393,15 +393,25 @@ def mlp_init(seed: int, layers=(55, 256, 256, 256, 45)) -> np.ndarray:
     return np.concatenate(parts)
 
 
-def view_graph_partition(scene: Scene, k: int, seed: int) -> np.ndarray:
-    """Group ids (n_cams,) of a decomposition into connected groups of about
-    k cameras: breadth-first growth on the covisibility graph (cameras that
-    share a point) from seeded random start cameras; a last group smaller
-    than k / 2 joins the neighbouring group it shares most points with.
-    Used as the decomposition input of sub-reconstruction runs."""
+def view_graph_partition(scene: Scene, k: int, seed: int, min_shared: int = 8,
+                         min_support: int = 10) -> np.ndarray:
+    """Group ids (n_cams,) of a decomposition into groups of about k cameras
+    whose sub-reconstructions are well posed.
+
+    Two cameras are strongly linked when they share at least ``min_shared``
+    points.  A group grows from a seeded random start camera by adding the
+    unassigned camera with the most points shared with the group along strong
+    links; a group left smaller than k / 2 joins the strongly linked
+    neighbour it shares most points with.  Then, until nothing changes, a
+    camera that sees fewer than ``min_support`` points together with another
+    camera of its group moves to the neighbouring group where it sees the
+    most, and every strongly connected piece of a group but its largest moves
+    to the group it shares most points with.  Used as the decomposition input
+    of sub-reconstruction runs."""
     n = scene.n_cams
+    oc, op = scene.obs_cam.astype(np.int64), scene.obs_pt.astype(np.int64)
     by_pt = {}
-    for c, j in zip(scene.obs_cam.tolist(), scene.obs_pt.tolist()):
+    for c, j in zip(oc.tolist(), op.tolist()):
         by_pt.setdefault(j, []).append(c)
     adj = [dict() for _ in range(n)]
     for cams in by_pt.values():
@@ -409,6 +419,10 @@ def view_graph_partition(scene: Scene, k: int, seed: int) -> np.ndarray:
             for b in cams:
                 if a != b:
                     adj[a][b] = adj[a].get(b, 0) + 1
+    strong = [{b: w for b, w in adj[a].items() if w >= min_shared} for a in range(n)]
+    cam_pts = [[] for _ in range(n)]
+    for c, j in zip(oc.tolist(), op.tolist()):
+        cam_pts[c].append(j)
     rng = np.random.default_rng(seed)
     group = np.full(n, -1, dtype=np.int64)
     sizes = []
@@ -417,28 +431,77 @@ def view_graph_partition(scene: Scene, k: int, seed: int) -> np.ndarray:
             continue
         gid = len(sizes)
         group[start] = gid
-        members, head = [int(start)], 0
-        while head < len(members) and len(members) < k:
-            cur = members[head]
-            head += 1
-            # strongest links first, then camera id, for a deterministic order
-            for nb, _ in sorted(adj[cur].items(), key=lambda kv: (-kv[1], kv[0])):
-                if group[nb] < 0 and len(members) < k:
-                    group[nb] = gid
-                    members.append(nb)
-        sizes.append(len(members))
-    # small groups join the neighbouring group they share most points with
+        size = 1
+        score = {}
+        for b, w in strong[int(start)].items():
+            if group[b] < 0:
+                score[b] = score.get(b, 0) + w
+        while size < k and score:
+            nxt = max(score.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+            del score[nxt]
+            group[nxt] = gid
+            size += 1
+            for b, w in strong[nxt].items():
+                if group[b] < 0:
+                    score[b] = score.get(b, 0) + w
+        sizes.append(size)
+
+    def links_of(cams, own):
+        links = {}
+        for a in cams:
+            for b, w in adj[a].items():
+                if group[b] != own:
+                    links[group[b]] = links.get(group[b], 0) + w
+        return links
+
     for gid, size in enumerate(sizes):
         if size >= max(2, k // 2):
             continue
-        mine = np.flatnonzero(group == gid)
-        links = {}
-        for a in mine.tolist():
-            for b, w in adj[a].items():
-                if group[b] != gid:
-                    links[group[b]] = links.get(group[b], 0) + w
+        mine = np.flatnonzero(group == gid).tolist()
+        links = links_of(mine, gid)
         if links:
-            target = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
-            group[mine] = target
+            group[mine] = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+
+    def support(c, g):
+        # points camera c sees together with another camera of group g
+        return sum(1 for j in cam_pts[c] if any(group[b] == g and b != c for b in by_pt[j]))
+
+    for _ in range(20):
+        changed = False
+        for c in range(n):
+            own = support(c, group[c])
+            if own >= min_support:
+                continue
+            cand = {group[b] for b in adj[c]} - {group[c]}
+            best = max(cand, key=lambda g: (support(c, g), -g), default=None)
+            if best is not None and support(c, best) > own:
+                group[c] = best
+                changed = True
+        for gid in np.unique(group).tolist():
+            mine = set(np.flatnonzero(group == gid).tolist())
+            pieces, seen = [], set()
+            for c0 in sorted(mine):
+                if c0 in seen:
+                    continue
+                piece, stack = [], [c0]
+                seen.add(c0)
+                while stack:
+                    a = stack.pop()
+                    piece.append(a)
+                    for b in strong[a]:
+                        if b in mine and b not in seen:
+                            seen.add(b)
+                            stack.append(b)
+                pieces.append(piece)
+            if len(pieces) < 2:
+                continue
+            pieces.sort(key=len, reverse=True)
+            for piece in pieces[1:]:
+                links = links_of(piece, gid)
+                if links:
+                    group[piece] = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+                    changed = True
+        if not changed:
+            break
     _, dense = np.unique(group, return_inverse=True)
     return dense.astype(np.int32)

@@ -39,3 +39,16 @@ def test_min_trace_choice_and_partition_properties():
     tr = np.trace(cand, axis1=2, axis2=3)
     assert np.all(np.trace(blocks, axis1=1, axis2=2) <= tr.min(axis=0) * (1 + 1e-12))
     assert np.array_equal(blocks, cand[chosen, np.arange(s.n_cams)])
+
+
+def test_partition_groups_determine_their_cameras():
+    """Every camera of a group sees at least 10 points with another camera of
+    its group, and every group has at least two cameras."""
+    from oracle.subrecon import subscene
+    s = sg.spiral_slab(0)
+    for k, seed in ((100, 0), (25, 10)):
+        g = sg.view_graph_partition(s, k, seed=seed)
+        assert np.bincount(g).min() >= 2
+        for gid in range(g.max() + 1):
+            sub = subscene(s, np.flatnonzero(g == gid))
+            assert np.bincount(sub.obs_cam, minlength=sub.n_cams).min() >= 10, (k, gid)
