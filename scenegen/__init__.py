@@ -399,15 +399,22 @@ def view_graph_partition(scene: Scene, k: int, seed: int, min_shared: int = 8,
     whose sub-reconstructions are well posed.
 
     Two cameras are strongly linked when they share at least ``min_shared``
-    points.  A group grows from a seeded random start camera by adding the
-    unassigned camera with the most points shared with the group along strong
-    links; a group left smaller than k / 2 joins the strongly linked
-    neighbour it shares most points with.  Then, until nothing changes, a
-    camera that sees fewer than ``min_support`` points together with another
-    camera of its group moves to the neighbouring group where it sees the
-    most, and every strongly connected piece of a group but its largest moves
-    to the group it shares most points with.  Used as the decomposition input
-    of sub-reconstruction runs."""
+    points.  round(n / k) seeds are spread over the view graph (a seeded
+    random camera, then each time a camera farthest in strong-link hops from
+    all seeds so far); the groups then grow together, in turn, each adding
+    the unassigned camera with the most points shared with it along strong
+    links.  A group left smaller than k / 2 joins the strongly linked
+    neighbour it shares most points with.  Then, until nothing changes, every
+    group registers its cameras as incremental reconstruction would (the
+    pair sharing most points first, then any camera that sees at least
+    ``min_support`` points already seen by two registered cameras), and a
+    camera left unregistered moves to the neighbouring group whose
+    registered cameras fix more of its points.  A camera attached to its
+    group only through points it shares with a single other camera, or a
+    chain of cameras hanging from one camera, would leave the length of a
+    baseline free: the sub-reconstruction would have a null space larger
+    than the similarity gauge.  Used as the decomposition input of
+    sub-reconstruction runs."""
     n = scene.n_cams
     oc, op = scene.obs_cam.astype(np.int64), scene.obs_pt.astype(np.int64)
     by_pt = {}
@@ -425,26 +432,66 @@ def view_graph_partition(scene: Scene, k: int, seed: int, min_shared: int = 8,
         cam_pts[c].append(j)
     rng = np.random.default_rng(seed)
     group = np.full(n, -1, dtype=np.int64)
-    sizes = []
-    for start in rng.permutation(n):
-        if group[start] >= 0:
-            continue
-        gid = len(sizes)
-        group[start] = gid
-        size = 1
-        score = {}
-        for b, w in strong[int(start)].items():
+    # seeds: a random camera, then repeatedly the camera farthest (in hops
+    # along strong links) from every seed so far
+    n_groups = max(1, int(round(n / k)))
+    hops = np.full(n, np.iinfo(np.int64).max, dtype=np.int64)
+    seeds = []
+    nxt_seed = int(rng.integers(n))
+    for _ in range(n_groups):
+        seeds.append(nxt_seed)
+        hops[nxt_seed] = 0
+        frontier = [nxt_seed]
+        d = 0
+        while frontier:
+            d += 1
+            new = []
+            for a in frontier:
+                for b in strong[a]:
+                    if hops[b] > d:
+                        hops[b] = d
+                        new.append(b)
+            frontier = new
+        far = np.flatnonzero(hops == hops.max())
+        nxt_seed = int(far[rng.integers(far.size)])
+    # all groups grow together, one camera per group in turn, each taking the
+    # unassigned camera that shares the most points with it along strong links
+    scores = [{} for _ in seeds]
+    sizes = [0] * len(seeds)
+
+    def take(gid, c):
+        group[c] = gid
+        sizes[gid] += 1
+        for b, w in strong[c].items():
             if group[b] < 0:
-                score[b] = score.get(b, 0) + w
-        while size < k and score:
-            nxt = max(score.items(), key=lambda kv: (kv[1], -kv[0]))[0]
-            del score[nxt]
-            group[nxt] = gid
-            size += 1
-            for b, w in strong[nxt].items():
+                scores[gid][b] = scores[gid].get(b, 0) + w
+
+    for gid, c in enumerate(seeds):
+        take(gid, c)
+    active = True
+    while active:
+        active = False
+        for gid in range(len(seeds)):
+            sc = scores[gid]
+            while sc:
+                c, _ = max(sc.items(), key=lambda kv: (kv[1], -kv[0]))
+                del sc[c]
+                if group[c] < 0:
+                    take(gid, c)
+                    active = True
+                    break
+    # cameras no strong link reaches start groups of their own
+    for c in np.flatnonzero(group < 0).tolist():
+        if group[c] < 0:
+            sizes.append(0)
+            scores.append({})
+            gid = len(sizes) - 1
+            take(gid, c)
+            while scores[gid] and sizes[gid] < k:
+                b, _ = max(scores[gid].items(), key=lambda kv: (kv[1], -kv[0]))
+                del scores[gid][b]
                 if group[b] < 0:
-                    score[b] = score.get(b, 0) + w
-        sizes.append(size)
+                    take(gid, b)
 
     def links_of(cams, own):
         links = {}
@@ -462,44 +509,56 @@ def view_graph_partition(scene: Scene, k: int, seed: int, min_shared: int = 8,
         if links:
             group[mine] = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
 
-    def support(c, g):
-        # points camera c sees together with another camera of group g
-        return sum(1 for j in cam_pts[c] if any(group[b] == g and b != c for b in by_pt[j]))
+    def rigid_core(members):
+        # cameras registered as in incremental reconstruction: the pair that
+        # shares most points, then repeatedly the camera that sees the most
+        # points already seen by two registered cameras, while it sees at
+        # least min_support of them
+        mem = set(members)
+        pair = max(((w, a, b) for a in members for b, w in adj[a].items() if b in mem and a < b),
+                   default=None)
+        if pair is None:
+            return set(), set()
+        core = set()
+        seen, fixed, cnt = {}, set(), {c: 0 for c in members}
+
+        def register(c):
+            core.add(c)
+            for j in cam_pts[c]:
+                seen[j] = seen.get(j, 0) + 1
+                if seen[j] == 2:
+                    fixed.add(j)
+                    for b in by_pt[j]:
+                        if b in mem and b not in core:
+                            cnt[b] += 1
+
+        register(pair[1])
+        register(pair[2])
+        while True:
+            rest = [c for c in members if c not in core]
+            if not rest:
+                break
+            c = max(rest, key=lambda c: (cnt[c], -c))
+            if cnt[c] < min_support:
+                break
+            register(c)
+        return core, fixed
 
     for _ in range(20):
         changed = False
-        for c in range(n):
-            own = support(c, group[c])
-            if own >= min_support:
-                continue
-            cand = {group[b] for b in adj[c]} - {group[c]}
-            best = max(cand, key=lambda g: (support(c, g), -g), default=None)
-            if best is not None and support(c, best) > own:
-                group[c] = best
-                changed = True
-        for gid in np.unique(group).tolist():
-            mine = set(np.flatnonzero(group == gid).tolist())
-            pieces, seen = [], set()
-            for c0 in sorted(mine):
-                if c0 in seen:
+        gids = np.unique(group).tolist()
+        cores = {g: rigid_core(np.flatnonzero(group == g).tolist()) for g in gids}
+        for g in gids:
+            core, _ = cores[g]
+            for c in np.flatnonzero(group == g).tolist():
+                if c in core:
                     continue
-                piece, stack = [], [c0]
-                seen.add(c0)
-                while stack:
-                    a = stack.pop()
-                    piece.append(a)
-                    for b in strong[a]:
-                        if b in mine and b not in seen:
-                            seen.add(b)
-                            stack.append(b)
-                pieces.append(piece)
-            if len(pieces) < 2:
-                continue
-            pieces.sort(key=len, reverse=True)
-            for piece in pieces[1:]:
-                links = links_of(piece, gid)
-                if links:
-                    group[piece] = max(links.items(), key=lambda kv: (kv[1], -kv[0]))[0]
+                own = sum(1 for j in cam_pts[c] if j in cores[g][1])
+                cand = {group[b] for b in adj[c]} - {g}
+                best = max(cand, key=lambda h: (sum(1 for j in cam_pts[c] if j in cores[h][1]), -h),
+                           default=None)
+                if best is not None and sum(1 for j in cam_pts[c] if j in cores[best][1]) > own:
+                    group[c] = best
                     changed = True
         if not changed:
             break
