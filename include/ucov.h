@@ -144,6 +144,26 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
                            const ucov_options *opt, double *cov_out,
                            ucov_report *rep);
 
+/* The whole camera covariance and the covariance of every point (Sec. 5.2:
+ * the points are eliminated by block inversion, M = L diag(Z, V) L^T with
+ * L = [[I, W V^-1], [0, I]], and their blocks recovered from the camera
+ * covariance X; the sum runs over the point's observations only).
+ *   UCOV_GAUGE_CAMERA: X = Z^+ and the block of point j is
+ *     V_j^-1 + V_j^-1 W_j^T Z^+ W_j V_j^-1
+ *     (the generalised inverse of M whose null space holds the similarity
+ *     directions of the cameras alone);
+ *   UCOV_GAUGE_PAPER: X = (M^+)_cc and the block is the point block of M^+.
+ * cam_cov: N x N float64 column-major with leading dimension ldc >= N
+ * (N = 9 n_cams), both triangles, or NULL; its diagonal blocks are those of
+ * ucov_camera_covariance.  pt_cov: n_pts x 9 float64 (row-major 3 x 3 per
+ * point), or NULL; not both NULL (UCOV_EINVAL).  Device arrays.
+ * opt->precision must be UCOV_FP64.  Device workspace: two Np x Np float64
+ * matrices (Np = N rounded up to 64) besides the scene's.
+ * rep: ms_inverse covers the factorisation and the product L^-T L^-1,
+ * ms_extract the output kernels. */
+int ucov_full_covariance(ucov_ctx *ctx, const ucov_scene *scene, const ucov_options *opt,
+                         double *cam_cov, int64_t ldc, double *pt_cov, ucov_report *rep);
+
 /* Covariance blocks of several independent scenes in one call: the
  * sub-reconstructions of Sec. 6, each evaluated exactly on its own gauge (a
  * camera's covariance from a sub-reconstruction around it bounds the one from

@@ -60,9 +60,10 @@ def _normal(scene):
     return oc, op, n, m, JP, JX, Lam, U, V, W
 
 
-def structured(scene, gauge="camera"):
+def structured(scene, gauge="camera", select=None):
     """Whole camera covariance (N x N) and point blocks (m, 3, 3) by the
-    block-inversion route."""
+    block-inversion route; ``select`` (point indices) restricts the point
+    blocks to those points, in that order."""
     if gauge not in GAUGES:
         raise ValueError(gauge)
     oc, op, n, m, JP, JX, Lam, U, V, W = _normal(scene)
@@ -75,11 +76,12 @@ def structured(scene, gauge="camera"):
         _, G, F = paper_gauge.structured_matrix(scene)
         Hp = nullspace.point_rows(scene.pts).reshape(m, 3, 7)
         Finv = np.linalg.inv(F)
-    pts = np.zeros((m, 3, 3))
+    sel = np.arange(m) if select is None else np.asarray(select)
+    pts = np.zeros((sel.size, 3, 3))
     track = [[] for _ in range(m)]
     for o in range(oc.size):
         track[op[o]].append(o)
-    for j in range(m):
+    for out_i, j in enumerate(sel):
         Wj = np.zeros((N, 3))  # the columns of W of point j
         for o in track[j]:
             Wj[9 * oc[o]:9 * oc[o] + 9] = W[o]
@@ -90,7 +92,7 @@ def structured(scene, gauge="camera"):
             E = (Wj + G @ Finv @ Hp[j].T) @ Vinv[j]
             K = Vinv[j] @ Hp[j] @ Finv @ Hp[j].T @ Vinv[j]
             C = Vinv[j] - K + E.T @ X @ E
-        pts[j] = 0.5 * (C + C.T)
+        pts[out_i] = 0.5 * (C + C.T)
     return 0.5 * (X + X.T), pts
 
 

@@ -51,7 +51,8 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_pinv_blocks", "ucov_strerror", "ucov_last_error",
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
-           "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance"]
+           "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
+           "ucov_full_covariance"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -77,6 +78,8 @@ def load(path: str = LIB_PATH):
         "ucov_camera_covariance_batched": (ctypes.c_int, [P, I32, ctypes.POINTER(Scene),
                                                           ctypes.POINTER(Options), P,
                                                           ctypes.POINTER(D), ctypes.POINTER(Report)]),
+        "ucov_full_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), ctypes.POINTER(Options),
+                                                P, I64, P, ctypes.POINTER(Report)]),
         "ucov_jacobians": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
         "ucov_reduced_camera_matrix": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, I64,
                                                       ctypes.POINTER(Report)]),
@@ -156,6 +159,10 @@ class DeviceScene:
     def n_cams(self):
         return int(self.cams.shape[0])
 
+    @property
+    def n_pts(self):
+        return int(self.pts.shape[0])
+
     def struct(self) -> Scene:
         for a in (self.cams, self.pts, self.obs_cam, self.obs_pt):
             assert a.is_cuda and a.is_contiguous()
@@ -214,6 +221,29 @@ class Context:
                                              out.data_ptr(), ctypes.byref(rep))
         self._check(rc, rep)
         return out, rep.as_dict()
+
+    def full_covariance(self, scene: DeviceScene, cameras=True, points=True, alpha=0.0,
+                        gauge=GAUGE_CAMERA):
+        """The whole camera covariance (N, N) and the point covariances
+        (m, 3, 3) as float64 device tensors (None where not requested), and the
+        report."""
+        torch = self.torch
+        dev = scene.cams.device
+        N = 9 * scene.n_cams
+        cam = torch.empty((N, N), dtype=torch.float64, device=dev) if cameras else None
+        pts = torch.empty((scene.n_pts, 3, 3), dtype=torch.float64, device=dev) if points else None
+        opt = Options(FP64, 0, 0.0, alpha, gauge)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        # column-major N x N with leading dimension N is the row-major tensor's transpose;
+        # the matrix is symmetric
+        rc = self.lib.ucov_full_covariance(self.h, ctypes.byref(sc), ctypes.byref(opt),
+                                           cam.data_ptr() if cam is not None else None, N,
+                                           pts.data_ptr() if pts is not None else None,
+                                           ctypes.byref(rep))
+        self._check(rc, rep)
+        return cam, pts, rep.as_dict()
 
     def camera_covariance_batched(self, scenes, alpha=0.0, out=None):
         """Covariance blocks of independent scenes in one call: a list of

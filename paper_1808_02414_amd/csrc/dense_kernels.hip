@@ -585,6 +585,24 @@ __global__ __launch_bounds__(256) void k_gemm64_pair_b(const GemmArgs<T> *stab,
   }
 }
 
+// Strict upper triangle of an n x n matrix (n a multiple of 32) set from its
+// lower triangle through 32 x 32 LDS tiles: workgroup (tm, tn), tm >= tn,
+// reads tile (tm, tn) with coalesced column loads and writes its transpose
+// at (tn, tm), rows across the lanes.  tile[c][r] holds a(32 tm + r, 32 tn + c).
+__global__ __launch_bounds__(256) void k_mirror_lower(double *a, int64_t lda) {
+  const int64_t tm = blockIdx.x, tn = blockIdx.y;
+  if (tn > tm) return;
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t R0 = 32 * tm, C0 = 32 * tn;
+  for (int c = ty; c < 32; c += 8) tile[c][tx] = a[(R0 + tx) + (C0 + c) * lda];
+  __syncthreads();
+  for (int c = ty; c < 32; c += 8) {
+    const int64_t row = C0 + tx, col = R0 + c;  // a(row, col) = a(col, row) = tile[tx][c]
+    if (row < col) a[row + col * lda] = tile[tx][c];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // elementwise helpers
 // ---------------------------------------------------------------------------
@@ -1202,6 +1220,15 @@ int64_t spd_lower_inverse_scratch(int64_t Np) { return recurse_scratch(Np); }
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st) {
   recurse<double>(a, lda, 0, Np, tmp, ds, st);
+}
+
+void spd_inverse_from_factor(const double *linv, int64_t ld, int64_t Np, double *x, int64_t ldx,
+                             hipStream_t st) {
+  // X = L^-T L^-1 on the tiles on or below the diagonal (diagonal tiles whole),
+  // then the strict upper triangle from the lower one
+  gemm<double, true, false, true>(Np, Np, Np, linv, ld, linv, ld, x, ldx, 1.0, 0.0, kGeMN, st);
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)(Np / 32), (unsigned)(Np / 32)), dim3(256), 0,
+                     st, x, ldx);
 }
 
 void launch_pad_identity_scenes(int n_scenes, int64_t max_np, const int32_t *cam_off,

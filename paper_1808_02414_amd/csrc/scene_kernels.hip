@@ -940,9 +940,10 @@ __global__ __launch_bounds__(256) void k_paper_g(SceneDev sc, const int64_t *bin
   }
 }
 
-// F = L_F L_F^T (one thread), then every row of q replaced by L_F^-1 applied
-// to it (P = G L_F^-T); the gauge weight is 1.
-__global__ __launch_bounds__(1024) void k_paper_p(int64_t N, const double *f, double *q,
+// F = L_F L_F^T (one thread; L_F stored row-major after F's 28 values),
+// then every row of q replaced by L_F^-1 applied to it (P = G L_F^-T); the
+// gauge weight is 1.
+__global__ __launch_bounds__(1024) void k_paper_p(int64_t N, double *f, double *q,
                                                  double *alpha, DevStatus *ds) {
   __shared__ double L[7][7];
   __shared__ int ok;
@@ -971,6 +972,8 @@ __global__ __launch_bounds__(1024) void k_paper_p(int64_t N, const double *f, do
       for (int b = a + 1; b < 7; ++b) L[a][b] = 0.0;
     }
     if (!ok) report_error(ds, UCOV_EGAUGE, -1);
+    for (int a = 0; a < 7; ++a)
+      for (int b = 0; b < 7; ++b) f[28 + 7 * a + b] = L[a][b];
     alpha[0] = 1.0;
   }
   __syncthreads();

@@ -57,7 +57,8 @@ struct ucov_ctx {
   size_t h_ds_cap = 0;
   // learned screener
   Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
-  Buf pg_f;  // the paper gauge's 7 x 7 F (28 values)
+  Buf pg_f;  // the paper gauge's F (28 upper values), then L_F (7 x 7 row-major)
+  Buf fc_x, fc_part, fc_xq, fc_k;  // whole covariance: X, X q partial sums, X q, q^T X q
   // sub-reconstructions: index maps, the gathered sub-scenes and their blocks
   Buf sr_idx, sr_cams, sr_pts, sr_info, sr_cand, sr_chosen;
 
@@ -405,7 +406,8 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
                  &c->mlp_ws, &c->mlp_grad, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
-                 &c->sr_info, &c->sr_cand, &c->sr_chosen};
+                 &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
+                 &c->fc_xq, &c->fc_k};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   if (c->h_stage) hipHostFree(c->h_stage);
@@ -488,7 +490,7 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   SceneWork w = scene_work(c);
   hipEventRecord(c->ev[2], c->stream);
   if (o.gauge == UCOV_GAUGE_PAPER) {
-    UCOV_TRY(ensure(c, c->pg_f, 8 * 28));
+    UCOV_TRY(ensure(c, c->pg_f, 8 * kPaperF));
     launch_paper_gauge(sc, w, as<double>(c->pg_f), c->ds, c->stream);
     launch_gauge(N, nullptr, w.q, w.zdiag, nullptr, 0, 1.0, w.s, w.alpha, c->ds, c->stream);
   } else {
@@ -532,6 +534,83 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
   UCOV_TRY(check_hip(c, "scale"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
   if (rep) hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+  return UCOV_OK;
+}
+
+// The whole camera covariance and every point's 3 x 3 covariance (Sec. 5.2:
+// the points eliminated by block inversion and recovered from the camera
+// covariance).  The dense stage keeps the full scaled inverse X = L^-T L^-1.
+int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
+                         double *cam_cov, int64_t ldc, double *pt_cov, ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_scene(c, scene));
+  const int64_t N = 9 * (int64_t)scene->n_cams;
+  if (!cam_cov && !pt_cov) return c->fail(UCOV_EINVAL, "no output requested");
+  if (cam_cov && ldc < N) return c->fail(UCOV_EINVAL, "bad leading dimension of cam_cov");
+  ucov_options o;
+  fill_defaults(opt, o);
+  if (o.precision != UCOV_FP64)
+    return c->fail(UCOV_EINVAL, "the whole covariance supports UCOV_FP64 only");
+  if (o.gauge != UCOV_GAUGE_CAMERA && o.gauge != UCOV_GAUGE_PAPER)
+    return c->fail(UCOV_EINVAL, "unknown gauge");
+  const bool paper = o.gauge == UCOV_GAUGE_PAPER;
+  hipSetDevice(c->device);
+  reset_report(rep);
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, single_bins(sc), nullptr, nullptr, false, rep));
+  const int64_t Np = round_up(N, kTile);
+  UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
+  UCOV_TRY(ensure(c, c->s, 8 * N));
+  UCOV_TRY(ensure(c, c->amat, 8 * Np * Np));
+  UCOV_TRY(ensure(c, c->fc_x, 8 * Np * Np));
+  UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
+  if (paper) {
+    UCOV_TRY(ensure(c, c->pg_f, 8 * kPaperF));
+    if (pt_cov) {
+      UCOV_TRY(ensure(c, c->fc_part, 8 * 7 * N * xq_splits(N)));
+      UCOV_TRY(ensure(c, c->fc_xq, 8 * 7 * N));
+      UCOV_TRY(ensure(c, c->fc_k, 8 * 49));
+    }
+  }
+  SceneWork w = scene_work(c);
+  hipStream_t st = c->stream;
+  hipEventRecord(c->ev[2], st);
+  if (paper) {
+    launch_paper_gauge(sc, w, as<double>(c->pg_f), c->ds, st);
+    launch_gauge(N, nullptr, w.q, w.zdiag, nullptr, 0, 1.0, w.s, w.alpha, c->ds, st);
+  } else {
+    launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, st);
+  }
+  double *A = as<double>(c->amat), *X = as<double>(c->fc_x);
+  launch_assemble(sc, w, 1, A, Np, c->n_nonzero, st);
+  launch_pad_identity(N, Np, A, Np, st);
+  UCOV_TRY(check_hip(c, "assemble"));
+  hipEventRecord(c->ev[3], st);
+  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
+  spd_inverse_from_factor(A, Np, Np, X, Np, st);
+  hipEventRecord(c->ev[4], st);
+  if (cam_cov) launch_full_camera(N, X, Np, w.s, w.q, w.alpha, !paper, cam_cov, ldc, st);
+  if (pt_cov) {
+    if (paper) {
+      double *xq = as<double>(c->fc_xq), *km = as<double>(c->fc_k);
+      launch_xq(N, X, Np, w.s, w.q, as<double>(c->fc_part), xq, km, st);
+      launch_point_cov(sc, w, X, Np, xq, as<double>(c->pg_f) + 28, km, true, pt_cov, st);
+    } else {
+      launch_point_cov(sc, w, X, Np, w.q, nullptr, nullptr, false, pt_cov, st);
+    }
+  }
+  hipEventRecord(c->ev[5], st);
+  UCOV_TRY(check_hip(c, "whole covariance kernels"));
+  UCOV_TRY(sync_status(c, rep, "whole covariance"));
+  if (rep) {
+    hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
+    hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[1]);
+    hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
+    hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
+    hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
+  }
   return UCOV_OK;
 }
 

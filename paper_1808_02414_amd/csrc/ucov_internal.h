@@ -121,8 +121,10 @@ void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const 
                          double user_alpha, double *s, double *alpha, DevStatus *ds,
                          hipStream_t st);
 // The paper's gauge (M^+)_cc: q <- G L_F^-T (N x 7) with G = H_c - W V^-1 H_p
-// and F = H_p^T V^-1 H_p = L_F L_F^T (f: 28 doubles of scratch), alpha <- 1,
-// so that (Z + q q^T)^-1 is the covariance.  Needs hc from the scene stage.
+// and F = H_p^T V^-1 H_p = L_F L_F^T (f: kPaperF doubles, F's upper triangle
+// then L_F row-major), alpha <- 1, so that (Z + q q^T)^-1 is the covariance.
+// Needs hc from the scene stage.
+constexpr int kPaperF = 28 + 49;
 void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *ds,
                         hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
@@ -196,6 +198,11 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st);
 int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t *n_launches);
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st);
+// x = L^-T L^-1 (Np x Np, both triangles) from the in-place inverse factor
+// of spd_lower_inverse_fp64 (lower triangle, zero upper part of its diagonal
+// tiles).
+void spd_inverse_from_factor(const double *linv, int64_t ld, int64_t Np, double *x, int64_t ldx,
+                             hipStream_t st);
 // Concatenated scenes: identity padding of every scene's matrix, and the
 // blocks of every camera (cov: n_cams x 81 in concatenation order).
 void launch_pad_identity_scenes(int n_scenes, int64_t max_np, const int32_t *cam_off,
@@ -228,5 +235,22 @@ void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, d
 // x += x r with the correction on FP32 MFMA.
 void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32, float *d32,
                   hipStream_t st);
+
+// ---- whole covariance (point_kernels.hip) -----------------------------------
+// cov (N x N, ld ldc) = S X S - [subtract] Q Q^T / alpha from the scaled
+// inverse x (both triangles, ld ldx).
+void launch_full_camera(int64_t N, const double *x, int64_t ldx, const double *s,
+                        const double *q, const double *alpha, bool subtract, double *cov,
+                        int64_t ldc, hipStream_t st);
+// Number of column splits of launch_xq; its part buffer holds 7 N splits values.
+int64_t xq_splits(int64_t N);
+// xq = S x S q (N x 7, ld N) and kmat = q^T xq (7 x 7 row-major).
+void launch_xq(int64_t N, const double *x, int64_t ldx, const double *s, const double *q,
+               double *part, double *xq, double *kmat, hipStream_t st);
+// 3 x 3 covariance of every point (out: m x 9 row-major); b is Q (camera
+// gauge) or X q (paper gauge, with lf = L_F and kmat = q^T X q).
+void launch_point_cov(const SceneDev &sc, const SceneWork &w, const double *x, int64_t ldx,
+                      const double *b, const double *lf, const double *kmat, bool paper,
+                      double *out, hipStream_t st);
 
 }  // namespace ucov

@@ -1,0 +1,129 @@
+"""GPU parity of the whole camera covariance and the point covariances
+(``ucov_full_covariance``, Sec. 5.2 block inversion) against the FP64 oracle.
+
+Tolerances follow the camera-covariance contract: relative Frobenius error
+per 3 x 3 point block and per 9 x 9 camera block <= 1e-6, and the scaled
+error |dX_rc| / sqrt(X_rr X_cc) over the whole camera matrix <= 1e-5 (the
+Frobenius norm of a block is dominated by its largest variance).  The
+diagonal camera blocks must match ``ucov_camera_covariance``, which reduces
+the same factor along another route, to 1e-9.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import points as opts
+
+pytestmark = pytest.mark.gpu
+
+GAUGES = [(0, "camera"), (1, "paper")]
+
+
+@pytest.fixture(scope="module")
+def ucov():
+    import torch
+    import paper_1808_02414_amd as u
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = u.Context(0)
+    yield u, ctx
+    ctx.close()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def point_errors(got, ref):
+    fro = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    d = np.sqrt(np.diagonal(ref, axis1=1, axis2=2))
+    scaled = np.abs(got - ref) / (d[:, :, None] * d[:, None, :])
+    return float(fro.max()), float(scaled.max())
+
+
+def camera_errors(got, ref):
+    n = ref.shape[0] // 9
+    fro = max(np.linalg.norm(got[9 * i:9 * i + 9, 9 * i:9 * i + 9] - ref[9 * i:9 * i + 9, 9 * i:9 * i + 9])
+              / np.linalg.norm(ref[9 * i:9 * i + 9, 9 * i:9 * i + 9]) for i in range(n))
+    d = np.sqrt(np.diag(ref))
+    scaled = float(np.max(np.abs(got - ref) / np.outer(d, d)))
+    return fro, scaled
+
+
+MAKERS = [lambda: sg.tiny_circle(3), lambda: sg.tiny_circle(4, with_info=True),
+          lambda: sg.spiral_slab(5, n=60, m=3000), lambda: sg.spiral_slab(7, n=120, m=8000, with_info=True)]
+
+
+@pytest.mark.parametrize("maker", MAKERS)
+@pytest.mark.parametrize("gauge,name", GAUGES)
+def test_whole_covariance_matches_oracle(ucov, maker, gauge, name):
+    u, ctx = ucov
+    s = maker()
+    print(f"whole covariance {s.name} n={s.n_cams} m={s.n_pts} gauge={name}", flush=True)
+    d = u.DeviceScene.from_scene(s)
+    cam, pts, rep = ctx.full_covariance(d, gauge=gauge)
+    cam, pts = cam.cpu().numpy(), pts.cpu().numpy()
+    Xr, Pr = opts.structured(s, name)
+    fro, scaled = camera_errors(cam, Xr)
+    pf, ps = point_errors(pts, Pr)
+    print(f"  cameras fro {fro:.2e} scaled {scaled:.2e}; points fro {pf:.2e} scaled {ps:.2e}")
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    assert pf < 1e-6 and ps < 1e-5, (pf, ps)
+    assert np.array_equal(cam, cam.T)
+    blocks, _ = ctx.camera_covariance(d, gauge=gauge)
+    blocks = blocks.cpu().numpy()
+    diag = np.stack([cam[9 * i:9 * i + 9, 9 * i:9 * i + 9] for i in range(s.n_cams)])
+    assert np.max(np.linalg.norm(diag - blocks, axis=(1, 2)) / np.linalg.norm(blocks, axis=(1, 2))) < 1e-9
+
+
+@pytest.mark.parametrize("gauge,name", GAUGES)
+def test_points_only_and_cameras_only(ucov, gauge, name):
+    u, ctx = ucov
+    s = sg.tiny_circle(8)
+    d = u.DeviceScene.from_scene(s)
+    cam_a, pts_a, _ = ctx.full_covariance(d, gauge=gauge)
+    cam_b, none_b, _ = ctx.full_covariance(d, points=False, gauge=gauge)
+    none_c, pts_c, _ = ctx.full_covariance(d, cameras=False, gauge=gauge)
+    assert none_b is None and none_c is None
+    # equal up to the order in which the scene stage sums a block's Schur
+    # terms (placed with atomics), which varies from call to call
+    assert rel(cam_b.cpu().numpy(), cam_a.cpu().numpy()) < 1e-9
+    assert rel(pts_c.cpu().numpy(), pts_a.cpu().numpy()) < 1e-9
+
+
+def test_rejects_bad_requests(ucov):
+    import ctypes
+    from paper_1808_02414_amd import _binding as B
+    u, ctx = ucov
+    s = sg.tiny_circle(9)
+    d = u.DeviceScene.from_scene(s)
+    with pytest.raises(u.UcovError) as e:
+        ctx.full_covariance(d, cameras=False, points=False)
+    assert e.value.code == B.EINVAL
+    opt = B.Options(B.FP32_NS, 0, 0.0, 0.0, B.GAUGE_CAMERA)
+    sc = d.struct()
+    rc = ctx.lib.ucov_full_covariance(ctx.h, ctypes.byref(sc), ctypes.byref(opt), None, 0,
+                                      None, None)
+    assert rc == B.EINVAL
+
+
+@pytest.mark.parametrize("gauge,name", GAUGES)
+def test_whole_covariance_full_size_sampled(ucov, gauge, name):
+    """The 500-camera, 50 000-point spiral (the benchmark scene): the whole
+    camera matrix against the oracle's, 300 sampled points against the
+    oracle's point formula, every point block symmetric positive definite."""
+    u, ctx = ucov
+    s = sg.spiral_slab(0)
+    d = u.DeviceScene.from_scene(s)
+    print(f"whole covariance spiral 500 gauge={name}", flush=True)
+    cam, pts, rep = ctx.full_covariance(d, gauge=gauge)
+    cam, pts = cam.cpu().numpy(), pts.cpu().numpy()
+    print(f"  ms inverse {rep['ms_inverse']:.2f} extract {rep['ms_extract']:.2f}", flush=True)
+    sel = np.random.default_rng(0).choice(s.n_pts, 300, replace=False)
+    Xr, Pr = opts.structured(s, name, select=sel)
+    fro, scaled = camera_errors(cam, Xr)
+    pf, ps = point_errors(pts[sel], Pr)
+    print(f"  cameras fro {fro:.2e} scaled {scaled:.2e}; points fro {pf:.2e} scaled {ps:.2e}")
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    assert pf < 1e-6 and ps < 1e-5, (pf, ps)
+    lam = np.linalg.eigvalsh(pts)
+    assert lam.min() > 0.0
