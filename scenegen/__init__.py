@@ -393,6 +393,52 @@ def mlp_init(seed: int, layers=(55, 256, 256, 256, 45)) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def additions(scene: Scene, seed: int, k: int, new_camera: bool = False):
+    """Seeded new observations for incremental updates.  Without new_camera:
+    k pairs (camera, point) not yet observed, the camera a spiral/ring
+    neighbour (index within 3) of one of the point's cameras with the point in
+    front of it.  With new_camera: a new camera, a perturbed copy of a random
+    camera, observing up to k of the points its source sees that lie in front
+    of it.  Returns (new_cam, new_pt, new_info or None, cam_new or None); the
+    new camera has index n_cams."""
+    rng = np.random.default_rng(seed)
+    n, m = scene.n_cams, scene.n_pts
+
+    def in_front(cam, X):
+        R = Rotation.from_rotvec(cam[0:3]).as_matrix()
+        return float((R @ (X - cam[3:6]))[2]) > 0.0
+
+    if new_camera:
+        src = int(rng.integers(n))
+        cam_new = scene.cams[src].copy()
+        spread = float(np.linalg.norm(scene.cams[:, 3:6].std(axis=0)))
+        cam_new[3:6] += rng.normal(0.0, 0.02 * spread, 3)
+        cam_new[0:3] += rng.normal(0.0, 0.01, 3)
+        pts = [int(j) for j in scene.obs_pt[scene.obs_cam == src] if in_front(cam_new, scene.pts[j])]
+        sel = rng.choice(len(pts), size=min(k, len(pts)), replace=False)
+        pt = np.sort(np.asarray([pts[q] for q in sel], np.int32))
+        info = None if scene.obs_info is None else random_information(rng, pt.size)
+        return np.full(pt.size, n, np.int32), pt, info, cam_new
+    seen = set(zip(scene.obs_cam.tolist(), scene.obs_pt.tolist()))
+    cams_of = {}
+    for c, j in zip(scene.obs_cam.tolist(), scene.obs_pt.tolist()):
+        cams_of.setdefault(j, []).append(c)
+    cam, pt = [], []
+    tries = 0
+    while len(cam) < k and tries < 100 * k:
+        tries += 1
+        j = int(rng.integers(m))
+        c0 = cams_of[j][int(rng.integers(len(cams_of[j])))]
+        c = (c0 + int(rng.integers(-3, 4))) % n
+        if (c, j) in seen or not in_front(scene.cams[c], scene.pts[j]):
+            continue
+        seen.add((c, j))
+        cam.append(c)
+        pt.append(j)
+    info = None if scene.obs_info is None else random_information(rng, len(cam))
+    return np.asarray(cam, np.int32), np.asarray(pt, np.int32), info, None
+
+
 def view_graph_partition(scene: Scene, k: int, seed: int, min_shared: int = 8,
                          min_support: int = 10) -> np.ndarray:
     """Group ids (n_cams,) of a decomposition into groups of about k cameras
