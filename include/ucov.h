@@ -164,6 +164,39 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
 int ucov_full_covariance(ucov_ctx *ctx, const ucov_scene *scene, const ucov_options *opt,
                          double *cam_cov, int64_t ldc, double *pt_cov, ucov_report *rep);
 
+/* Incremental update (Sec. 6): the whole camera covariance after adding
+ * observations to the scene, from the covariance before, by the Woodbury
+ * identity (in its corrected form
+ * (Z + J^T W J)^-1 = Z^-1 - Z^-1 J^T (W^-1 + J Z^-1 J^T)^-1 J Z^-1).  A new
+ * observation of an existing point acts on the cameras, once the point is
+ * eliminated, as the rows J_c - J_x V_j^-1 W_j^T with error covariance
+ * Lambda^-1 + J_x V_j^-1 J_x^T (shared between new observations of one
+ * point).  Observations may come from existing cameras or from one new
+ * camera, which is then eliminated as well (flat prior): the old cameras keep
+ * their gauge (the similarity of the old cameras held fixed).
+ * scene: the reconstruction before the addition (its rules as for
+ * ucov_camera_covariance).  n_new >= 1 observations, device arrays:
+ * new_cam[k] in [0, n_cams] (n_cams = the new camera, only with cam_new),
+ * new_pt[k] in [0, n_pts), new_info (n_new x 3 as obs_info, or NULL for
+ * identity).  No camera may observe a point twice (UCOV_EINVAL, rep->bad_index
+ * the new observation).  cam_new: 9 parameters of the new camera (device), or
+ * NULL; if given, some new observation must use it.
+ * cam_cov: in, the scene's whole camera covariance in the camera gauge
+ * (N x N column-major, leading dimension ldc >= N, N = 9 n_cams, as
+ * ucov_full_covariance writes it); out, the covariance of the same cameras
+ * after the addition.  new_cov (9 x 9 row-major) and new_cross (N x 9
+ * row-major: old parameter, new-camera parameter) receive the new camera's
+ * covariance and its cross-covariance with the old cameras, or are NULL;
+ * UCOV_EGAUGE when the new camera's observations do not determine it.
+ * Device workspace: an Np x Np matrix and three Np x Kp ones (Np = N, Kp =
+ * 2 n_new, each rounded up to 64).
+ * rep: ms_schur covers the new rows, ms_inverse the Woodbury products,
+ * ms_extract the copy back. */
+int ucov_update_covariance(ucov_ctx *ctx, const ucov_scene *scene, int64_t n_new,
+                           const int32_t *new_cam, const int32_t *new_pt, const double *new_info,
+                           const double *cam_new, double *cam_cov, int64_t ldc, double *new_cov,
+                           double *new_cross, ucov_report *rep);
+
 /* Covariance blocks of several independent scenes in one call: the
  * sub-reconstructions of Sec. 6, each evaluated exactly on its own gauge (a
  * camera's covariance from a sub-reconstruction around it bounds the one from

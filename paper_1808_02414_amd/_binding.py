@@ -52,7 +52,7 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
            "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
-           "ucov_full_covariance"]
+           "ucov_full_covariance", "ucov_update_covariance"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
                                                           ctypes.POINTER(D), ctypes.POINTER(Report)]),
         "ucov_full_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), ctypes.POINTER(Options),
                                                 P, I64, P, ctypes.POINTER(Report)]),
+        "ucov_update_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), I64, P, P, P, P, P, I64,
+                                                  P, P, ctypes.POINTER(Report)]),
         "ucov_jacobians": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
         "ucov_reduced_camera_matrix": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, I64,
                                                       ctypes.POINTER(Report)]),
@@ -244,6 +246,32 @@ class Context:
                                            ctypes.byref(rep))
         self._check(rc, rep)
         return cam, pts, rep.as_dict()
+
+    def update_covariance(self, scene: DeviceScene, cam_cov, new_cam, new_pt, new_info=None,
+                          cam_new=None):
+        """Update the whole camera covariance ``cam_cov`` ((N, N) float64
+        device tensor, as from ``full_covariance``) in place for the new
+        observations (device int32 tensors; optional (k, 3) information and
+        a new camera's 9 parameters).  Returns (cam_cov, new camera's 9 x 9
+        covariance or None, its (N, 9) cross-covariance or None, report)."""
+        torch = self.torch
+        dev = scene.cams.device
+        N = 9 * scene.n_cams
+        assert cam_cov.shape == (N, N) and cam_cov.dtype == torch.float64 and cam_cov.is_contiguous()
+        k = int(new_cam.numel())
+        ncov = ncross = None
+        if cam_new is not None:
+            ncov = torch.empty((9, 9), dtype=torch.float64, device=dev)
+            ncross = torch.empty((N, 9), dtype=torch.float64, device=dev)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        rc = self.lib.ucov_update_covariance(self.h, ctypes.byref(sc), k, ptr(new_cam), ptr(new_pt),
+                                             ptr(new_info), ptr(cam_new), cam_cov.data_ptr(), N,
+                                             ptr(ncov), ptr(ncross), ctypes.byref(rep))
+        self._check(rc, rep)
+        return cam_cov, ncov, ncross, rep.as_dict()
 
     def camera_covariance_batched(self, scenes, alpha=0.0, out=None):
         """Covariance blocks of independent scenes in one call: a list of

@@ -1222,6 +1222,24 @@ void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, Dev
   recurse<double>(a, lda, 0, Np, tmp, ds, st);
 }
 
+static_assert((int)kFull == (int)kGemmFull && (int)kLeN == (int)kGemmLeN &&
+                  (int)kGeN == (int)kGemmGeN && (int)kLeM == (int)kGemmLeM &&
+                  (int)kGeMN == (int)kGemmGeMN,
+              "public K-range modes follow the tile kernels'");
+
+void gemm_f64(bool at, bool bt, bool lower, int64_t M, int64_t N, int64_t K, const double *A,
+              int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc, double alpha,
+              double beta, int kmode, hipStream_t st) {
+  if (!at && !bt && !lower)
+    gemm<double, false, false, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode, st);
+  else if (!at && bt && !lower)
+    gemm<double, false, true, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode, st);
+  else if (at && !bt && !lower)
+    gemm<double, true, false, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode, st);
+  else if (at && !bt && lower)
+    gemm<double, true, false, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode, st);
+}
+
 void spd_inverse_from_factor(const double *linv, int64_t ld, int64_t Np, double *x, int64_t ldx,
                              hipStream_t st) {
   // X = L^-T L^-1 on the tiles on or below the diagonal (diagonal tiles whole),

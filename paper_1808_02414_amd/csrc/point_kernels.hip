@@ -172,20 +172,7 @@ __global__ __launch_bounds__(256) void k_point_cov(int m, const int64_t *ptr_p,
   }
   wsum6(v);
   double w[3][3];
-  {
-    const double L00 = sqrt(v[0]), L10 = v[1] / L00, L20 = v[2] / L00;
-    const double L11 = sqrt(v[3] - L10 * L10), L21 = (v[4] - L20 * L10) / L11;
-    const double L22 = sqrt(v[5] - L20 * L20 - L21 * L21);
-    const double M00 = 1.0 / L00, M11 = 1.0 / L11, M22 = 1.0 / L22;
-    const double M10 = -L10 * M00 * M11, M21 = -L21 * M11 * M22;
-    const double M20 = -(L20 * M00 + L21 * M10) * M22;
-    w[0][0] = M00 * M00 + M10 * M10 + M20 * M20;
-    w[0][1] = w[1][0] = M10 * M11 + M20 * M21;
-    w[0][2] = w[2][0] = M20 * M22;
-    w[1][1] = M11 * M11 + M21 * M21;
-    w[1][2] = w[2][1] = M21 * M22;
-    w[2][2] = M22 * M22;
-  }
+  spd3_inverse(v, w);
   // sum over ordered slot pairs: the unordered pairs (ia >= ib), the
   // off-diagonal ones counted with their transposes
   double acc[6] = {0, 0, 0, 0, 0, 0};

@@ -59,6 +59,8 @@ struct ucov_ctx {
   Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
   Buf pg_f;  // the paper gauge's F (28 upper values), then L_F (7 x 7 row-major)
   Buf fc_x, fc_part, fc_xq, fc_k;  // whole covariance: X, X q partial sums, X q, q^T X q
+  // incremental update: indices, padded Z^+, JtT, B, T, S, scratch, Jacobians, J_n, U, small, V, W
+  Buf up_idx, up_z, up_jt, up_b, up_t, up_s, up_tmp, up_nj, up_jn, up_u, up_g, up_v, up_w;
   // sub-reconstructions: index maps, the gathered sub-scenes and their blocks
   Buf sr_idx, sr_cams, sr_pts, sr_info, sr_cand, sr_chosen;
 
@@ -407,7 +409,9 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
                  &c->mlp_ws, &c->mlp_grad, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
                  &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
-                 &c->fc_xq, &c->fc_k};
+                 &c->fc_xq, &c->fc_k, &c->up_idx, &c->up_z, &c->up_jt, &c->up_b,
+                 &c->up_t, &c->up_s, &c->up_tmp, &c->up_nj, &c->up_jn, &c->up_u, &c->up_g,
+                 &c->up_v, &c->up_w};
   for (Buf *b : bufs)
     if (b->p) hipFree(b->p);
   if (c->h_stage) hipHostFree(c->h_stage);
@@ -608,6 +612,125 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
     hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[1]);
     hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
     hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
+    hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
+  }
+  return UCOV_OK;
+}
+
+// Incremental update (Sec. 6): the whole camera covariance after adding
+// observations of existing points by existing cameras or by one new camera,
+// by the Woodbury identity on the effective observation rows.
+int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
+                           const int32_t *new_cam, const int32_t *new_pt, const double *new_info,
+                           const double *cam_new, double *cam_cov, int64_t ldc, double *new_cov,
+                           double *new_cross, ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  UCOV_TRY(check_scene(c, scene));
+  const int64_t n = scene->n_cams, m = scene->n_pts, N = 9 * n;
+  if (n_new < 1 || !new_cam || !new_pt || !cam_cov || ldc < N)
+    return c->fail(UCOV_EINVAL, "bad update arguments");
+  if ((new_cov || new_cross) && !cam_new)
+    return c->fail(UCOV_EINVAL, "new-camera outputs without a new camera");
+  hipSetDevice(c->device);
+  reset_report(rep);
+  hipStream_t st = c->stream;
+  // host bookkeeping of the new observations' indices
+  std::vector<int32_t> hc(n_new), hp(n_new);
+  if (hipMemcpyAsync(hc.data(), new_cam, 4 * n_new, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hp.data(), new_pt, 4 * n_new, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return c->fail(UCOV_EDEVICE, "index readback");
+  int64_t by_new = 0;
+  for (int64_t a = 0; a < n_new; ++a) {
+    if (hp[a] < 0 || hp[a] >= m || hc[a] < 0 || hc[a] > n || (hc[a] == n && !cam_new)) {
+      if (rep) rep->bad_index = (int32_t)a;
+      return c->fail(UCOV_EINVAL, "new observation index out of range");
+    }
+    by_new += hc[a] == n;
+  }
+  if (cam_new && by_new == 0) return c->fail(UCOV_EINVAL, "the new camera has no observations");
+  std::vector<int32_t> ord(n_new), grp0(n_new);
+  for (int64_t a = 0; a < n_new; ++a) ord[a] = (int32_t)a;
+  std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+    return hp[x] != hp[y] ? hp[x] < hp[y] : (hc[x] != hc[y] ? hc[x] < hc[y] : x < y);
+  });
+  for (int64_t a = 0; a < n_new; ++a) {
+    const bool same = a > 0 && hp[ord[a]] == hp[ord[a - 1]];
+    if (same && hc[ord[a]] == hc[ord[a - 1]]) {
+      if (rep) rep->bad_index = ord[a];
+      return c->fail(UCOV_EINVAL, "duplicate new observation");
+    }
+    grp0[a] = same ? grp0[a - 1] : (int32_t)a;
+  }
+  // the old scene's point stage: Jacobians, V_j^-1, Y = J_X V^-1
+  const SceneDev sc = scene_dev(scene);
+  clear_status(c);
+  UCOV_TRY(run_scene_stage(c, sc, 1, nullptr, nullptr, true, rep));
+  SceneWork w = scene_work(c);
+  launch_point_blocks(sc, w, c->ds, st);
+  const int64_t Np = round_up(N, kTile), Kp = round_up(2 * n_new, kTile);
+  UCOV_TRY(ensure(c, c->up_idx, 4 * 2 * n_new));
+  UCOV_TRY(ensure(c, c->up_z, 8 * Np * Np));
+  UCOV_TRY(ensure(c, c->up_jt, 8 * Np * Kp));
+  UCOV_TRY(ensure(c, c->up_b, 8 * Np * Kp));
+  UCOV_TRY(ensure(c, c->up_t, 8 * Np * Kp));
+  UCOV_TRY(ensure(c, c->up_s, 8 * Kp * Kp));
+  UCOV_TRY(ensure(c, c->up_tmp, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Kp))));
+  UCOV_TRY(ensure(c, c->up_nj, 8 * 24 * n_new));
+  UCOV_TRY(ensure(c, c->up_jn, 8 * Kp * 64));
+  if (cam_new) {
+    UCOV_TRY(ensure(c, c->up_u, 8 * Kp * 64));
+    UCOV_TRY(ensure(c, c->up_g, 8 * (64 * 64 + 2 * 81)));
+    UCOV_TRY(ensure(c, c->up_v, 8 * Np * 64));
+    UCOV_TRY(ensure(c, c->up_w, 8 * Np * 64));
+  }
+  int32_t *d_ord = as<int32_t>(c->up_idx), *d_grp = d_ord + n_new;
+  if (hipMemcpyAsync(d_ord, ord.data(), 4 * n_new, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_grp, grp0.data(), 4 * n_new, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return c->fail(UCOV_EDEVICE, "index upload");
+  double *Zp = as<double>(c->up_z), *jt = as<double>(c->up_jt), *B = as<double>(c->up_b),
+         *T = as<double>(c->up_t), *S = as<double>(c->up_s), *jn = as<double>(c->up_jn),
+         *nj = as<double>(c->up_nj);
+  hipEventRecord(c->ev[2], st);
+  launch_copy_in(N, Np, cam_cov, ldc, Zp, st);
+  fill_f64(jt, 0.0, Np * Kp, st);
+  fill_f64(S, 0.0, Kp * Kp, st);
+  fill_f64(jn, 0.0, Kp * 64, st);
+  launch_new_jacobians(sc, n_new, d_ord, new_cam, new_pt, new_info, cam_new, nj, jn, Kp, c->ds,
+                       st);
+  launch_new_rows(sc, w, n_new, d_ord, new_cam, new_pt, d_grp, nj, jt, Np, S, Kp, c->ds, st);
+  launch_pad_identity(2 * n_new, Kp, S, Kp, st);
+  UCOV_TRY(check_hip(c, "update rows"));
+  UCOV_TRY(sync_status(c, rep, "new observations"));
+  hipEventRecord(c->ev[3], st);
+  // B = Z^+ JtT, S += JtT^T B (lower), S = L L^T -> L^-1, T = B L^-T, Z^+ -= T T^T
+  gemm_f64(false, false, false, Np, Kp, Np, Zp, Np, jt, Np, B, Np, 1.0, 0.0, kGemmFull, st);
+  gemm_f64(true, false, true, Kp, Kp, Np, jt, Np, B, Np, S, Kp, 1.0, 1.0, kGemmFull, st);
+  spd_lower_inverse_fp64(S, Kp, Kp, as<double>(c->up_tmp), c->ds, st);
+  gemm_f64(false, true, false, Np, Kp, Kp, B, Np, S, Kp, T, Np, 1.0, 0.0, kGemmLeN, st);
+  gemm_f64(false, true, false, Np, Np, Kp, T, Np, T, Np, Zp, Np, -1.0, 1.0, kGemmFull, st);
+  if (cam_new) {
+    // U = L^-1 J_n, C_n = (U^T U)^-1, V = T U, Z^+ += (V L_C)(V L_C)^T
+    double *U = as<double>(c->up_u), *G = as<double>(c->up_g), *V = as<double>(c->up_v),
+           *Wm = as<double>(c->up_w);
+    double *cn = G + 64 * 64, *lc = cn + 81;
+    gemm_f64(false, false, false, Kp, 64, Kp, S, Kp, jn, Kp, U, Kp, 1.0, 0.0, kGemmLeM, st);
+    gemm_f64(true, false, false, 64, 64, Kp, U, Kp, U, Kp, G, 64, 1.0, 0.0, kGemmFull, st);
+    gemm_f64(false, false, false, Np, 64, Kp, T, Np, U, Kp, V, Np, 1.0, 0.0, kGemmFull, st);
+    launch_new_camera(G, cn, lc, N, Np, V, Wm, new_cross, c->ds, st);
+    gemm_f64(false, true, false, Np, Np, 64, Wm, Np, Wm, Np, Zp, Np, 1.0, 1.0, kGemmFull, st);
+    if (new_cov) hipMemcpyAsync(new_cov, cn, 8 * 81, hipMemcpyDeviceToDevice, st);
+  }
+  hipEventRecord(c->ev[4], st);
+  launch_copy_out(N, Np, Zp, cam_cov, ldc, st);
+  hipEventRecord(c->ev[5], st);
+  UCOV_TRY(check_hip(c, "update products"));
+  UCOV_TRY(sync_status(c, rep, "covariance update"));
+  if (rep) {
+    hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[2]);
+    hipEventElapsedTime(&rep->ms_schur, c->ev[2], c->ev[3]);
     hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
     hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
   }

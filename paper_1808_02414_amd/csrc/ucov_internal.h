@@ -20,6 +20,23 @@ __device__ inline void report_error(DevStatus *st, int code, int index) {
   if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->index, index);
 }
 
+// Inverse of a symmetric positive definite 3 x 3 held as (00 01 02 11 12 22),
+// through its Cholesky factor (full 3 x 3 result).
+__device__ inline void spd3_inverse(const double *v, double w[3][3]) {
+  const double L00 = sqrt(v[0]), L10 = v[1] / L00, L20 = v[2] / L00;
+  const double L11 = sqrt(v[3] - L10 * L10), L21 = (v[4] - L20 * L10) / L11;
+  const double L22 = sqrt(v[5] - L20 * L20 - L21 * L21);
+  const double M00 = 1.0 / L00, M11 = 1.0 / L11, M22 = 1.0 / L22;
+  const double M10 = -L10 * M00 * M11, M21 = -L21 * M11 * M22;
+  const double M20 = -(L20 * M00 + L21 * M10) * M22;
+  w[0][0] = M00 * M00 + M10 * M10 + M20 * M20;
+  w[0][1] = w[1][0] = M10 * M11 + M20 * M21;
+  w[0][2] = w[2][0] = M20 * M22;
+  w[1][1] = M11 * M11 + M21 * M21;
+  w[1][2] = w[2][1] = M21 * M22;
+  w[2][2] = M22 * M22;
+}
+
 // Tile edge of the dense factorisation; every dense dimension is padded to it.
 constexpr int kTile = 64;
 
@@ -198,6 +215,20 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st);
 int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t *n_launches);
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st);
+// C = alpha op(A) op(B) + beta C in FP64 on the MFMA tile kernels (column-
+// major; M, N, K multiples of 64).  at: A stored K x M; bt: B stored N x K;
+// lower: only tiles on or below the diagonal (with at and no bt only).
+// kmode limits K to the nonzero part of a triangular operand:
+enum GemmK {
+  kGemmFull = 0,
+  kGemmLeN = 1,   // k < (tile_n + 1) 64: B lower triangular, used transposed
+  kGemmGeN = 2,   // k >= tile_n 64: B lower triangular
+  kGemmLeM = 3,   // k < (tile_m + 1) 64: A lower triangular
+  kGemmGeMN = 4,  // k >= max(tile_m, tile_n) 64: A^T B, both lower triangular
+};
+void gemm_f64(bool at, bool bt, bool lower, int64_t M, int64_t N, int64_t K, const double *A,
+              int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc, double alpha,
+              double beta, int kmode, hipStream_t st);
 // x = L^-T L^-1 (Np x Np, both triangles) from the in-place inverse factor
 // of spd_lower_inverse_fp64 (lower triangle, zero upper part of its diagonal
 // tiles).
@@ -252,5 +283,29 @@ void launch_xq(int64_t N, const double *x, int64_t ldx, const double *s, const d
 void launch_point_cov(const SceneDev &sc, const SceneWork &w, const double *x, int64_t ldx,
                       const double *b, const double *lf, const double *kmat, bool paper,
                       double *out, hipStream_t st);
+
+
+// ---- incremental update (update_kernels.hip) --------------------------------
+// New observations in point-grouped order (position a -> caller's index
+// ord[a]): whitened Jacobians nj (k x 24) and the new camera's rows jn
+// (kp x 64, zeroed beforehand).
+void launch_new_jacobians(const SceneDev &sc, int64_t k, const int32_t *ord,
+                          const int32_t *ncam, const int32_t *npt, const double *ninfo,
+                          const double *cam_new, double *nj, double *jn, int64_t kp,
+                          DevStatus *ds, hipStream_t st);
+// Effective rows JtT (np x kp, zeroed) and the lower triangle of their error
+// covariance S (kp x kp, zeroed); grp0[a]: first position of a's point.
+void launch_new_rows(const SceneDev &sc, const SceneWork &w, int64_t k, const int32_t *ord,
+                     const int32_t *ncam, const int32_t *npt, const int32_t *grp0,
+                     const double *nj, double *jt, int64_t np, double *S, int64_t kp,
+                     DevStatus *ds, hipStream_t st);
+void launch_copy_in(int64_t N, int64_t np, const double *src, int64_t ldc, double *zp,
+                    hipStream_t st);
+void launch_copy_out(int64_t N, int64_t np, const double *zp, double *dst, int64_t ldc,
+                     hipStream_t st);
+// C_n = (U^T U)^-1 from g = U^T U (64 x 64) and its factor lc; W = V L_C
+// (np x 64) and cross = -V C_n (N x 9, when not null).
+void launch_new_camera(const double *g, double *cn, double *lc, int64_t N, int64_t np,
+                       const double *V, double *W, double *cross, DevStatus *ds, hipStream_t st);
 
 }  // namespace ucov
