@@ -299,63 +299,110 @@ def _zipf_lengths(rng, m, s=1.5, lo=2, hi=30):
 
 def clustered(seed: int = 0, n_clusters: int = 10, per_cluster: int = 300,
               m: int = 500_000, ring: float = 40.0, frac_cross: float = 0.02,
-              frac_far: float = 0.05, with_info: bool = False) -> Scene:
-    """Clustered groups of cameras with Zipf track lengths and far points."""
+              frac_far: float = 0.05, with_info: bool = False, max_track: int = 30) -> Scene:
+    """Clustered sites: n_clusters groups of per_cluster cameras, each group
+    on a ring of radius 12 (heights 1-5) around its own object (points in a
+    cylinder of radius 4, height [-2, 2]) at a site on a circle of radius
+    ``ring``.  Track lengths Zipf(1.5) on [2, max_track], capped by the
+    cameras that see the point inside the 640 x 480 frame; a track is the arc
+    of cameras nearest a random seeing camera among those that see it.
+    ``frac_cross`` of the points lie between neighbouring sites and are seen
+    from both (half the track each), which links the sites; ``frac_far`` lie
+    about 1000 units away along a camera's viewing ray and are seen by its
+    neighbours, a near-zero baseline that makes their 3 x 3 point blocks
+    ill-conditioned.  Every observed point is in front of its cameras."""
     rng = np.random.default_rng(seed)
     n = n_clusters * per_cluster
     ang = 2 * np.pi * np.arange(n_clusters) / n_clusters
-    kc = ring * np.column_stack([np.cos(ang), np.sin(ang), np.zeros(n_clusters)])
+    site = ring * np.column_stack([np.cos(ang), np.sin(ang), np.zeros(n_clusters)])
     cl = np.repeat(np.arange(n_clusters), per_cluster)
-    centres = kc[cl] + np.array([0.0, 0.0, 10.0]) + rng.normal(0.0, 3.0, (n, 3))
-    target = kc[cl] + rng.normal(0.0, 1.0, (n, 3))
-    radial = np.column_stack([np.cos(ang[cl]), np.sin(ang[cl]), np.zeros(n)])
-    rot = _look_at_rotvec(centres, target - centres, radial)
-    cams = np.column_stack([rot, centres, _intrinsics(rng, n)])
-    fwd = target - centres
-    fwd /= np.linalg.norm(fwd, axis=1, keepdims=True)
-
-    t = _zipf_lengths(rng, m)
+    phi = (2 * np.pi * np.tile(np.arange(per_cluster), n_clusters) / per_cluster
+           + rng.normal(0.0, 0.3 * np.pi / per_cluster, n))
+    centres = site[cl] + np.column_stack([12.0 * np.cos(phi), 12.0 * np.sin(phi),
+                                          rng.uniform(1.0, 5.0, n)])
+    target = site[cl] + rng.normal(0.0, 0.5, (n, 3))
+    axes = _look_at_axes(target - centres, np.tile([0.0, 0.0, 1.0], (n, 1)))
+    cams = np.column_stack([Rotation.from_matrix(axes).as_rotvec(), centres, _intrinsics(rng, n)])
+    members = [np.flatnonzero(cl == c) for c in range(n_clusters)]
     kind = rng.uniform(0, 1, m)
-    cross = kind < frac_cross
-    far = (kind >= frac_cross) & (kind < frac_cross + frac_far)
-    home = rng.integers(0, n_clusters, m)
-    pts = kc[home] + np.column_stack([rng.uniform(-6, 6, (m, 2)), rng.uniform(-2, 2, m)])
-    nb = (home + 1) % n_clusters
-    pts[cross] = 0.5 * (kc[home[cross]] + kc[nb[cross]]) + rng.normal(0, 2.0, (int(cross.sum()), 3))
+    n_cross = int((kind < frac_cross).sum())
+    n_far = int(((kind >= frac_cross) & (kind < frac_cross + frac_far)).sum())
+    n_local = m - n_cross - n_far
 
-    trees = [cKDTree(centres[cl == c]) for c in range(n_clusters)]
-    base = [np.flatnonzero(cl == c) for c in range(n_clusters)]
-    tracks = [None] * m
-    # local points: 2t nearest cameras of the home cluster
+    def draw_tracks(P, cand, want, chunk=4096):
+        # per point: the candidates that see it, then the arc of the t nearest
+        # to a random one of them (None when fewer than two see it)
+        out = []
+        for j0 in range(0, P.shape[0], chunk):
+            Pc, cc = P[j0:j0 + chunk], cand[j0:j0 + chunk]
+            vis = _in_view(axes, centres, Pc, cc)
+            nvis = vis.sum(axis=1)
+            keys = rng.random(vis.shape)
+            keys[~vis] = np.inf
+            anchor = centres[cc[np.arange(cc.shape[0]), np.argmin(keys, axis=1)]]
+            dist = np.linalg.norm(centres[cc] - anchor[:, None, :], axis=2)
+            dist[~vis] = np.inf
+            order = np.argsort(dist, axis=1, kind="stable")
+            t = np.minimum(want[j0:j0 + chunk], nvis)
+            for q in range(cc.shape[0]):
+                out.append(cc[q, order[q, :t[q]]] if nvis[q] >= 2 else None)
+        return out
+
+    pts_l, tracks = [], []
+    # local points of every site
+    per_site = np.bincount(rng.integers(0, n_clusters, n_local), minlength=n_clusters)
     for c in range(n_clusters):
-        sel = np.flatnonzero((home == c) & ~cross)
-        if sel.size == 0:
-            continue
-        kmax = int(min(per_cluster, 2 * t[sel].max()))
-        _, near = trees[c].query(pts[sel], k=kmax, workers=-1)
-        near = np.atleast_2d(near)
-        for row, j in enumerate(sel):
-            cand = near[row, :min(per_cluster, 2 * t[j])]
-            tracks[j] = base[c][rng.choice(cand, size=t[j], replace=False)]
-    # cross-cluster tracks: half from each neighbouring cluster
-    for j in np.flatnonzero(cross):
-        a, b = home[j], nb[j]
-        ta = max(1, t[j] // 2)
-        tb = max(1, t[j] - ta)
-        _, na = trees[a].query(pts[j], k=min(per_cluster, 2 * ta))
-        _, nbb = trees[b].query(pts[j], k=min(per_cluster, 2 * tb))
-        na, nbb = np.atleast_1d(na), np.atleast_1d(nbb)
-        tracks[j] = np.concatenate([base[a][rng.choice(na, ta, replace=False)],
-                                    base[b][rng.choice(nbb, tb, replace=False)]])
-    # near-zero-baseline points: pushed far along the mean viewing direction
-    for j in np.flatnonzero(far):
-        cams_j = tracks[j]
-        cc = centres[cams_j].mean(axis=0)
-        d = fwd[cams_j].mean(axis=0)
-        d /= np.linalg.norm(d)
-        spread = np.linalg.norm(centres[cams_j] - cc, axis=1).max() + 1e-3
-        pts[j] = cc + d * spread * 1e4
-    return _finish(rng, cams, pts, tracks, "clustered", seed, with_info)
+        need = int(per_site[c])
+        while need > 0:
+            b = int(1.2 * need) + 16
+            r = 4.0 * np.sqrt(rng.uniform(0, 1, b))
+            th = rng.uniform(0, 2 * np.pi, b)
+            P = site[c] + np.column_stack([r * np.cos(th), r * np.sin(th), rng.uniform(-2, 2, b)])
+            cand = np.tile(members[c], (b, 1))
+            tr = draw_tracks(P, cand, _zipf_lengths(rng, b, hi=max_track))
+            for j in range(b):
+                if tr[j] is not None and need > 0:
+                    pts_l.append(P[j])
+                    tracks.append(tr[j])
+                    need -= 1
+    # points between neighbouring sites, seen from both
+    need = n_cross
+    while need > 0:
+        b = int(2 * need) + 16
+        c = rng.integers(0, n_clusters, b)
+        d = (c + 1) % n_clusters
+        P = 0.5 * (site[c] + site[d]) + np.column_stack([rng.normal(0, 3.0, (b, 2)),
+                                                         rng.uniform(0.0, 4.0, b)])
+        want = _zipf_lengths(rng, b, hi=max_track)
+        ta = np.maximum(1, want // 2)
+        tb = np.maximum(1, want - ta)
+        tr_a = draw_tracks(P, np.stack([members[x] for x in c]), 2 * ta)
+        tr_b = draw_tracks(P, np.stack([members[x] for x in d]), 2 * tb)
+        for j in range(b):
+            if tr_a[j] is None or tr_b[j] is None or need == 0:
+                continue
+            pts_l.append(P[j])
+            tracks.append(np.concatenate([tr_a[j][:ta[j]], tr_b[j][:tb[j]]]))
+            need -= 1
+    # far points: near-zero baseline
+    need = n_far
+    while need > 0:
+        b = int(1.2 * need) + 16
+        a = rng.integers(0, n, b)
+        ray = np.column_stack([rng.uniform(-0.25, 0.25, b), rng.uniform(-0.18, 0.18, b), np.ones(b)])
+        ray = (axes[a] * ray[:, :, None]).sum(axis=1)
+        ray /= np.linalg.norm(ray, axis=1, keepdims=True)
+        P = centres[a] + ray * rng.uniform(800.0, 1200.0, b)[:, None]
+        cand = np.stack([members[x] for x in cl[a]])
+        tr = draw_tracks(P, cand, _zipf_lengths(rng, b, hi=max_track))
+        for j in range(b):
+            if tr[j] is not None and need > 0:
+                pts_l.append(P[j])
+                tracks.append(tr[j])
+                need -= 1
+    pts = np.asarray(pts_l)
+    order = rng.permutation(len(tracks))
+    return _finish(rng, cams, pts[order], [tracks[i] for i in order], "clustered", seed, with_info)
 
 
 def batch_scenes(seed: int = 1000, count: int = 256, lo: int = 20, hi: int = 400,

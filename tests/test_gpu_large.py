@@ -1,0 +1,97 @@
+"""The clustered recipe on the GPU: small scenes against the oracle, and the
+large scene (10 sites of 300 cameras, 500 000 points, ~3.4 million
+observations, Z 27000 x 27000) against stored oracle blocks of four cameras
+(``tests/golden/make_clustered3000.py``: the oracle needs minutes there) and
+the Penrose conditions of the whole matrices.
+
+Tolerances: per block relative Frobenius <= 1e-6 and scaled <= 1e-5, as for
+the other parity tests.  The Penrose residuals are computed with FP64
+products of the N x N matrices on the device (torch, as a checker); their
+bound is set from the arithmetic: a backward-stable inverse leaves
+|Z S Z - Z| and |S Z S - S| of order N eps relative (measured 2.5e-11 and
+1.4e-12, bound 1e-8), while the symmetry of the projector Z S carries the
+error of S times |Z|, of order kappa eps with kappa near 1e6 for the scaled
+camera matrix (measured 5e-9, bound 1e-7).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle.pipeline import camera_covariance as oracle_cov
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "clustered3000_blocks.json")
+
+
+@pytest.fixture(scope="module")
+def ucov():
+    import torch
+    import paper_1808_02414_amd as u
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = u.Context(0)
+    yield u, ctx
+    ctx.close()
+
+
+def block_errors(got, ref):
+    fro = max(np.linalg.norm(g - r) / np.linalg.norm(r) for g, r in zip(got, ref))
+    d = np.sqrt(np.abs(np.diagonal(ref, axis1=1, axis2=2)))
+    return fro, float(np.max(np.abs(got - ref) / (d[:, :, None] * d[:, None, :])))
+
+
+@pytest.mark.parametrize("maker", [lambda: sg.clustered(3, n_clusters=3, per_cluster=40, m=6000),
+                                   lambda: sg.clustered(4, n_clusters=4, per_cluster=30, m=5000,
+                                                        with_info=True)])
+def test_clustered_matches_oracle(ucov, maker):
+    u, ctx = ucov
+    s = maker()
+    print(f"clustered n={s.n_cams} m={s.n_pts} t={s.n_obs}", flush=True)
+    got, _ = ctx.camera_covariance(u.DeviceScene.from_scene(s))
+    fro, scaled = block_errors(got.cpu().numpy(), oracle_cov(s)["blocks"])
+    print(f"  fro {fro:.2e} scaled {scaled:.2e}")
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+def test_clustered3000(ucov):
+    import hashlib
+    import torch
+    u, ctx = ucov
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    s = sg.clustered(0)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(s.obs_cam, np.int32).tobytes())
+    h.update(np.ascontiguousarray(s.obs_pt, np.int32).tobytes())
+    assert h.hexdigest() == gold["structure_sha256"], "scene generated differently"
+    assert np.isclose(np.abs(s.cams).sum(), gold["checksums"]["cams"], rtol=1e-12)
+    assert np.isclose(np.abs(s.pts).sum(), gold["checksums"]["pts"], rtol=1e-12)
+    print(f"clustered3000 n={s.n_cams} m={s.n_pts} t={s.n_obs}", flush=True)
+    d = u.DeviceScene.from_scene(s)
+    blocks, rep = ctx.camera_covariance(d)
+    print(f"  covariance: dense stage {rep['ms_inverse']:.1f} ms", flush=True)
+    blocks = blocks.cpu().numpy()
+    ref = np.array([[float(v) for v in b] for b in gold["blocks"]]).reshape(-1, 9, 9)
+    fro, scaled = block_errors(blocks[gold["cameras"]], ref)
+    print(f"  sampled cameras fro {fro:.2e} scaled {scaled:.2e}", flush=True)
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    lam = np.linalg.eigvalsh(0.5 * (blocks + np.transpose(blocks, (0, 2, 1))))
+    assert lam.min() > 0.0
+    # the whole matrices: Sigma = Z^+ (Penrose conditions) and Sigma Q = 0
+    Z, _ = ctx.reduced_camera_matrix(d)
+    Sig, _, _ = ctx.full_covariance(d, points=False)
+    _, q = ctx.gauge_basis(d)
+    diag = torch.stack([Sig[9 * i:9 * i + 9, 9 * i:9 * i + 9] for i in range(s.n_cams)]).cpu().numpy()
+    assert np.max(np.linalg.norm(diag - blocks, axis=(1, 2)) / np.linalg.norm(blocks, axis=(1, 2))) < 1e-9
+    nz, ns = torch.linalg.norm(Z), torch.linalg.norm(Sig)
+    ZS = Z @ Sig
+    r1 = float(torch.linalg.norm(ZS @ Z - Z) / nz)
+    r2 = float(torch.linalg.norm(Sig @ ZS - Sig) / ns)
+    r3 = float(torch.linalg.norm(ZS - ZS.T) / torch.linalg.norm(ZS))
+    r4 = float(torch.linalg.norm(Sig @ q) / ns)
+    print(f"  Penrose: |ZSZ - Z| {r1:.2e}  |SZS - S| {r2:.2e}  |ZS - (ZS)^T| {r3:.2e}  |S Q| {r4:.2e}",
+          flush=True)
+    assert r1 < 1e-8 and r2 < 1e-8 and r3 < 1e-7 and r4 < 1e-8

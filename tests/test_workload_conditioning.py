@@ -29,6 +29,8 @@ def rounding_sensitivity(scene, seed=1):
     lambda: sg.spiral_slab(13, n=60, m=3000),
     lambda: sg.batch_scenes(seed=3000, count=8, lo=20, hi=70)[5],
     lambda: sg.batch_scenes(count=1, lo=20, hi=21)[0],
+    lambda: sg.clustered(3, n_clusters=3, per_cluster=40, m=6000),
+    lambda: sg.clustered(4, n_clusters=4, per_cluster=30, m=5000, with_info=True),
 ])
 def test_parity_scenes_are_well_conditioned(maker):
     s = maker()
@@ -44,3 +46,21 @@ def test_observations_lie_in_the_image():
     assert inside.mean() > 0.99
     tl = np.bincount(s.obs_pt)
     assert tl.min() >= 2
+
+
+def test_clustered_observations_lie_in_the_image():
+    """Clustered scenes use the same visibility model; their far points have
+    a near-zero baseline (ill-conditioned but accepted point blocks)."""
+    from oracle import camera, schur
+    s = sg.clustered(5, n_clusters=3, per_cluster=40, m=6000)
+    u = np.asarray(camera.project_values(s.cams, s.pts, s.obs_cam, s.obs_pt))
+    inside = (u[:, 0] >= 0) & (u[:, 0] <= 640) & (u[:, 1] >= 0) & (u[:, 1] <= 480)
+    assert inside.mean() > 0.99
+    far = np.linalg.norm(s.pts, axis=1) > 500
+    assert 0.02 < far.mean() < 0.08
+    oc, op = s.obs_cam.astype(np.int64), s.obs_pt.astype(np.int64)
+    JP, JX = camera.jacobians(s.cams, s.pts, oc, op)
+    _, V, _ = schur.normal_blocks(JP, JX, schur.information_blocks(None, oc.size), oc, op,
+                                  s.n_cams, s.n_pts)
+    cond = np.linalg.cond(V)
+    assert cond[far].min() > 100 * np.median(cond[~far])
