@@ -10,6 +10,7 @@ same precision: a pre-activation near zero may switch sign between BF16 and
 FP64 operands and then reroutes that unit's gradient entirely.  Adam and the
 label transforms run in FP32/FP64 arithmetic (1e-5).
 """
+import os
 import time
 
 import numpy as np
@@ -189,6 +190,7 @@ def test_trained_screener_gains_over_screening_without_it(ucov):
 
     Fh, Sh = scr.training_set(ctx, held)
     pred, spread = model.predict(ctx, Fh)
+    pred_all = pred.clone()
     ref = Sh.cpu().numpy()
     err_net = block_rel_errors(pred.cpu().numpy(), ref)
     # network output 0 is the training mean of every standardised parameter
@@ -224,3 +226,34 @@ def test_trained_screener_gains_over_screening_without_it(ucov):
     assert med["net"] < 0.35 * min(med["mean"], med["zii"]), med
     assert rho > 0.9
     assert t_screen < t_exact
+
+    # screening with fallback: cameras whose predicted spread exceeds the
+    # threshold get the exact covariance, the others the network's
+    s = held[-1]
+    d = dev_held[-1]
+    _, sp = model.predict(ctx, ctx.screener_features(d))
+    thr = float(torch.quantile(sp, 0.8))
+    cov, spread, fallback = model.screen(ctx, d, thr)
+    exact = ctx.camera_covariance(d)[0]
+    pred, _ = model.predict(ctx, ctx.screener_features(d))
+    fb = fallback.cpu().numpy()
+    print(f"  screen: {fb.sum()} of {fb.size} cameras fall back", flush=True)
+    assert 0 < fb.sum() < fb.size
+    # the exact path sums each Schur block in arrival order: repeated calls
+    # agree to ~1e-11, not bit for bit
+    assert block_rel_errors(cov[fallback].cpu().numpy(), exact[fallback].cpu().numpy()).max() < 1e-8
+    assert bool((spread[~fallback] <= thr).all()) and bool((spread[fallback] > thr).all())
+    kept = ~fallback
+    assert not bool(torch.isclose(cov[kept], exact[kept], rtol=1e-9, atol=0.0).all())
+    err_screen = block_rel_errors(cov.cpu().numpy(), exact.cpu().numpy())
+    err_pred = block_rel_errors(pred.cpu().numpy(), exact.cpu().numpy())
+    assert np.mean(err_screen) < np.mean(err_pred)
+
+    # the trained screener round-trips through a safetensors file
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "screener.safetensors")
+        model.save(path)
+        loaded = scr.Screener.load(path)
+    again, _ = loaded.predict(ctx, Fh)
+    assert torch.allclose(again, pred_all, rtol=1e-6, atol=0.0)
