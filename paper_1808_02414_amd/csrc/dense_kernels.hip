@@ -313,8 +313,10 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 //   1. one wave factors the 16x16 diagonal block in registers (row per lane,
 //      scalar lane broadcasts, hardware reciprocal square roots refined by
 //      Newton steps) and inverts it: L_pp and L_pp^-1;
-//   2. the panel below: L_ip = A_ip L_pp^-T            (MFMA, 4 waves)
-//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA, 4 waves)
+//   2. the panel below: L_ip = A_ip L_pp^-T            (MFMA, all waves)
+//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA); wave 0 takes
+//      block (p+1, p+1) and goes straight on to step 1 of panel p + 1 while
+//      the other waves finish the trailing update.
 // Inversion (forward elimination of L Y = I by block rows), panel p:
 //   a. L(., p) is staged in the unused upper blocks of block row p, and
 //      Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1;
@@ -378,52 +380,77 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   __syncthreads();
   const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
 
-  for (int p = 0; p < NPAN; ++p) {
+  // Diagonal block p on wave 0: lane r < 16 holds row r; L_pp into S,
+  // L_pp^-1 into Dinv[p].
+  auto factor_diag = [&](int p) {
     const int c0 = 16 * p;
-    // ---- 1. diagonal block on wave 0: lane r < 16 holds row r ----
-    if (wid == 0) {
-      T v[16], y[16], rsv[16];
+    T v[16], y[16], rsv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      v[c] = S[(c0 + c) * LD + c0 + lr];
+      y[c] = (lr == c) ? T(1) : T(0);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const T piv = readlane(v[j], j);
+      ok = ok && (piv > T(0));
+      const T rs = rsqrt_nr(piv);
+      rsv[j] = rs;
+      const T lj = v[j] * rs;  // L[lr][j]
+#pragma unroll
+      for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane(v[j], c) * rs);
+      v[j] = lr > j ? lj : (lr == j ? piv * rs : T(0));
+    }
+    // y = L^-1: with row y_j final, y_r -= (L[r][j] / L[j][j]) y_j for r > j
+#pragma unroll
+    for (int j = 0; j < 15; ++j) {
+      const T f = v[j] * rsv[j];
+#pragma unroll
+      for (int c = 0; c <= j; ++c) {
+        const T yjc = readlane(y[c], j);
+        if (lr > j) y[c] -= f * yjc;
+      }
+    }
+    T my_rs = T(0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) my_rs = (lr == j) ? rsv[j] : my_rs;
+    if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        v[c] = S[(c0 + c) * LD + c0 + lr];
-        y[c] = (lr == c) ? T(1) : T(0);
+        S[(c0 + c) * LD + c0 + lr] = v[c];
+        Dinv[p][c * 16 + lr] = y[c] * my_rs;
       }
-      bool ok = true;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const T piv = readlane(v[j], j);
-        ok = ok && (piv > T(0));
-        const T rs = rsqrt_nr(piv);
-        rsv[j] = rs;
-        const T lj = v[j] * rs;  // L[lr][j]
-#pragma unroll
-        for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane(v[j], c) * rs);
-        v[j] = lr > j ? lj : (lr == j ? piv * rs : T(0));
-      }
-      // y = L^-1: with row y_j final, y_r -= (L[r][j] / L[j][j]) y_j for r > j
-#pragma unroll
-      for (int j = 0; j < 15; ++j) {
-        const T f = v[j] * rsv[j];
-#pragma unroll
-        for (int c = 0; c <= j; ++c) {
-          const T yjc = readlane(y[c], j);
-          if (lr > j) y[c] -= f * yjc;
-        }
-      }
-      T my_rs = T(0);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) my_rs = (lr == j) ? rsv[j] : my_rs;
-      if (lane < 16) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          S[(c0 + c) * LD + c0 + lr] = v[c];
-          Dinv[p][c * 16 + lr] = y[c] * my_rs;
-        }
-      }
-      if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
     }
-    __syncthreads();
-    // ---- 2. panel: L_ip = A_ip L_pp^-T ----
+    if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
+  };
+  // Trailing block (i, j) -= L_ip L_jp^T (one wave, MFMA).
+  auto trailing_block = [&](int p, int i, int j) {
+    const int c0 = 16 * p;
+    typename MF::acc_t acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kk + lg;
+      const T a = -S[(c0 + k) * LD + 16 * i + lr];
+      const T bb = S[(c0 + k) * LD + 16 * j + lr];
+      acc = MF::mma(a, bb, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+  };
+
+  // Factorisation with a one-panel lookahead: after the panel solve of p,
+  // wave 0 updates the next diagonal block (p + 1, p + 1) and factors it at
+  // once while the other waves update the rest of the trailing blocks.  (The
+  // block's update and its factorisation are ordered within wave 0: its
+  // LDS writes complete before the factorisation reads them.)
+  if (wid == 0) factor_diag(0);
+  __syncthreads();
+  for (int p = 0; p < NPAN; ++p) {
+    const int c0 = 16 * p;
+    // ---- panel: L_ip = A_ip L_pp^-T ----
     for (int i = p + 1 + wid; i < NPAN; i += NW) {
       typename MF::acc_t acc = MF::zero();
 #pragma unroll
@@ -437,29 +464,24 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
       for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
     }
     __syncthreads();
-    // ---- 3. trailing: A_ij -= L_ip L_jp^T, p < j <= i ----
-    {
+    if (p + 1 == NPAN) break;
+    // ---- trailing: A_ij -= L_ip L_jp^T, p < j <= i; block (p+1, p+1) and
+    // the next diagonal factorisation on wave 0, the others on waves 1.. ----
+    if (wid == 0) {
+      trailing_block(p, p + 1, p + 1);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      factor_diag(p + 1);
+    } else {
       const int m = NPAN - 1 - p;  // trailing block rows
       const int nblk = m * (m + 1) / 2;
-      for (int b = wid; b < nblk; b += NW) {
+      for (int b = wid; b < nblk; b += NW - 1) {
         int jj = 0, rem = b;  // b -> (ii, jj) in the lower triangle of m x m blocks
         while (rem >= m - jj) {
           rem -= m - jj;
           ++jj;
         }
-        const int i = p + 1 + jj + rem, j = p + 1 + jj;
-        typename MF::acc_t acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int k = 4 * kk + lg;
-          const T a = -S[(c0 + k) * LD + 16 * i + lr];
-          const T bb = S[(c0 + k) * LD + 16 * j + lr];
-          acc = MF::mma(a, bb, acc);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+        trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
       }
     }
     __syncthreads();
