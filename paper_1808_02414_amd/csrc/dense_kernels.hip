@@ -320,7 +320,9 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 // Inversion (forward elimination of L Y = I by block rows), panel p:
 //   a. L(., p) is staged in the unused upper blocks of block row p, and
 //      Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1;
-//   b. W(i, c) -= L_ip Y(p, c) for i > p, c <= p.
+//   b. W(i, c) -= L_ip Y(p, c) for i > p, c <= p;
+// step a of panel p runs beside its trailing update, step b beside the
+// panel solve of p + 1.
 // Writes L^-1 (lower) into the tile and zeros above its diagonal.
 // ---------------------------------------------------------------------------
 constexpr int kLP = 4;  // LDS leading-dimension padding
@@ -441,107 +443,128 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
   };
 
-  // Factorisation with a one-panel lookahead: after the panel solve of p,
-  // wave 0 updates the next diagonal block (p + 1, p + 1) and factors it at
-  // once while the other waves update the rest of the trailing blocks.  (The
-  // block's update and its factorisation are ordered within wave 0: its
-  // LDS writes complete before the factorisation reads them.)
-  if (wid == 0) factor_diag(0);
-  __syncthreads();
-  for (int p = 0; p < NPAN; ++p) {
+  // Inversion steps of panel p (forward elimination L Y = I by block rows):
+  //   a. stage L(i, p), i > p, in block (p, i) (upper, unused); Y(p, c) =
+  //      L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1 (into block (p, c));
+  //   b. W(i, c) -= L_ip Y(p, c), i > p, c <= p (W(i, p) starts at zero).
+  // Once the panel solve of p has run, the factorisation reads only column
+  // blocks beyond p and lower blocks, so step a of p runs beside the trailing
+  // update of p and step b of p beside the panel solve of p + 1.
+  auto inv_stage = [&](int p, int i) {
     const int c0 = 16 * p;
-    // ---- panel: L_ip = A_ip L_pp^-T ----
-    for (int i = p + 1 + wid; i < NPAN; i += NW) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = MF::row(lane, v);  // (row r, col lr) of L_ip
+      S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
+    }
+  };
+  auto inv_y = [&](int p, int c) {
+    const int c0 = 16 * p;
+    if (c == p) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = lg + 4 * v;
+        S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * 16 + lr];
+      }
+    } else {
       typename MF::acc_t acc = MF::zero();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int k = 4 * kk + lg;
-        const T a = S[(c0 + k) * LD + 16 * i + lr];
-        const T b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+        const T a = Dinv[p][k * 16 + lr];           // (L_pp^-1)[lr][k]
+        const T b = S[(16 * c + lr) * LD + c0 + k];  // W(p, c)[k][lr]
         acc = MF::mma(a, b, acc);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+      for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + MF::row(lane, v)] = acc[v];
     }
-    __syncthreads();
-    if (p + 1 == NPAN) break;
-    // ---- trailing: A_ij -= L_ip L_jp^T, p < j <= i; block (p+1, p+1) and
-    // the next diagonal factorisation on wave 0, the others on waves 1.. ----
-    if (wid == 0) {
-      trailing_block(p, p + 1, p + 1);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      factor_diag(p + 1);
-    } else {
-      const int m = NPAN - 1 - p;  // trailing block rows
-      const int nblk = m * (m + 1) / 2;
-      for (int b = wid; b < nblk; b += NW - 1) {
-        int jj = 0, rem = b;  // b -> (ii, jj) in the lower triangle of m x m blocks
-        while (rem >= m - jj) {
-          rem -= m - jj;
-          ++jj;
-        }
-        trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
-      }
+  };
+  auto inv_update = [&](int p, int i, int c) {
+    const int c0 = 16 * p;
+    typename MF::acc_t acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      acc[v] = (c == p) ? T(0) : S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kk + lg;
+      const T a = -S[(16 * i + k) * LD + c0 + lr];  // L_ip[lr][k] from the stage
+      const T bb = S[(16 * c + lr) * LD + c0 + k];  // Y(p, c)[k][lr]
+      acc = MF::mma(a, bb, acc);
     }
-    __syncthreads();
-  }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+  };
 
-  // ---- inversion by block rows ----
+  // Factorisation with a one-panel lookahead (wave 0 updates the next
+  // diagonal block and factors it while the other waves finish the trailing
+  // update; the block's update and its factorisation are ordered within wave
+  // 0, its LDS writes complete before the factorisation reads them), fused
+  // with the inversion steps: two barriers per panel.
+  if (wid == 0) factor_diag(0);
+  __syncthreads();
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
-    // a. stage L(i, p), i > p, in block (p, i) (upper, unused); Y(p, c)
-    for (int i = p + 1 + wid; i < NPAN; i += NW) {
+    // ---- phase A: panel L_ip = A_ip L_pp^-T (i > p)  and  step b of p - 1 ----
+    {
+      const int npan = NPAN - 1 - p;
+      const int nb = p > 0 ? (NPAN - p) * p : 0;  // i in [p, NPAN), c in [0, p)
+      for (int t = wid; t < npan + nb; t += NW) {
+        if (t < npan) {
+          const int i = p + 1 + t;
+          typename MF::acc_t acc = MF::zero();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = MF::row(lane, v);  // (row r, col lr) of L_ip
-        S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
-      }
-    }
-    for (int c = wid; c <= p; c += NW) {
-      if (c == p) {
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + lg;
+            const T a = S[(c0 + k) * LD + 16 * i + lr];
+            const T b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+            acc = MF::mma(a, b, acc);
+          }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int col = lg + 4 * v;
-          S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * 16 + lr];
+          for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+        } else {
+          const int u = t - npan, m = NPAN - p;
+          inv_update(p - 1, p + u % m, u / m);
         }
-      } else {
-        typename MF::acc_t acc = MF::zero();
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int k = 4 * kk + lg;
-          const T a = Dinv[p][k * 16 + lr];           // (L_pp^-1)[lr][k]
-          const T b = S[(16 * c + lr) * LD + c0 + k];  // W(p, c)[k][lr]
-          acc = MF::mma(a, b, acc);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + MF::row(lane, v)] = acc[v];
       }
     }
     __syncthreads();
-    // b. W(i, c) -= L_ip Y(p, c), i > p, c <= p (W(i, p) starts at zero)
+    // ---- phase B: trailing A_ij -= L_ip L_jp^T (p < j <= i) with block
+    // (p+1, p+1) and the next diagonal factorisation on wave 0, and step a
+    // of p on the other waves ----
     {
-      const int m = NPAN - 1 - p;
-      const int nblk = m * (p + 1);
-      for (int b = wid; b < nblk; b += NW) {
-        const int i = p + 1 + b % m, c = b / m;
-        typename MF::acc_t acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          acc[v] = (c == p) ? T(0) : S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int k = 4 * kk + lg;
-          const T a = -S[(16 * i + k) * LD + c0 + lr];  // L_ip[lr][k] from the stage
-          const T bb = S[(16 * c + lr) * LD + c0 + k];  // Y(p, c)[k][lr]
-          acc = MF::mma(a, bb, acc);
+      const int m = NPAN - 1 - p;          // trailing block rows
+      const int ntr = m * (m + 1) / 2;     // trailing blocks, block (p+1, p+1) first
+      const int na = m + p + 1;            // stagings, Y(p, c < p), Y(p, p)
+      const bool look = p + 1 < NPAN;
+      if (look && wid == 0) {
+        trailing_block(p, p + 1, p + 1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        factor_diag(p + 1);
+      } else {
+        const int w0 = look ? 1 : 0, nw = look ? NW - 1 : NW;
+        const int first = look ? 1 : 0;  // block (p+1, p+1) is wave 0's
+        for (int t = wid - w0; t < (ntr - first) + na; t += nw) {
+          if (t < ntr - first) {
+            int jj = 0, rem = t + first;  // -> (ii, jj) in the lower triangle of m x m blocks
+            while (rem >= m - jj) {
+              rem -= m - jj;
+              ++jj;
+            }
+            trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
+          } else {
+            const int u = t - (ntr - first);
+            if (u < m) inv_stage(p, p + 1 + u);
+            else inv_y(p, u - m);
+          }
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
       }
     }
     __syncthreads();
   }
+  // step b of the last panel has no rows below it
+
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     const int e = 2 * (tid + NT * k);
