@@ -250,7 +250,12 @@ def spiral_slab(seed: int = 0, n: int = 500, m: int = 50_000, p_geom: float = 0.
     K = int(min(n, 2 * max_track + 20))
     pts_l, cand_l, vis_l = [], [], []
     have = 0
+    rounds = 0
     while have < m:
+        rounds += 1
+        if rounds > 200:
+            raise RuntimeError("spiral_slab: too few points are seen by two cameras "
+                               f"({have} of {m}); use more cameras")
         b = int(1.3 * (m - have)) + 64
         # a ray through a random pixel of a random camera, cut at a random
         # height of the slab

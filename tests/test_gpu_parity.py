@@ -121,6 +121,57 @@ def test_covariance_ragged(ucov, n, m):
     assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
 
 
+def smallest_scenes():
+    """Two and three cameras of a circle seeing every point (the smallest
+    connected scenes).  Two cameras whose optical axes meet are degenerate
+    for two unknown focal lengths, so the two-camera scene tilts both."""
+    from scipy.spatial.transform import Rotation
+    base = sg.tiny_circle(31, n=10, m=150)
+    out = []
+    for n in (2, 3):
+        cams = base.cams[:n].copy()
+        if n == 2:
+            cams[1, :3] = (Rotation.from_rotvec([0.0, 0.0, 0.12]) * Rotation.from_rotvec(cams[1, :3])).as_rotvec()
+            cams[0, :3] = (Rotation.from_rotvec([0.08, 0.0, 0.0]) * Rotation.from_rotvec(cams[0, :3])).as_rotvec()
+        oc = np.tile(np.arange(n), base.n_pts).astype(np.int32)
+        op = np.repeat(np.arange(base.n_pts), n).astype(np.int32)
+        out.append(sg.Scene(cams, base.pts, oc, op))
+    return out
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_covariance_smallest_scenes(ucov, which):
+    u, ctx = ucov
+    s = smallest_scenes()[which]
+    print(f"covariance smallest scene n={s.n_cams}", flush=True)
+    got, _ = ctx.camera_covariance(dev(u, s))
+    fro, scaled = block_errors(got.cpu().numpy(), oracle_cov(s)["blocks"])
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+def test_covariance_exact_tile_multiple(ucov):
+    """64 cameras: 9n = 576 is a multiple of the 64 tile, so no padding."""
+    u, ctx = ucov
+    s = sg.tiny_circle(21, n=64, m=3000, track=(3, 6))
+    print("covariance n=64 (no padding)", flush=True)
+    got, _ = ctx.camera_covariance(dev(u, s))
+    fro, scaled = block_errors(got.cpu().numpy(), oracle_cov(s)["blocks"])
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+
+
+def test_rejects_too_small_inputs(ucov):
+    u, ctx = ucov
+    s = sg.tiny_circle(22)
+    one = sg.Scene(s.cams[:1], s.pts, np.zeros(s.n_pts, np.int32), np.arange(s.n_pts, dtype=np.int32))
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, one))
+    assert e.value.kind == "EINVAL"
+    empty = sg.Scene(s.cams, s.pts, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, empty))
+    assert e.value.kind == "EINVAL"
+
+
 def test_covariance_full_medium_scene(ucov):
     """The 500-camera spiral scene (Z 4500 x 4500), every block."""
     u, ctx = ucov
