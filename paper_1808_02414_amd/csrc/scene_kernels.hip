@@ -145,16 +145,51 @@ __global__ void k_fill_slots(SceneDev sc, const int64_t *ptr_p, int32_t *cur_p,
 }
 
 // One thread per point: order its observations by camera, reject duplicate
-// cameras and points with fewer than two observations.
-__global__ void k_sort_points(SceneDev sc, const int64_t *ptr_p, int32_t *slot_obs,
-                              int32_t *slot_cam, int32_t *slot_pt, DevStatus *ds) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
+// cameras and points with fewer than two observations.  Tracks of up to
+// kSortCap observations are sorted as (camera, observation) keys in LDS
+// (interleaved across the threads); longer ones in place in global memory.
+constexpr int kSortThreads = 128;
+constexpr int kSortCap = 32;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_points(SceneDev sc, const int64_t *ptr_p,
+                                                              int32_t *slot_obs, int32_t *slot_cam,
+                                                              int32_t *slot_pt, DevStatus *ds) {
+  __shared__ int64_t keys[kSortCap * kSortThreads];
+  const int tid = threadIdx.x;
+  int j = blockIdx.x * blockDim.x + tid;
   if (j >= sc.m) return;
   int64_t p0 = ptr_p[j], p1 = ptr_p[j + 1];
-  if (p1 - p0 < 2) {
+  const int64_t t = p1 - p0;
+  if (t < 2) {
     report_error(ds, UCOV_EPOINT, j);
   }
-  // insertion sort of the (small) segment by camera id
+  if (t <= kSortCap) {
+    for (int a = 0; a < t; ++a) {
+      const int32_t o = slot_obs[p0 + a];
+      keys[a * kSortThreads + tid] = ((int64_t)sc.oc[o] << 32) | (uint32_t)o;
+    }
+    for (int a = 1; a < t; ++a) {
+      const int64_t k = keys[a * kSortThreads + tid];
+      int b = a - 1;
+      while (b >= 0 && keys[b * kSortThreads + tid] > k) {
+        keys[(b + 1) * kSortThreads + tid] = keys[b * kSortThreads + tid];
+        --b;
+      }
+      keys[(b + 1) * kSortThreads + tid] = k;
+    }
+    int32_t prev = -1;
+    for (int a = 0; a < t; ++a) {
+      const int64_t k = keys[a * kSortThreads + tid];
+      const int32_t c = (int32_t)(k >> 32), o = (int32_t)(k & 0xffffffff);
+      if (c == prev) report_error(ds, UCOV_EINVAL, o);
+      prev = c;
+      slot_obs[p0 + a] = o;
+      slot_cam[p0 + a] = c;
+      slot_pt[p0 + a] = j;
+    }
+    return;
+  }
+  // insertion sort of a long segment by camera id
   for (int64_t a = p0 + 1; a < p1; ++a) {
     int32_t o = slot_obs[a];
     int32_t c = sc.oc[o];
@@ -537,7 +572,7 @@ __global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t 
 // ---------------------------------------------------------------------------
 // step a3: Cholesky-QR2 orthonormalisation, gauge weight, Jacobi scaling
 // ---------------------------------------------------------------------------
-constexpr int kGaugeThreads = 1024;
+constexpr int kGaugeThreads = 512;
 
 __device__ inline double block_sum(double v, double *red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -586,8 +621,10 @@ __device__ __forceinline__ bool cholqr_pass(int64_t N, int64_t ld, const double 
     __syncthreads();
   }
   __shared__ int okflag;
+  // the 7 x 7 factorisation runs on one thread; its matrices live in LDS
+  // (as private arrays indexed in loops they would go to scratch memory)
+  __shared__ double G[7][7], L[7][7], Li[7][7];
   if (threadIdx.x == 0) {
-    double G[7][7], L[7][7];
     int idx = 0;
     for (int a = 0; a < 7; ++a)
       for (int b = a; b < 7; ++b) {
@@ -613,7 +650,6 @@ __device__ __forceinline__ bool cholqr_pass(int64_t N, int64_t ld, const double 
       }
     }
     // R = L^T (upper); Ri = R^-1 = (L^-1)^T
-    double Li[7][7];
     for (int a = 0; a < 7; ++a)
       for (int b = 0; b < 7; ++b) Li[a][b] = 0.0;
     if (ok) {
@@ -1095,8 +1131,8 @@ void launch_count_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStr
 void launch_group_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_slots, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
                      w.ptr_p, w.cur_p, w.slot_obs);
-  hipLaunchKernelGGL(k_sort_points, dim3(blocks_for(sc.m, kBlk)), dim3(kBlk), 0, st, sc,
-                     w.ptr_p, w.slot_obs, w.slot_cam, w.slot_pt, ds);
+  hipLaunchKernelGGL(k_sort_points, dim3(blocks_for(sc.m, kSortThreads)), dim3(kSortThreads), 0,
+                     st, sc, w.ptr_p, w.slot_obs, w.slot_cam, w.slot_pt, ds);
 }
 
 void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *jx_out,
