@@ -5,7 +5,7 @@ features, for fast screening of reconstructions.  Screening cameras by their
 uncertainty, e.g. to drop mostly unconstrained ones before bundle adjustment,
 is one of the uses the paper motivates (Sec. 1).  The network itself is not
 part of the paper; the exact covariance (Sec. 5) is its training label and
-the judge of its error.
+the reference for its error.
 
 Everything here is plain FP64 numpy, written for checking, not speed:
 

@@ -11,7 +11,7 @@ the training loop and the statistics that standardise inputs and outputs
 device).
 
 The exact covariances that label the training set come from
-``Context.camera_covariance`` and stay the judge of the network's error.
+``Context.camera_covariance`` and remain the reference for the network's error.
 """
 from __future__ import annotations
 
