@@ -91,6 +91,9 @@ def run_single(args, ucov, torch, np, scene):
     ctx = ucov.Context(0)
     dev = ucov.DeviceScene.from_scene(scene, "cuda:0")
     prec = ucov.FP64 if args.precision == "fp64" else ucov.FP32_NS
+    if prec == ucov.FP64 and not args.no_tune:
+        # the library's tile-schedule tuning for this size, before the timed steps
+        args.tuned_threshold = ctx.tune_dense(9 * scene.n_cams)[0]
     out = torch.empty((scene.n_cams, 9, 9), dtype=torch.float64, device="cuda:0")
     for _ in range(args.warmup):
         ctx.camera_covariance(dev, precision=prec, out=out)
@@ -130,6 +133,8 @@ def main():
                     default="spiral500")
     ap.add_argument("--precision", choices=["fp64", "fp32ns"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default dense tile schedule instead of tuning it for the size")
     ap.add_argument("--n-cams", type=int, default=500)
     ap.add_argument("--n-pts", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -210,6 +215,8 @@ def main():
         "stages_ms": stages,
         "n_pairs": int(reps[-1]["n_pairs"]),
     }
+    if getattr(args, "tuned_threshold", None) is not None:
+        line["dense_tile_threshold"] = args.tuned_threshold
     if args.precision == "fp32ns":
         line["ns_iters"] = int(reps[-1]["ns_iters"])
         line["ns_residual"] = float(reps[-1]["ns_residual"])

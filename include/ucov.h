@@ -197,6 +197,17 @@ int ucov_update_covariance(ucov_ctx *ctx, const ucov_scene *scene, int64_t n_new
                            const double *cam_new, double *cam_cov, int64_t ldc, double *new_cov,
                            double *new_cross, ucov_report *rep);
 
+/* Tune the dense stage's tile schedule for matrices of size n (N = 9 n_cams
+ * of a scene): the recursion's products run on 64 x 64 or 32 x 32 MFMA tiles
+ * depending on their size; every candidate threshold is timed on a synthetic
+ * positive definite matrix of the padded size and the fastest is kept in this
+ * context for that size (used by ucov_camera_covariance and
+ * ucov_full_covariance in UCOV_FP64).  Results are unchanged by the choice up
+ * to rounding order.  threshold (HOST, or NULL): the chosen number of 64 x 64
+ * tiles below which products use 32 x 32 tiles; ms (HOST, or NULL): its dense
+ * stage time.  Allocates the dense workspace for that size. */
+int ucov_tune_dense(ucov_ctx *ctx, int64_t n, int64_t *threshold, float *ms);
+
 /* Covariance blocks of several independent scenes in one call: the
  * sub-reconstructions of Sec. 6, each evaluated exactly on its own gauge (a
  * camera's covariance from a sub-reconstruction around it bounds the one from

@@ -52,7 +52,7 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
            "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
-           "ucov_full_covariance", "ucov_update_covariance"]
+           "ucov_full_covariance", "ucov_update_covariance", "ucov_tune_dense"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
                                                 P, I64, P, ctypes.POINTER(Report)]),
         "ucov_update_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), I64, P, P, P, P, P, I64,
                                                   P, P, ctypes.POINTER(Report)]),
+        "ucov_tune_dense": (ctypes.c_int, [P, I64, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)]),
         "ucov_jacobians": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, P]),
         "ucov_reduced_camera_matrix": (ctypes.c_int, [P, ctypes.POINTER(Scene), P, I64,
                                                       ctypes.POINTER(Report)]),
@@ -272,6 +273,15 @@ class Context:
                                              ptr(ncov), ptr(ncross), ctypes.byref(rep))
         self._check(rc, rep)
         return cam_cov, ncov, ncross, rep.as_dict()
+
+    def tune_dense(self, n: int):
+        """Pick the dense stage's tile schedule for matrices of size n (9 per
+        camera); returns (threshold, milliseconds of the chosen schedule)."""
+        th = ctypes.c_int64()
+        ms = ctypes.c_float()
+        self._stream()
+        self._check(self.lib.ucov_tune_dense(self.h, int(n), ctypes.byref(th), ctypes.byref(ms)))
+        return int(th.value), float(ms.value)
 
     def camera_covariance_batched(self, scenes, alpha=0.0, out=None):
         """Covariance blocks of independent scenes in one call: a list of

@@ -648,6 +648,15 @@ __global__ __launch_bounds__(256) void k_mirror_lower(double *a, int64_t lda) {
   }
 }
 
+// A symmetric positive definite test matrix for timing the dense stage:
+// a_ij = 0.5 exp(-|i - j| / 8) off the diagonal, 10 on it (diagonally dominant).
+__global__ void k_tuning_matrix(int64_t n, double *a, int64_t lda) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r >= n) return;
+  const double d = (double)(r > c ? r - c : c - r);
+  a[r + c * lda] = r == c ? 10.0 : 0.5 * exp(-d / 8.0);
+}
+
 // ---------------------------------------------------------------------------
 // elementwise helpers
 // ---------------------------------------------------------------------------
@@ -865,14 +874,14 @@ GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, 
   return g;
 }
 
-// Products with fewer 64 x 64 tiles than this run on 32 x 32 tiles.
-constexpr int64_t kSmallTiles = 1024;
-
+// Products with fewer 64 x 64 tiles than `small` run on 32 x 32 tiles
+// (kSmallTilesDefault unless the size was tuned).
 template <typename T, bool AT, bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
-          T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st) {
+          T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st,
+          int64_t small = kSmallTilesDefault) {
   GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
-  if ((M / 64) * (N / 64) < kSmallTiles) {
+  if ((M / 64) * (N / 64) < small) {
     hipLaunchKernelGGL((k_gemm32<T, AT, BT, LOWER>), dim3((unsigned)(M / 32), (unsigned)(N / 32)),
                        dim3(64), 0, st, g);
     return;
@@ -882,9 +891,10 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
 }
 
 template <typename T>
-void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st) {
+void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st,
+               int64_t small = kSmallTilesDefault) {
   const unsigned a = (unsigned)((s.M / 64) * (s.N / 64)), b = (unsigned)((t.M / 64) * (t.N / 64));
-  if (a + b < kSmallTiles) {
+  if ((int64_t)a + b < small) {
     const unsigned a32 = (unsigned)((s.M / 32) * (s.N / 32)),
                    b32 = (unsigned)((t.M / 32) * (t.N / 32));
     hipLaunchKernelGGL((k_gemm32_pair<T>), dim3(a32 + b32), dim3(64), 0, st, s, t, (int)a32);
@@ -906,7 +916,8 @@ int64_t recurse_scratch(int64_t n) {
 // the right subtree was measured slower at every node size: the concurrent
 // products slow each other and the cross-stream waits add latency.)
 template <typename T>
-void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hipStream_t st) {
+void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hipStream_t st,
+             int64_t small = kSmallTilesDefault) {
   if (n == 64) {
     hipLaunchKernelGGL((k_leaf_mfma<T, 64>), dim3(1), dim3(LeafThreads<64>::value), 0, st, A, lda,
                        o, ds);
@@ -922,16 +933,18 @@ void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hip
   T *T2 = tmp;
   T *Tm = tmp + n2 * n1;
   T *child = Tm;
-  recurse(A, lda, o, n1, child, ds, st);
+  recurse(A, lda, o, n1, child, ds, st, small);
   T *A11 = A + o + o * lda;
   T *A21 = A + (o + n1) + o * lda;
   T *A22 = A + (o + n1) + (o + n1) * lda;
   const T one = T(1), zero = T(0), mone = T(-1);
-  gemm<T, false, true, false>(n2, n1, n1, A21, lda, A11, lda, Tm, n2, one, zero, kLeN, st);  // L21
+  gemm<T, false, true, false>(n2, n1, n1, A21, lda, A11, lda, Tm, n2, one, zero, kLeN, st,
+                              small);  // L21
   gemm_pair<T>(make_args<T>(n2, n2, n1, Tm, n2, Tm, n2, A22, lda, mone, one, kFull),  // Schur
-               make_args<T>(n2, n1, n1, Tm, n2, A11, lda, T2, n2, one, zero, kGeN), st);
-  recurse(A, lda, o + n1, n2, child, ds, st);
-  gemm<T, false, false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, mone, zero, kLeM, st);
+               make_args<T>(n2, n1, n1, Tm, n2, A11, lda, T2, n2, one, zero, kGeN), st, small);
+  recurse(A, lda, o + n1, n2, child, ds, st, small);
+  gemm<T, false, false, false>(n2, n1, n2, A22, lda, T2, n2, A21, lda, mone, zero, kLeM, st,
+                               small);
 }
 
 }  // namespace
@@ -1255,6 +1268,10 @@ void launch_scale_dense(int64_t N, const double *z, int64_t ldz, const double *q
   hipLaunchKernelGGL(k_scale_dense, grid2(N), dim3(256), 0, st, N, z, ldz, q, s, alpha, a, lda);
 }
 
+void launch_tuning_matrix(int64_t n, double *a, int64_t lda, hipStream_t st) {
+  hipLaunchKernelGGL(k_tuning_matrix, grid2(n), dim3(256), 0, st, n, a, lda);
+}
+
 void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStream_t st) {
   if (Np == N) return;
   hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)Np), dim3(64), 0, st, N, Np, a, lda);
@@ -1263,8 +1280,8 @@ void launch_pad_identity(int64_t N, int64_t Np, double *a, int64_t lda, hipStrea
 int64_t spd_lower_inverse_scratch(int64_t Np) { return recurse_scratch(Np); }
 
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
-                            hipStream_t st) {
-  recurse<double>(a, lda, 0, Np, tmp, ds, st);
+                            hipStream_t st, int64_t small) {
+  recurse<double>(a, lda, 0, Np, tmp, ds, st, small);
 }
 
 static_assert((int)kFull == (int)kGemmFull && (int)kLeN == (int)kGemmLeN &&

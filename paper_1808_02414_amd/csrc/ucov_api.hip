@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 #include <unordered_map>
+#include <map>
 #include <vector>
 
 #include "ucov_internal.h"
@@ -58,6 +59,12 @@ struct ucov_ctx {
   // learned screener
   Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
   Buf pg_f;  // the paper gauge's F (28 upper values), then L_F (7 x 7 row-major)
+  // dense stage: the tuned 32 x 32-tile threshold per padded size
+  std::map<int64_t, int64_t> small_tiles;
+  int64_t small_for(int64_t np) const {
+    const auto it = small_tiles.find(np);
+    return it == small_tiles.end() ? kSmallTilesDefault : it->second;
+  }
   Buf fc_x, fc_part, fc_xq, fc_k;  // whole covariance: X, X q partial sums, X q, q^T X q
   // incremental update: indices, padded Z^+, JtT, B, T, S, scratch, Jacobians, J_n, U, small, V, W
   Buf up_idx, up_z, up_jt, up_b, up_t, up_s, up_tmp, up_nj, up_jn, up_u, up_g, up_v, up_w;
@@ -343,7 +350,7 @@ int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_o
   hipEventRecord(c->ev[3], st);
   if (o.precision == UCOV_FP64) {
     UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
-    spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
+    spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st, c->small_for(Np));
     hipEventRecord(c->ev[4], st);
     launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), N, as<double>(c->alpha),
                    o.gauge != UCOV_GAUGE_PAPER, cov_out, st);
@@ -591,7 +598,7 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
   launch_pad_identity(N, Np, A, Np, st);
   UCOV_TRY(check_hip(c, "assemble"));
   hipEventRecord(c->ev[3], st);
-  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st);
+  spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st, c->small_for(Np));
   spd_inverse_from_factor(A, Np, Np, X, Np, st);
   hipEventRecord(c->ev[4], st);
   if (cam_cov) launch_full_camera(N, X, Np, w.s, w.q, w.alpha, !paper, cam_cov, ldc, st);
@@ -734,6 +741,47 @@ int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
     hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
     hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
   }
+  return UCOV_OK;
+}
+
+// Tile schedule of the dense stage for matrices of size n: every candidate
+// threshold for running the recursion's products on 32 x 32 instead of 64 x 64
+// tiles is timed on a synthetic positive definite matrix of the padded size
+// (best of three), and the fastest is kept for that size in this context.
+int ucov_tune_dense(ucov_ctx *c, int64_t n, int64_t *threshold, float *ms) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 1) return c->fail(UCOV_EINVAL, "n must be positive");
+  hipSetDevice(c->device);
+  const int64_t Np = round_up(n, kTile);
+  UCOV_TRY(ensure(c, c->amat, 8 * Np * Np));
+  UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
+  hipStream_t st = c->stream;
+  clear_status(c);
+  static const int64_t cand[] = {0, 256, 1024, 4096, (int64_t)1 << 40};
+  int64_t best = kSmallTilesDefault;
+  float best_ms = 0.0f;
+  for (int64_t small : cand) {
+    float t_min = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      launch_tuning_matrix(Np, as<double>(c->amat), Np, st);
+      hipEventRecord(c->ev[6], st);
+      spd_lower_inverse_fp64(as<double>(c->amat), Np, Np, as<double>(c->tmat), c->ds, st, small);
+      hipEventRecord(c->ev[7], st);
+      if (hipEventSynchronize(c->ev[7]) != hipSuccess) return c->fail(UCOV_EDEVICE, "tuning run");
+      float t = 0.0f;
+      hipEventElapsedTime(&t, c->ev[6], c->ev[7]);
+      if (rep == 0 || t < t_min) t_min = t;
+    }
+    if (best_ms == 0.0f || t_min < best_ms) {
+      best_ms = t_min;
+      best = small;
+    }
+  }
+  UCOV_TRY(check_hip(c, "tuning"));
+  UCOV_TRY(sync_status(c, nullptr, "tuning"));
+  c->small_tiles[Np] = best;
+  if (threshold) *threshold = best;
+  if (ms) *ms = best_ms;
   return UCOV_OK;
 }
 

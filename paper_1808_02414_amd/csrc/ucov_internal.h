@@ -213,8 +213,14 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st);
 // Host-only check of the plan for matrices of sizes np: every access inside
 // its matrix or scratch, every column block factored once.  0 when it holds.
 int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t *n_launches);
+// Products of the recursion with fewer 64 x 64 tiles than `small` run on
+// 32 x 32 tiles; the default comes from a sweep on the 4500 x 4500 case,
+// ucov_tune_dense picks it per size.
+constexpr int64_t kSmallTilesDefault = 1024;
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
-                            hipStream_t st);
+                            hipStream_t st, int64_t small = kSmallTilesDefault);
+// n x n symmetric positive definite matrix for timing (no padding).
+void launch_tuning_matrix(int64_t n, double *a, int64_t lda, hipStream_t st);
 // C = alpha op(A) op(B) + beta C in FP64 on the MFMA tile kernels (column-
 // major; M, N, K multiples of 64).  at: A stored K x M; bt: B stored N x K;
 // lower: only tiles on or below the diagonal (with at and no bt only).

@@ -172,6 +172,21 @@ def test_rejects_too_small_inputs(ucov):
     assert e.value.kind == "EINVAL"
 
 
+def test_tune_dense_then_covariance(ucov):
+    """The tile-schedule tuning picks one of its candidates and the
+    covariance computed with it still matches the oracle."""
+    u, ctx = ucov
+    s = sg.spiral_slab(13, n=150, m=15000)
+    th, ms = ctx.tune_dense(9 * s.n_cams)
+    print(f"tuned threshold {th} ({ms:.3f} ms)", flush=True)
+    assert th in (0, 256, 1024, 4096, 1 << 40) and ms > 0.0
+    got, _ = ctx.camera_covariance(dev(u, s))
+    fro, scaled = block_errors(got.cpu().numpy(), oracle_cov(s)["blocks"])
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    with pytest.raises(u.UcovError):
+        ctx.tune_dense(0)
+
+
 def test_covariance_full_medium_scene(ucov):
     """The 500-camera spiral scene (Z 4500 x 4500), every block."""
     u, ctx = ucov
