@@ -187,7 +187,8 @@ int ucov_full_covariance(ucov_ctx *ctx, const ucov_scene *scene, const ucov_opti
  * after the addition.  new_cov (9 x 9 row-major) and new_cross (N x 9
  * row-major: old parameter, new-camera parameter) receive the new camera's
  * covariance and its cross-covariance with the old cameras, or are NULL;
- * UCOV_EGAUGE when the new camera's observations do not determine it.
+ * UCOV_EGAUGE when the new camera's observations do not determine it.  On
+ * any error cam_cov is left as it was.
  * Device workspace: an Np x Np matrix and three Np x Kp ones (Np = N, Kp =
  * 2 n_new, each rounded up to 64).
  * rep: ms_schur covers the new rows, ms_inverse the Woodbury products,

@@ -731,9 +731,13 @@ int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
     if (new_cov) hipMemcpyAsync(new_cov, cn, 8 * 81, hipMemcpyDeviceToDevice, st);
   }
   hipEventRecord(c->ev[4], st);
+  // errors found on the device (a factor that does not exist, a new camera
+  // its observations do not determine) leave the caller's matrix untouched
+  UCOV_TRY(check_hip(c, "update products"));
+  UCOV_TRY(sync_status(c, rep, "covariance update"));
   launch_copy_out(N, Np, Zp, cam_cov, ldc, st);
   hipEventRecord(c->ev[5], st);
-  UCOV_TRY(check_hip(c, "update products"));
+  UCOV_TRY(check_hip(c, "update copy"));
   UCOV_TRY(sync_status(c, rep, "covariance update"));
   if (rep) {
     hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[2]);
