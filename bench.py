@@ -39,6 +39,7 @@ METRIC = "cameras/s of exact covariance + MFMA util on Z^-1, at 1e-6 rel err vs 
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_inverse_fp64_spiral500_hbm_counters.md")
+DEFAULT_TILE_THRESHOLD = 1024  # the library's untuned 32 x 32-tile threshold
 DENSE_SOURCE = os.path.join(ROOT, "paper_1808_02414_amd", "csrc", "dense_kernels.hip")
 
 
@@ -208,8 +209,11 @@ def main():
         "config": {"workload": workload, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     # the counters were taken with the default tile schedule
                      "traffic": (recorded_traffic() if args.workload == "spiral500"
-                                 and args.precision == "fp64" else None),
+                                 and args.precision == "fp64"
+                                 and getattr(args, "tuned_threshold", DEFAULT_TILE_THRESHOLD)
+                                 == DEFAULT_TILE_THRESHOLD else None),
                      "kernel": "dense inverse stage (k_leaf_mfma + k_gemm64/32 + k_gemm64/32_pair), "
                                "2N^3/3 flops per scene; traffic in bytes per step"},
         "stages_ms": stages,
