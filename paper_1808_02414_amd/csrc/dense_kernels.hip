@@ -178,14 +178,13 @@ __device__ inline void gemm_tile(const GemmArgs<T> &g, int tm, int tn) {
     }
 }
 
-// The same product on 32 x 32 tiles with one wave per workgroup, for
-// products too small to occupy every compute unit with 64 x 64 tiles: a
-// tile's K loop takes about as long as a 64 x 64 tile's, so four times the
-// workgroups finish about four times sooner while the GPU has room for them.
-// K ranges of triangular operands are cut at 32-granular bounds; the parts
-// they read above a diagonal lie inside leaf blocks, which hold zeros there.
-template <typename T, bool AT, bool BT, bool LOWER>
-__device__ inline void gemm_tile32(const GemmArgs<T> &g, int tm, int tn) {
+constexpr int kRow32 = 32 + kPad;
+constexpr int kStage32 = 2 * kKc * kRow32;  // one wave's A and B chunk (elements)
+static_assert(kStage32 >= 16 * 64, "a wave's slot also holds its partial tile");
+
+// sh: S * kStage32 elements of LDS, one slot per wave.
+template <typename T, bool AT, bool BT, bool LOWER, int S>
+__device__ inline void gemm_tile32_split(const GemmArgs<T> &g, int tm, int tn, T *sh) {
   typedef Mfma<T> MF;
   typedef typename MF::vec2 V2;
   if (LOWER && tn > tm) return;
@@ -200,15 +199,15 @@ __device__ inline void gemm_tile32(const GemmArgs<T> &g, int tm, int tn) {
   else if (kmode == kLeM) ke = min(K, (int64_t)(tm + 1) * 32);
   else if (kmode == kGeMN) kb = (int64_t)max(tm, tn) * 32;
 
-  __shared__ T As[kKc][32 + kPad];
-  __shared__ T Bs[kKc][32 + kPad];
-  const int lane = threadIdx.x;
+  constexpr int kRow = kRow32, kStage = kStage32;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  T *As = sh + wid * kStage;
+  T *Bs = As + kKc * kRow;
   typename MF::acc_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = MF::zero();
-  // loaders: 8 consecutive elements per lane per chunk
   const int lt_k = lane >> 2, lt_m = (lane & 3) * 8;  // K-major tile (M contiguous)
   const int lc_m = lane >> 1, lc_k = (lane & 1) * 8;  // M-major tile (K contiguous)
   const T *pa = AT ? A + lc_k + ((int64_t)tm * 32 + lc_m) * lda
@@ -229,59 +228,75 @@ __device__ inline void gemm_tile32(const GemmArgs<T> &g, int tm, int tn) {
       rb[2 * h + 1] = b.y;
     }
   };
-  if (kb < ke) load(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += kKc) {
-    __syncthreads();
+  auto wave_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  const int64_t step = (int64_t)S * kKc;
+  const int64_t k_first = kb + (int64_t)wid * kKc;
+  if (k_first < ke) load(k_first);
+  for (int64_t k0 = k_first; k0 < ke; k0 += step) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      if (AT) As[lc_k + v][lc_m] = ra[v];
-      else As[lt_k][lt_m + v] = ra[v];
-      if (BT) Bs[lt_k][lt_m + v] = rb[v];
-      else Bs[lc_k + v][lc_m] = rb[v];
+      if (AT) As[(lc_k + v) * kRow + lc_m] = ra[v];
+      else As[lt_k * kRow + lt_m + v] = ra[v];
+      if (BT) Bs[lt_k * kRow + lt_m + v] = rb[v];
+      else Bs[(lc_k + v) * kRow + lc_m] = rb[v];
     }
-    __syncthreads();
-    if (k0 + kKc < ke) load(k0 + kKc);
+    wave_sync();
+    if (k0 + step < ke) load(k0 + step);
 #pragma unroll
     for (int kk = 0; kk < kKc / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
       const int c = lane & 15;
-      const T a0 = As[kr][c], a1 = As[kr][16 + c];
-      const T b0 = Bs[kr][c], b1 = Bs[kr][16 + c];
+      const T a0 = As[kr * kRow + c], a1 = As[kr * kRow + 16 + c];
+      const T b0 = Bs[kr * kRow + c], b1 = Bs[kr * kRow + 16 + c];
       acc[0][0] = MF::mma(a0, b0, acc[0][0]);
       acc[0][1] = MF::mma(a0, b1, acc[0][1]);
       acc[1][0] = MF::mma(a1, b0, acc[1][0]);
       acc[1][1] = MF::mma(a1, b1, acc[1][1]);
     }
+    wave_sync();
   }
+  // partial tiles: slot of wave w holds [block 2*bi+bj][register v][lane]
+  __syncthreads();
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int64_t col = (int64_t)tn * 32 + bj * 16 + (lane & 15);
-      const int64_t row0 = (int64_t)tm * 32 + bi * 16;
+    for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        T *pc = C + row0 + MF::row(lane, v) + col * ldc;
-        const T x = g.alpha * acc[bi][bj][v];
-        *pc = g.beta == T(0) ? x : x + g.beta * (*pc);
-      }
-    }
+      for (int v = 0; v < 4; ++v) sh[wid * kStage + ((2 * bi + bj) * 4 + v) * 64 + lane] = acc[bi][bj][v];
+  __syncthreads();
+  for (int o = wid; o < 16; o += S) {  // o = 4 * block + v
+    T sum = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) sum += sh[s * kStage + o * 64 + lane];
+    const int blk = o >> 2, v = o & 3;
+    const int64_t col = (int64_t)tn * 32 + (blk & 1) * 16 + (lane & 15);
+    const int64_t row = (int64_t)tm * 32 + (blk >> 1) * 16 + MF::row(lane, v);
+    T *pc = C + row + col * ldc;
+    const T x = g.alpha * sum;
+    *pc = g.beta == T(0) ? x : x + g.beta * (*pc);
+  }
 }
 
-template <typename T, bool AT, bool BT, bool LOWER>
-__global__ __launch_bounds__(64) void k_gemm32(GemmArgs<T> g) {
-  gemm_tile32<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+template <typename T, bool AT, bool BT, bool LOWER, int S>
+__global__ __launch_bounds__(64 * S) void k_gemm32s(GemmArgs<T> g) {
+  __shared__ T sh[S * kStage32];
+  gemm_tile32_split<T, AT, BT, LOWER, S>(g, blockIdx.x, blockIdx.y, sh);
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_gemm32_pair(GemmArgs<T> s, GemmArgs<T> t, int nblk_s) {
+template <typename T, int S>
+__global__ __launch_bounds__(64 * S) void k_gemm32s_pair(GemmArgs<T> s, GemmArgs<T> t, int nblk_s) {
+  __shared__ T sh[S * kStage32];
   const int b = blockIdx.x;
   if (b < nblk_s) {
     const int mt = (int)(s.M / 32);
-    gemm_tile32<T, false, true, true>(s, b % mt, b / mt);
+    gemm_tile32_split<T, false, true, true, S>(s, b % mt, b / mt, sh);
   } else {
     const int mt = (int)(t.M / 32), bb = b - nblk_s;
-    gemm_tile32<T, false, false, false>(t, bb % mt, bb / mt);
+    gemm_tile32_split<T, false, false, false, S>(t, bb % mt, bb / mt, sh);
   }
 }
 
@@ -312,7 +327,8 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 // panels.  Factorisation, panel p:
 //   1. one wave factors the 16x16 diagonal block in registers (row per lane,
 //      scalar lane broadcasts, hardware reciprocal square roots refined by
-//      Newton steps) and inverts it: L_pp and L_pp^-1;
+//      Newton steps) and inverts it by forward elimination in the same
+//      column loop: L_pp and L_pp^-1;
 //   2. the panel below: L_ip = A_ip L_pp^-T            (MFMA, all waves)
 //   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA); wave 0 takes
 //      block (p+1, p+1) and goes straight on to step 1 of panel p + 1 while
@@ -363,21 +379,26 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   __shared__ T Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   T *G = A + o + o * lda;
-  // whole columns with paired loads (the upper part is read and discarded)
-  constexpr int NL = NB * NB / 2 / NT;
-  V2 ld2[NL];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int e = 2 * (tid + NT * k);
+  // Whole columns with paired loads (the upper part is read and discarded):
+  // column block 0 by every thread; the rest by waves 1.. while wave 0
+  // factors diagonal block 0.
+  constexpr int NL0 = 16 * NB / 2 / NT, NL1 = (NB - 16) * NB / 2 / (NT - 64);
+  static_assert(2 * NL0 * NT == 16 * NB && 2 * NL1 * (NT - 64) == (NB - 16) * NB,
+                "the leaf's loads divide evenly over its threads");
+  auto stage_pair = [&](int e, V2 x) {  // element pair (e, e + 1), column-major
     const int r = e % NB, c = e / NB;
-    ld2[k] = *reinterpret_cast<const V2 *>(G + r + (int64_t)c * lda);
-  }
+    S[c * LD + r] = r >= c ? x.x : T(0);
+    S[c * LD + r + 1] = r + 1 >= c ? x.y : T(0);
+  };
+  {
+    V2 ld2[NL0];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int e = 2 * (tid + NT * k);
-    const int r = e % NB, c = e / NB;
-    S[c * LD + r] = r >= c ? ld2[k].x : T(0);
-    S[c * LD + r + 1] = r + 1 >= c ? ld2[k].y : T(0);
+    for (int k = 0; k < NL0; ++k) {
+      const int e = 2 * (tid + NT * k);
+      ld2[k] = *reinterpret_cast<const V2 *>(G + e % NB + (int64_t)(e / NB) * lda);
+    }
+#pragma unroll
+    for (int k = 0; k < NL0; ++k) stage_pair(2 * (tid + NT * k), ld2[k]);
   }
   __syncthreads();
   const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
@@ -386,37 +407,36 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   // L_pp^-1 into Dinv[p].
   auto factor_diag = [&](int p) {
     const int c0 = 16 * p;
-    T v[16], y[16], rsv[16];
+    T v[16], y[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       v[c] = S[(c0 + c) * LD + c0 + lr];
       y[c] = (lr == c) ? T(1) : T(0);
     }
     bool ok = true;
+    T my_rs = T(0);
+    // Column j: w = L[lr][j] (lr >= j); the columns c > j lose w L[c][j].
+    // Beside it, the forward elimination of M Y = I with the unit lower
+    // M = L diag(L)^-1, whose column j is now known and whose row j of Y is
+    // final: row lr > j loses M[lr][j] times row j (Y[j][j] = 1).  Row lr of
+    // Y scaled by 1 / L[lr][lr] is row lr of L^-1.
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const T piv = readlane(v[j], j);
       ok = ok && (piv > T(0));
       const T rs = rsqrt_nr(piv);
-      rsv[j] = rs;
-      const T lj = v[j] * rs;  // L[lr][j]
+      my_rs = (lr == j) ? rs : my_rs;
+      const T w = v[j] * rs;
 #pragma unroll
-      for (int c = j + 1; c < 16; ++c) v[c] -= lj * (readlane(v[j], c) * rs);
-      v[j] = lr > j ? lj : (lr == j ? piv * rs : T(0));
-    }
-    // y = L^-1: with row y_j final, y_r -= (L[r][j] / L[j][j]) y_j for r > j
+      for (int c = j + 1; c < 16; ++c) v[c] -= w * readlane(w, c);
+      v[j] = lr >= j ? w : T(0);
+      if (j < 15) {
+        const T f = lr > j ? w * rs : T(0);
 #pragma unroll
-    for (int j = 0; j < 15; ++j) {
-      const T f = v[j] * rsv[j];
-#pragma unroll
-      for (int c = 0; c <= j; ++c) {
-        const T yjc = readlane(y[c], j);
-        if (lr > j) y[c] -= f * yjc;
+        for (int c = 0; c < j; ++c) y[c] -= f * readlane(y[c], j);
+        y[j] -= f;
       }
     }
-    T my_rs = T(0);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) my_rs = (lr == j) ? rsv[j] : my_rs;
     if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
@@ -501,7 +521,18 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   // update; the block's update and its factorisation are ordered within wave
   // 0, its LDS writes complete before the factorisation reads them), fused
   // with the inversion steps: two barriers per panel.
-  if (wid == 0) factor_diag(0);
+  if (wid == 0) {
+    factor_diag(0);
+  } else {
+    V2 ld2[NL1];
+#pragma unroll
+    for (int k = 0; k < NL1; ++k) {
+      const int e = 16 * NB + 2 * (tid - 64 + (NT - 64) * k);
+      ld2[k] = *reinterpret_cast<const V2 *>(G + e % NB + (int64_t)(e / NB) * lda);
+    }
+#pragma unroll
+    for (int k = 0; k < NL1; ++k) stage_pair(16 * NB + 2 * (tid - 64 + (NT - 64) * k), ld2[k]);
+  }
   __syncthreads();
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
@@ -565,6 +596,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   }
   // step b of the last panel has no rows below it
 
+  constexpr int NL = NB * NB / 2 / NT;
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
     const int e = 2 * (tid + NT * k);
@@ -875,15 +907,24 @@ GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, 
 }
 
 // Products with fewer 64 x 64 tiles than `small` run on 32 x 32 tiles
-// (kSmallTilesDefault unless the size was tuned).
+// (kSmallTilesDefault unless the size was tuned), with each tile's K range
+// split over 4 waves, or over 8 for products with fewer 32 x 32 tiles than
+// the GPU has compute units (256).  (One wave per 32 x 32 tile was measured
+// slower at every node size of the recursion.)
+constexpr int64_t kSplit8Tiles = 256;
+
 template <typename T, bool AT, bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
           T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st,
           int64_t small = kSmallTilesDefault) {
   GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
   if ((M / 64) * (N / 64) < small) {
-    hipLaunchKernelGGL((k_gemm32<T, AT, BT, LOWER>), dim3((unsigned)(M / 32), (unsigned)(N / 32)),
-                       dim3(64), 0, st, g);
+    const dim3 grid((unsigned)(M / 32), (unsigned)(N / 32));
+    const int64_t t32 = (M / 32) * (N / 32);
+    if (t32 < kSplit8Tiles)
+      hipLaunchKernelGGL((k_gemm32s<T, AT, BT, LOWER, 8>), grid, dim3(512), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_gemm32s<T, AT, BT, LOWER, 4>), grid, dim3(256), 0, st, g);
     return;
   }
   hipLaunchKernelGGL((k_gemm64<T, AT, BT, LOWER>), dim3((unsigned)(M / 64), (unsigned)(N / 64)),
@@ -897,7 +938,11 @@ void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st,
   if ((int64_t)a + b < small) {
     const unsigned a32 = (unsigned)((s.M / 32) * (s.N / 32)),
                    b32 = (unsigned)((t.M / 32) * (t.N / 32));
-    hipLaunchKernelGGL((k_gemm32_pair<T>), dim3(a32 + b32), dim3(64), 0, st, s, t, (int)a32);
+    const int64_t t32 = (int64_t)a32 + b32;
+    if (t32 < kSplit8Tiles)
+      hipLaunchKernelGGL((k_gemm32s_pair<T, 8>), dim3(a32 + b32), dim3(512), 0, st, s, t, (int)a32);
+    else
+      hipLaunchKernelGGL((k_gemm32s_pair<T, 4>), dim3(a32 + b32), dim3(256), 0, st, s, t, (int)a32);
     return;
   }
   hipLaunchKernelGGL((k_gemm64_pair<T>), dim3(a + b), dim3(256), 0, st, s, t, (int)a);
