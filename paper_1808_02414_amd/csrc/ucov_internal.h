@@ -216,7 +216,7 @@ int spd_plan_check_host(const int64_t *np, int count, std::string *why, int64_t 
 // Products of the recursion with fewer 64 x 64 tiles than `small` run on
 // 32 x 32 tiles; the default comes from a sweep on the 4500 x 4500 case,
 // ucov_tune_dense picks it per size.
-constexpr int64_t kSmallTilesDefault = 1024;
+constexpr int64_t kSmallTilesDefault = 4096;
 void spd_lower_inverse_fp64(double *a, int64_t lda, int64_t Np, double *tmp, DevStatus *ds,
                             hipStream_t st, int64_t small = kSmallTilesDefault);
 // n x n symmetric positive definite matrix for timing (no padding).
