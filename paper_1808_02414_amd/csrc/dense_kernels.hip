@@ -334,11 +334,10 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 //      block (p+1, p+1) and goes straight on to step 1 of panel p + 1 while
 //      the other waves finish the trailing update.
 // Inversion (forward elimination of L Y = I by block rows), panel p:
-//   a. L(., p) is staged in the unused upper blocks of block row p, and
-//      Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1;
-//   b. W(i, c) -= L_ip Y(p, c) for i > p, c <= p;
-// step a of panel p runs beside its trailing update, step b beside the
-// panel solve of p + 1.
+//   Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1, and
+//   W(i, c) -= L_ip Y(p, c) for i > p;
+// the columns c < p run beside the trailing update of p (one wave per
+// column), column p, which overwrites L_ip, beside the panel solve of p + 1.
 // Writes L^-1 (lower) into the tile and zeros above its diagonal.
 // ---------------------------------------------------------------------------
 constexpr int kLP = 4;  // LDS leading-dimension padding
@@ -463,21 +462,11 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     for (int v = 0; v < 4; ++v) S[(16 * j + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
   };
 
-  // Inversion steps of panel p (forward elimination L Y = I by block rows):
-  //   a. stage L(i, p), i > p, in block (p, i) (upper, unused); Y(p, c) =
-  //      L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1 (into block (p, c));
-  //   b. W(i, c) -= L_ip Y(p, c), i > p, c <= p (W(i, p) starts at zero).
-  // Once the panel solve of p has run, the factorisation reads only column
-  // blocks beyond p and lower blocks, so step a of p runs beside the trailing
-  // update of p and step b of p beside the panel solve of p + 1.
-  auto inv_stage = [&](int p, int i) {
-    const int c0 = 16 * p;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = MF::row(lane, v);  // (row r, col lr) of L_ip
-      S[(16 * i + lr) * LD + c0 + r] = S[(c0 + lr) * LD + 16 * i + r];
-    }
-  };
+  // Inversion steps (forward elimination L Y = I by block rows; W(i, c)
+  // accumulates -sum_k L_ik Y(k, c) in block (i, c) over the factor):
+  //   Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1, in block (p, c);
+  //   W(i, c) -= L_ip Y(p, c) for i > p (W(i, p) starts at zero and replaces
+  //   L_ip in place).
   auto inv_y = [&](int p, int c) {
     const int c0 = 16 * p;
     if (c == p) {
@@ -499,7 +488,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
       for (int v = 0; v < 4; ++v) S[(16 * c + lr) * LD + c0 + MF::row(lane, v)] = acc[v];
     }
   };
-  auto inv_update = [&](int p, int i, int c) {
+  auto inv_col = [&](int p, int i, int c) {
     const int c0 = 16 * p;
     typename MF::acc_t acc;
 #pragma unroll
@@ -508,8 +497,9 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * kk + lg;
-      const T a = -S[(16 * i + k) * LD + c0 + lr];  // L_ip[lr][k] from the stage
-      const T bb = S[(16 * c + lr) * LD + c0 + k];  // Y(p, c)[k][lr]
+      const T a = -S[(c0 + k) * LD + 16 * i + lr];  // L_ip[lr][k]
+      const T bb = (c == p) ? Dinv[p][lr * 16 + k]  // Y(p, c)[k][lr]
+                            : S[(16 * c + lr) * LD + c0 + k];
       acc = MF::mma(a, bb, acc);
     }
 #pragma unroll
@@ -536,11 +526,12 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   __syncthreads();
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
-    // ---- phase A: panel L_ip = A_ip L_pp^-T (i > p)  and  step b of p - 1 ----
+    // ---- phase A: panel L_ip = A_ip L_pp^-T (i > p), and column p - 1 of
+    // the inversion: Y(p-1, p-1) and W(i, p-1) for i >= p over L_{i,p-1} ----
     {
       const int npan = NPAN - 1 - p;
-      const int nb = p > 0 ? (NPAN - p) * p : 0;  // i in [p, NPAN), c in [0, p)
-      for (int t = wid; t < npan + nb; t += NW) {
+      const int ncol = p > 0 ? NPAN - p + 1 : 0;
+      for (int t = wid; t < npan + ncol; t += NW) {
         if (t < npan) {
           const int i = p + 1 + t;
           typename MF::acc_t acc = MF::zero();
@@ -554,19 +545,21 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
 #pragma unroll
           for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
         } else {
-          const int u = t - npan, m = NPAN - p;
-          inv_update(p - 1, p + u % m, u / m);
+          const int u = t - npan;
+          if (u == 0) inv_y(p - 1, p - 1);
+          else inv_col(p - 1, p - 1 + u, p - 1);
         }
       }
     }
     __syncthreads();
     // ---- phase B: trailing A_ij -= L_ip L_jp^T (p < j <= i) with block
-    // (p+1, p+1) and the next diagonal factorisation on wave 0, and step a
-    // of p on the other waves ----
+    // (p+1, p+1) and the next diagonal factorisation on wave 0; on the other
+    // waves, beside the trailing blocks, the inversion's columns c < p, each
+    // by one wave: Y(p, c), then W(i, c) for every i > p (these read L_ip,
+    // which the trailing update only reads, and write blocks left of p) ----
     {
-      const int m = NPAN - 1 - p;          // trailing block rows
-      const int ntr = m * (m + 1) / 2;     // trailing blocks, block (p+1, p+1) first
-      const int na = m + p + 1;            // stagings, Y(p, c < p), Y(p, p)
+      const int m = NPAN - 1 - p;       // trailing block rows
+      const int ntr = m * (m + 1) / 2;  // trailing blocks, block (p+1, p+1) first
       const bool look = p + 1 < NPAN;
       if (look && wid == 0) {
         trailing_block(p, p + 1, p + 1);
@@ -575,27 +568,29 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
         factor_diag(p + 1);
       } else {
         const int w0 = look ? 1 : 0, nw = look ? NW - 1 : NW;
-        const int first = look ? 1 : 0;  // block (p+1, p+1) is wave 0's
-        for (int t = wid - w0; t < (ntr - first) + na; t += nw) {
-          if (t < ntr - first) {
-            int jj = 0, rem = t + first;  // -> (ii, jj) in the lower triangle of m x m blocks
+        const int first = look ? 1 : 0;      // block (p+1, p+1) is wave 0's
+        const int ncol = look ? p : p + 1;   // columns c < p; the last panel adds Y(p, p)
+        for (int t = wid - w0; t < ncol + (ntr - first); t += nw) {
+          if (t < ncol) {
+            inv_y(p, t);
+            if (t < p) {
+              __builtin_amdgcn_s_waitcnt(0);  // Y(p, t) is read back by this wave
+              __builtin_amdgcn_wave_barrier();
+              for (int i = p + 1; i < NPAN; ++i) inv_col(p, i, t);
+            }
+          } else {
+            int jj = 0, rem = t - ncol + first;  // -> (ii, jj) in the lower triangle of m x m blocks
             while (rem >= m - jj) {
               rem -= m - jj;
               ++jj;
             }
             trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
-          } else {
-            const int u = t - (ntr - first);
-            if (u < m) inv_stage(p, p + 1 + u);
-            else inv_y(p, u - m);
           }
         }
       }
     }
     __syncthreads();
   }
-  // step b of the last panel has no rows below it
-
   constexpr int NL = NB * NB / 2 / NT;
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
