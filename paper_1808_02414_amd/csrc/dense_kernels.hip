@@ -340,7 +340,10 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 // column), column p, which overwrites L_ip, beside the panel solve of p + 1.
 // Writes L^-1 (lower) into the tile and zeros above its diagonal.
 // ---------------------------------------------------------------------------
-constexpr int kLP = 4;  // LDS leading-dimension padding
+// LDS strides of the leaf: column-strided accesses (lane = column) then fall
+// on distinct banks (a stride of 2 dwords modulo the bank count).
+constexpr int kLP = 1;   // leading-dimension padding of the tile
+constexpr int kDL = 17;  // column stride of the 16x16 diagonal inverses
 
 // Broadcast lane l's value of x to the whole wave (scalar lane reads).
 __device__ inline double readlane(double x, int l) {
@@ -375,7 +378,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   constexpr int NPAN = NB / 16;
   constexpr int NW = NT / 64;  // waves
   __shared__ T S[NB * LD];
-  __shared__ T Dinv[NPAN][16 * 16];  // L_pp^-1, column-major 16x16
+  __shared__ T Dinv[NPAN][16 * kDL];  // L_pp^-1, column-major 16x16
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   T *G = A + o + o * lda;
   // Whole columns with paired loads (the upper part is read and discarded):
@@ -440,7 +443,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         S[(c0 + c) * LD + c0 + lr] = v[c];
-        Dinv[p][c * 16 + lr] = y[c] * my_rs;
+        Dinv[p][c * kDL + lr] = y[c] * my_rs;
       }
     }
     if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
@@ -473,14 +476,14 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = lg + 4 * v;
-        S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * 16 + lr];
+        S[(c0 + col) * LD + c0 + lr] = Dinv[p][col * kDL + lr];
       }
     } else {
       typename MF::acc_t acc = MF::zero();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int k = 4 * kk + lg;
-        const T a = Dinv[p][k * 16 + lr];           // (L_pp^-1)[lr][k]
+        const T a = Dinv[p][k * kDL + lr];          // (L_pp^-1)[lr][k]
         const T b = S[(16 * c + lr) * LD + c0 + k];  // W(p, c)[k][lr]
         acc = MF::mma(a, b, acc);
       }
@@ -498,7 +501,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
     for (int kk = 0; kk < 4; ++kk) {
       const int k = 4 * kk + lg;
       const T a = -S[(c0 + k) * LD + 16 * i + lr];  // L_ip[lr][k]
-      const T bb = (c == p) ? Dinv[p][lr * 16 + k]  // Y(p, c)[k][lr]
+      const T bb = (c == p) ? Dinv[p][lr * kDL + k]  // Y(p, c)[k][lr]
                             : S[(16 * c + lr) * LD + c0 + k];
       acc = MF::mma(a, bb, acc);
     }
@@ -539,7 +542,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
           for (int kk = 0; kk < 4; ++kk) {
             const int k = 4 * kk + lg;
             const T a = S[(c0 + k) * LD + 16 * i + lr];
-            const T b = Dinv[p][k * 16 + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+            const T b = Dinv[p][k * kDL + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
             acc = MF::mma(a, b, acc);
           }
 #pragma unroll
