@@ -330,9 +330,10 @@ __global__ __launch_bounds__(256) void k_gemm64_pair(GemmArgs<T> s, GemmArgs<T> 
 //      Newton steps) and inverts it by forward elimination in the same
 //      column loop: L_pp and L_pp^-1;
 //   2. the panel below: L_ip = A_ip L_pp^-T            (MFMA, all waves)
-//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA); wave 0 takes
-//      block (p+1, p+1) and goes straight on to step 1 of panel p + 1 while
-//      the other waves finish the trailing update.
+//   3. the trailing lower blocks: A_ij -= L_ip L_jp^T   (MFMA); wave 0
+//      solves panel row p + 1, updates block (p+1, p+1) from it at once and
+//      goes on to step 1 of panel p + 1 while the other waves do the rest of
+//      the panel and the trailing update.
 // Inversion (forward elimination of L Y = I by block rows), panel p:
 //   Y(p, c) = L_pp^-1 W(p, c) for c < p, Y(p, p) = L_pp^-1, and
 //   W(i, c) -= L_ip Y(p, c) for i > p;
@@ -510,10 +511,9 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   };
 
   // Factorisation with a one-panel lookahead (wave 0 updates the next
-  // diagonal block and factors it while the other waves finish the trailing
-  // update; the block's update and its factorisation are ordered within wave
-  // 0, its LDS writes complete before the factorisation reads them), fused
-  // with the inversion steps: two barriers per panel.
+  // diagonal block beside the panel solve and factors it beside the trailing
+  // update; each step's LDS writes are read back only by wave 0 itself),
+  // fused with the inversion steps: two barriers per panel.
   if (wid == 0) {
     factor_diag(0);
   } else {
@@ -530,33 +530,45 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   for (int p = 0; p < NPAN; ++p) {
     const int c0 = 16 * p;
     // ---- phase A: panel L_ip = A_ip L_pp^-T (i > p), and column p - 1 of
-    // the inversion: Y(p-1, p-1) and W(i, p-1) for i >= p over L_{i,p-1} ----
+    // the inversion: Y(p-1, p-1) and W(i, p-1) for i >= p over L_{i,p-1}.
+    // Wave 0 solves row p + 1 and at once updates block (p+1, p+1), the
+    // next diagonal block, from it ----
     {
       const int npan = NPAN - 1 - p;
       const int ncol = p > 0 ? NPAN - p + 1 : 0;
-      for (int t = wid; t < npan + ncol; t += NW) {
-        if (t < npan) {
-          const int i = p + 1 + t;
-          typename MF::acc_t acc = MF::zero();
+      auto panel = [&](int i) {
+        typename MF::acc_t acc = MF::zero();
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int k = 4 * kk + lg;
-            const T a = S[(c0 + k) * LD + 16 * i + lr];
-            const T b = Dinv[p][k * kDL + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
-            acc = MF::mma(a, b, acc);
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k = 4 * kk + lg;
+          const T a = S[(c0 + k) * LD + 16 * i + lr];
+          const T b = Dinv[p][k * kDL + lr];  // (L_pp^-1)[lr][k] = B^T[k][lr]
+          acc = MF::mma(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
+      };
+      const int first = npan > 0 ? 1 : 0;  // task 0 (row p + 1) is wave 0's
+      if (first && wid == 0) {
+        panel(p + 1);
+        __builtin_amdgcn_s_waitcnt(0);  // L_{p+1,p} is read back by this wave
+        __builtin_amdgcn_wave_barrier();
+        trailing_block(p, p + 1, p + 1);
+      } else {
+        for (int t = wid; t < npan + ncol; t += NW - first) {
+          if (t < npan) {
+            panel(p + 1 + t);
+          } else {
+            const int u = t - npan;
+            if (u == 0) inv_y(p - 1, p - 1);
+            else inv_col(p - 1, p - 1 + u, p - 1);
           }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) S[(c0 + lr) * LD + 16 * i + MF::row(lane, v)] = acc[v];
-        } else {
-          const int u = t - npan;
-          if (u == 0) inv_y(p - 1, p - 1);
-          else inv_col(p - 1, p - 1 + u, p - 1);
         }
       }
     }
     __syncthreads();
-    // ---- phase B: trailing A_ij -= L_ip L_jp^T (p < j <= i) with block
-    // (p+1, p+1) and the next diagonal factorisation on wave 0; on the other
+    // ---- phase B: trailing A_ij -= L_ip L_jp^T (p < j <= i, block (p+1, p+1)
+    // done) and the next diagonal factorisation on wave 0; on the other
     // waves, beside the trailing blocks, the inversion's columns c < p, each
     // by one wave: Y(p, c), then W(i, c) for every i > p (these read L_ip,
     // which the trailing update only reads, and write blocks left of p) ----
@@ -565,9 +577,6 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
       const int ntr = m * (m + 1) / 2;  // trailing blocks, block (p+1, p+1) first
       const bool look = p + 1 < NPAN;
       if (look && wid == 0) {
-        trailing_block(p, p + 1, p + 1);
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
         factor_diag(p + 1);
       } else {
         const int w0 = look ? 1 : 0, nw = look ? NW - 1 : NW;
