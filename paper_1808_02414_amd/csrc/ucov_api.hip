@@ -47,6 +47,7 @@ struct ucov_ctx {
   // workspace
   Buf cnt_p, ptr_p, cur_p, slot_obs, slot_cam, slot_pt, rec;
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos;
+  Buf cam_iota, cam_keys, cam_slots, cam_ptr, cam_tmp;  // slots grouped by camera
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
   // batched calls: the concatenated scenes, their tables and per-scene status
@@ -143,9 +144,11 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Steps a1-a2 up to the per-camera diagonal blocks and the nullspace rows.
 // On return the slot records, pair bins, zdiag and hc are valid.
 // nbins: camera-pair bins, n(n+1)/2 for one scene, the sum over the scenes of
-// a concatenation.  The status must have been cleared by the caller.
+// a concatenation; max_scene_cams: cameras of the largest scene (n for one
+// scene).  The status must have been cleared by the caller.
 int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_out,
-                    double *jx_out, bool jac_only, ucov_report *rep) {
+                    double *jx_out, bool jac_only, ucov_report *rep,
+                    int64_t max_scene_cams = -1) {
   const int64_t n = sc.n, m = sc.m, t = sc.t;
   const int64_t N = 9 * n;
   const int64_t scan_tiles = (std::max(nbins, m) + 4095) / 4096 + 2;
@@ -191,8 +194,28 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.nzcount = as<int64_t>(c->nzcount);
   w.nzpos = as<int64_t>(c->nzpos);
   launch_point_blocks(sc, w, c->ds, st);
-  fill_i32(w.bin_cnt, 0, nbins, st);
-  launch_pair_count(sc, w, st);
+  // camera-pair bins: camera-major with LDS counters where the largest
+  // scene's cameras fit them, else one global atomic per pair
+  const int64_t mc = max_scene_cams < 0 ? n : max_scene_cams;
+  const bool cam_major = t > 0 && mc <= kCamHistMax;
+  if (cam_major) {
+    const size_t tmp_bytes = camera_lists_scratch(t);
+    UCOV_TRY(ensure(c, c->cam_iota, 4 * t));
+    UCOV_TRY(ensure(c, c->cam_keys, 4 * t));
+    UCOV_TRY(ensure(c, c->cam_slots, 4 * t));
+    UCOV_TRY(ensure(c, c->cam_ptr, 8 * (n + 1)));
+    UCOV_TRY(ensure(c, c->cam_tmp, std::max<size_t>(tmp_bytes, 8)));
+    w.cam_iota = as<int32_t>(c->cam_iota);
+    w.cam_keys = as<int32_t>(c->cam_keys);
+    w.cam_slots = as<int32_t>(c->cam_slots);
+    w.cam_ptr = as<int64_t>(c->cam_ptr);
+    if (launch_camera_lists(sc, w, c->cam_tmp.p, tmp_bytes, st) != 0)
+      return c->fail(UCOV_EDEVICE, "sorting the slots by camera");
+    launch_pair_count_cam(sc, w, (int)mc, st);
+  } else {
+    fill_i32(w.bin_cnt, 0, nbins, st);
+    launch_pair_count(sc, w, st);
+  }
   exclusive_scan(w.bin_cnt, w.bin_ptr, nbins, w.scan_tmp, st);
   launch_nonzero_bins(sc, w, nbins, st);
   UCOV_TRY(check_hip(c, "point kernels"));
@@ -209,7 +232,8 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.pairs = as<int2>(c->pairs);
   w.zdiag = as<double>(c->zdiag);
   w.hc = as<double>(c->hc);
-  launch_pair_fill(sc, w, st);
+  if (cam_major) launch_pair_fill_cam(sc, w, (int)mc, st);
+  else launch_pair_fill(sc, w, st);
   hipEventRecord(c->ev[1], st);
   launch_camera_diag(sc, w, c->ds, st);
   UCOV_TRY(check_hip(c, "schur kernels"));
@@ -229,6 +253,10 @@ SceneWork scene_work(ucov_ctx *c) {
   w.bin_ptr = as<int64_t>(c->bin_ptr);
   w.bin_cur = as<int32_t>(c->bin_cur);
   w.pairs = as<int2>(c->pairs);
+  w.cam_iota = as<int32_t>(c->cam_iota);
+  w.cam_keys = as<int32_t>(c->cam_keys);
+  w.cam_slots = as<int32_t>(c->cam_slots);
+  w.cam_ptr = as<int64_t>(c->cam_ptr);
   w.nzlist = as<int2>(c->nzlist);
   w.nzcount = as<int64_t>(c->nzcount);
   w.nzpos = as<int64_t>(c->nzpos);
@@ -410,6 +438,7 @@ void ucov_destroy(ucov_ctx *c) {
   else hipDeviceSynchronize();
   Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_obs, &c->slot_cam, &c->slot_pt,
                  &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount, &c->nzpos,
+                 &c->cam_iota, &c->cam_keys, &c->cam_slots, &c->cam_ptr, &c->cam_tmp,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
@@ -933,7 +962,9 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
     return rc;
   };
   {
-    const int rc = run_scene_stage(c, sc, bin_off[S], nullptr, nullptr, false, rep);
+    int64_t max_cams = 0;
+    for (int s = 0; s < S; ++s) max_cams = std::max<int64_t>(max_cams, cam_off[s + 1] - cam_off[s]);
+    const int rc = run_scene_stage(c, sc, bin_off[S], nullptr, nullptr, false, rep, max_cams);
     if (rc != UCOV_OK) return localize(rc);
   }
   UCOV_TRY(ensure(c, c->q, 8 * 7 * N));

@@ -91,6 +91,11 @@ struct SceneWork {
   int64_t *bin_ptr;   // nbins + 1
   int32_t *bin_cur;   // nbins
   int2 *pairs;        // n_pairs (slot a of camera i, slot b of camera k)
+  // slots grouped by camera (camera-major bin construction)
+  int32_t *cam_iota;  // t: 0, 1, ..., t - 1
+  int32_t *cam_keys;  // t: camera of each slot, sorted
+  int32_t *cam_slots; // t: slots in camera order, ascending within a camera
+  int64_t *cam_ptr;   // n + 1
   int2 *nzlist;       // (i, k) of every non-empty bin, in bin order
   int64_t *nzcount;   // [0]: number of non-empty bins
   int64_t *nzpos;     // nbins + 1: exclusive scan of the non-empty flags
@@ -125,6 +130,18 @@ void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st);
 // nzlist / nzcount from bin_cnt (needs bin_cur as scratch; leaves it zero)
 void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStream_t st);
 void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st);
+// Camera-major bins for scenes of at most kCamHistMax cameras (LDS counters
+// per camera): the camera lists, then every bin count (no prior zero fill),
+// then the pairs.  camera_lists_scratch: bytes of sort scratch for t slots;
+// launch_camera_lists returns nonzero when the sort cannot be launched.
+constexpr int kCamHistMax = 16384;
+size_t camera_lists_scratch(int64_t t);
+int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_bytes,
+                        hipStream_t st);
+void launch_pair_count_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
+                           hipStream_t st);
+void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
+                          hipStream_t st);
 void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 // Orthonormal Q (Cholesky-QR2 of hc; skipped when hc is null and q is given),
 // the gauge weight alpha and the Jacobi scaling s.  diag(Z) comes from the
