@@ -1235,9 +1235,14 @@ void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st) {
                      w.ptr_p, w.slot_cam, w.slot_pt, w.bin_ptr, w.bin_cur, w.pairs);
 }
 
+// Radix passes (onesweep) from 64 Ki slots on; rocPRIM's default sends up to
+// 1 Mi items to a merge sort, 21 launches for the 500-camera scene's slots.
+using CamSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                 rocprim::default_config, 65536>;
+
 size_t camera_lists_scratch(int64_t t) {
   size_t bytes = 0;
-  rocprim::radix_sort_pairs(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
+  rocprim::radix_sort_pairs<CamSortConfig>(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
                             (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)t, 0, 32);
   return bytes;
 }
@@ -1249,7 +1254,7 @@ int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_
   hipLaunchKernelGGL(k_iota_i32, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, w.cam_iota,
                      sc.t);
   const hipError_t e =
-      rocprim::radix_sort_pairs(tmp, tmp_bytes, (const int32_t *)w.slot_cam, w.cam_keys,
+      rocprim::radix_sort_pairs<CamSortConfig>(tmp, tmp_bytes, (const int32_t *)w.slot_cam, w.cam_keys,
                                 (const int32_t *)w.cam_iota, w.cam_slots, (size_t)sc.t, 0, bits, st);
   if (e != hipSuccess) return -1;
   hipLaunchKernelGGL(k_cam_bounds, dim3(blocks_for((int64_t)sc.n + 1, kBlk)), dim3(kBlk), 0, st,
