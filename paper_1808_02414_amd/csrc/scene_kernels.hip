@@ -644,6 +644,14 @@ __global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t 
 // ---------------------------------------------------------------------------
 constexpr int kGaugeThreads = 512;
 
+// Lane l's value of x on every lane (scalar lane reads).
+__device__ inline double lane_bcast(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double block_sum(double v, double *red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_sum(v);
@@ -691,49 +699,46 @@ __device__ __forceinline__ bool cholqr_pass(int64_t N, int64_t ld, const double 
     __syncthreads();
   }
   __shared__ int okflag;
-  // the 7 x 7 factorisation runs on one thread; its matrices live in LDS
-  // (as private arrays indexed in loops they would go to scratch memory)
-  __shared__ double G[7][7], L[7][7], Li[7][7];
-  if (threadIdx.x == 0) {
-    int idx = 0;
-    for (int a = 0; a < 7; ++a)
-      for (int b = a; b < 7; ++b) {
-        G[a][b] = Gs[idx];
-        G[b][a] = Gs[idx];
-        ++idx;
-      }
+  // the 7 x 7 factorisation and its inverse on wave 0, in registers: lane
+  // r < 7 holds row r (of G, then L, then L^-1), columns broadcast by lane
+  // reads; R = L^T, Ri = R^-1 = (L^-1)^T
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    double l[7], y[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const int lo = r < c ? r : c, hi = r < c ? c : r;  // upper-packed (lo, hi)
+      l[c] = r < 7 ? Gs[lo * 7 - lo * (lo - 1) / 2 + (hi - lo)] : 0.0;
+      y[c] = r == c ? 1.0 : 0.0;
+    }
     bool ok = true;
-    for (int a = 0; a < 7; ++a)
-      for (int b = 0; b < 7; ++b) L[a][b] = 0.0;
-    for (int j = 0; j < 7 && ok; ++j) {
-      double d = G[j][j];
-      for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-      if (!(d > 0.0)) {
-        ok = false;
-        break;
-      }
-      L[j][j] = sqrt(d);
-      for (int r = j + 1; r < 7; ++r) {
-        double v = G[r][j];
-        for (int k = 0; k < j; ++k) v -= L[r][k] * L[j][k];
-        L[r][j] = v / L[j][j];
-      }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const double piv = lane_bcast(l[j], j);
+      ok = ok && piv > 0.0;
+      const double d = sqrt(piv);
+      const double w = r == j ? d : l[j] / d;  // L[r][j] for r >= j
+#pragma unroll
+      for (int c = j + 1; c < 7; ++c) l[c] -= w * lane_bcast(w, c);
+      l[j] = r >= j ? w : 0.0;
     }
-    // R = L^T (upper); Ri = R^-1 = (L^-1)^T
-    for (int a = 0; a < 7; ++a)
-      for (int b = 0; b < 7; ++b) Li[a][b] = 0.0;
-    if (ok) {
-      for (int c = 0; c < 7; ++c) {
-        for (int r = c; r < 7; ++r) {
-          double v = (r == c) ? 1.0 : 0.0;
-          for (int k = c; k < r; ++k) v -= L[r][k] * Li[k][c];
-          Li[r][c] = v / L[r][r];
-        }
-      }
+    // forward elimination with M = L diag(L)^-1: row r > j loses M[r][j]
+    // times row j; row r of L^-1 is then row r over L[r][r]
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double f = r > j ? l[j] / lane_bcast(l[j], j) : 0.0;
+#pragma unroll
+      for (int c = 0; c < j; ++c) y[c] -= f * lane_bcast(y[c], j);
+      y[j] -= f;
     }
-    for (int a = 0; a < 7; ++a)
-      for (int b = 0; b < 7; ++b) Ri[a * 7 + b] = Li[b][a];
-    okflag = ok ? 1 : 0;
+    double lrr = 1.0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) lrr = r == k ? l[k] : lrr;
+    if (r < 7) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) Ri[c * 7 + r] = ok ? y[c] / lrr : 0.0;
+    }
+    if (r == 0) okflag = ok ? 1 : 0;
   }
   __syncthreads();
   if (!okflag) return false;
