@@ -1004,48 +1004,65 @@ __global__ __launch_bounds__(1024) void k_paper_p(int64_t N, double *f, double *
 // assembly of Z (mode 0) or S (Z + a QQ^T) S (mode 1)
 //
 // k_fill_empty writes the camera blocks without Schur terms (Z_ik = 0): zeros
-// in mode 0, the scaled gauge term in mode 1; one thread per element, columns
-// walked with coalesced stores.  k_bin_blocks takes one wave per non-empty
+// in mode 0, the scaled gauge term in mode 1; one thread per row of a camera's
+// 9 columns, with coalesced column stores.  k_bin_blocks takes one wave per non-empty
 // bin (i, k) and writes that whole 9x9 block.
 // ---------------------------------------------------------------------------
-// One workgroup per global column gc; its threads walk the rows r >= c of the
-// column's scene (coalesced).  The scene gives the matrix (offset a_off[s],
-// leading dimension a_ld[s]) and the row range.
+// One workgroup per camera k (its 9 columns) and chunk of kFillRows rows of
+// the column's scene: each thread takes one row r, loads its 7 Q values,
+// scale and bin test once and writes its entries r >= c in the 9 columns
+// (column stores coalesced across the threads).  The scene gives the matrix
+// (offset a_off[s], leading dimension a_ld[s]) and the row range.
+constexpr int kFillRows = 1024;
+
 __global__ __launch_bounds__(256) void k_fill_empty(SceneDev sc, const int32_t *bin_cnt,
                                                    const double *q, const double *s,
                                                    const double *alpha, int mode, double *out,
                                                    int64_t ld) {
   const int64_t N = 9 * (int64_t)sc.n;  // rows of q (all scenes)
-  const int64_t gc = blockIdx.x;
+  const int kc = blockIdx.x;
+  const int64_t gc0 = 9 * (int64_t)kc;
   int si = 0;
   int64_t row0 = 0, Ns = N, off = 0, lds = ld;
   if (sc.cam_scene) {
-    si = sc.cam_scene[gc / 9];
+    si = sc.cam_scene[kc];
     row0 = 9 * (int64_t)sc.cam_off[si];
     Ns = 9 * (int64_t)(sc.cam_off[si + 1] - sc.cam_off[si]);
     off = sc.a_off[si];
     lds = sc.a_ld[si];
   }
-  const int64_t c = gc - row0;
-  const int kc = (int)(gc / 9);
-  double qc[7];
-#pragma unroll
-  for (int h = 0; h < 7; ++h) qc[h] = mode ? q[h * N + gc] : 0.0;
+  const int64_t c0 = gc0 - row0;  // first column in the scene
+  const int64_t r_begin = c0 + (int64_t)blockIdx.y * kFillRows;
+  if (r_begin >= Ns) return;
+  const int64_t r_end = min(Ns, r_begin + kFillRows);
+  __shared__ double qcs[9][7], scs[9];
+  const int tid = threadIdx.x;
+  if (tid < 63) qcs[tid / 7][tid % 7] = mode ? q[(tid % 7) * N + gc0 + tid / 7] : 0.0;
+  if (tid < 9) scs[tid] = mode ? s[gc0 + tid] : 0.0;
+  __syncthreads();
   const double a = mode ? alpha[si] : 0.0;
-  const double sc_c = mode ? s[gc] : 0.0;
   double *o = out + off;
-  for (int64_t r = c + threadIdx.x; r < Ns; r += blockDim.x) {
+  for (int64_t r = r_begin + tid; r < r_end; r += blockDim.x) {
     const int64_t gr = row0 + r;
     if (bin_cnt[bin_of(sc, (int)(gr / 9), kc)] != 0) continue;
+    const int jmax = (int)min((int64_t)8, r - c0);  // columns c0 + j <= r
     if (mode == 0) {
-      o[r + c * lds] = 0.0;
-      o[c + r * lds] = 0.0;
+      for (int j = 0; j <= jmax; ++j) {
+        o[r + (c0 + j) * lds] = 0.0;
+        o[(c0 + j) + r * lds] = 0.0;
+      }
       continue;
     }
-    double g = 0.0;
+    double qr[7];
 #pragma unroll
-    for (int h = 0; h < 7; ++h) g += q[h * N + gr] * qc[h];
-    o[r + c * lds] = s[gr] * (a * g) * sc_c;
+    for (int h = 0; h < 7; ++h) qr[h] = q[h * N + gr];
+    const double sr = s[gr];
+    for (int j = 0; j <= jmax; ++j) {
+      double g = 0.0;
+#pragma unroll
+      for (int h = 0; h < 7; ++h) g += qr[h] * qcs[j][h];
+      o[r + (c0 + j) * lds] = sr * (a * g) * scs[j];
+    }
   }
 }
 
@@ -1374,10 +1391,10 @@ void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const 
 }
 
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
-                     int64_t n_nonzero, hipStream_t st) {
-  const int64_t N = 9 * (int64_t)sc.n;
-  hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)N), dim3(256), 0, st, sc, w.bin_cnt, w.q, w.s,
-                     w.alpha, mode, out, ld);
+                     int64_t n_nonzero, hipStream_t st, int64_t max_scene_cams) {
+  const int64_t rows = 9 * (max_scene_cams < 0 ? (int64_t)sc.n : max_scene_cams);
+  hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)sc.n, (unsigned)((rows + kFillRows - 1) / kFillRows)),
+                     dim3(256), 0, st, sc, w.bin_cnt, w.q, w.s, w.alpha, mode, out, ld);
   if (n_nonzero > 0)
     hipLaunchKernelGGL(k_bin_blocks, dim3((blocks_for(n_nonzero, 4) + 7) / 8 * 8), dim3(256), 0, st, sc,
                        w.nzlist, w.nzcount, w.bin_ptr, w.pairs, w.rec, w.zdiag, w.q, w.s,

@@ -961,9 +961,9 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
                      std::to_string(g - base);
     return rc;
   };
+  int64_t max_cams = 0;
+  for (int s = 0; s < S; ++s) max_cams = std::max<int64_t>(max_cams, cam_off[s + 1] - cam_off[s]);
   {
-    int64_t max_cams = 0;
-    for (int s = 0; s < S; ++s) max_cams = std::max<int64_t>(max_cams, cam_off[s + 1] - cam_off[s]);
     const int rc = run_scene_stage(c, sc, bin_off[S], nullptr, nullptr, false, rep, max_cams);
     if (rc != UCOV_OK) return localize(rc);
   }
@@ -974,7 +974,7 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   SceneWork w = scene_work(c);
   hipEventRecord(c->ev[2], st);
   launch_gauge_scenes(sc, w.hc, w.q, w.zdiag, o.alpha, w.s, w.alpha, c->ds, st);
-  launch_assemble(sc, w, 1, as<double>(c->amat), 0, c->n_nonzero, st);
+  launch_assemble(sc, w, 1, as<double>(c->amat), 0, c->n_nonzero, st, max_cams);
   UCOV_TRY(check_hip(c, "batched assemble"));
   {
     const int rc = sync_status(c, rep, "batched gauge");

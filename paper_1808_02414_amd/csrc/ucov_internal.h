@@ -163,9 +163,10 @@ void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *
                         hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
 // S (Z + a QQ^T) S into out (per scene at out + a_off[s] with leading dimension
-// a_ld[s] for a concatenation).  n_nonzero is the number of non-empty bins.
+// a_ld[s] for a concatenation).  n_nonzero is the number of non-empty bins;
+// max_scene_cams: cameras of the largest scene (n for one scene).
 void launch_assemble(const SceneDev &sc, SceneWork &w, int mode, double *out, int64_t ld,
-                     int64_t n_nonzero, hipStream_t st);
+                     int64_t n_nonzero, hipStream_t st, int64_t max_scene_cams = -1);
 
 // Sub-reconstructions: sub-scene arrays gathered from a parent scene through
 // index maps (camera, point and, when pinfo is set, observation of the parent
