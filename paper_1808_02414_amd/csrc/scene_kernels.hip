@@ -1119,8 +1119,10 @@ __global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzl
   if (i != k) {
     const int64_t bin = bin_of(sc, i, k);
     const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
-    // 16 pairs (8 MFMAs) per iteration; all loads are issued before the MFMAs
-    constexpr int U = 8;
+    // 8 pairs (4 MFMAs) per iteration; all loads are issued before the MFMAs
+    // (16 or 4 pairs per iteration measured slower: fewer waves in flight,
+    // or fewer loads per wave)
+    constexpr int U = 4;
     for (int64_t e = e0; e < e1; e += 2 * U) {
       int2 pr[U];
 #pragma unroll
