@@ -1097,7 +1097,9 @@ __global__ __launch_bounds__(256) void k_concat(const BatchEntry *tab, double *c
 // K_e J_P,b (2E x 9): an FP64 MFMA (16x16x4) contraction over the pair
 // dimension, two pairs per instruction, rows and columns padded 9 -> 16.
 // Lane l supplies A[kk][l%16] and B[kk][l%16] with kk = l/16 = 2 (pair) + row.
-__global__ __launch_bounds__(256) void k_bin_blocks(SceneDev sc, const int2 *nzlist,
+// (6 waves per SIMD: 80 registers without spills; more waves in flight
+// beat deeper loads per wave here, and 8 waves spill)
+__global__ __launch_bounds__(256, 6) void k_bin_blocks(SceneDev sc, const int2 *nzlist,
                                                    const int64_t *nzcount, const int64_t *bin_ptr,
                                                    const int2 *pairs, const double *rec,
                                                    const double *zdiag, const double *q,
