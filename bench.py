@@ -175,7 +175,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is not part of this build", file=sys.stderr)
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
