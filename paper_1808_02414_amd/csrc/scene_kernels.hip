@@ -218,59 +218,82 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_points(SceneDev sc, const
 // the information block (L^T L = Sigma_u^-1), written into the slot record.
 // Only the first ptr_p[m] slots are filled (observations with out-of-range
 // indices are never placed), so every slot loop is bounded by that count.
-__global__ void k_jacobians(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_obs,
-                            const int32_t *slot_cam, const int32_t *slot_pt, double *rec,
-                            double *jp_out, double *jx_out, DevStatus *ds) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ptr_p[sc.m]) return;
-  const int32_t o = slot_obs[s];
-  const int i = slot_cam[s], j = slot_pt[s];
-  double cam[9], X[3];
+// The workgroup's records pass through LDS so that the stores are coalesced
+// (a record's 24 values are contiguous; one thread per record would store
+// with a 256-byte stride across the lanes).  A slot with an error reports it
+// and gets zeros (the call fails on the reported status).
+constexpr int kJacPitch = 25;  // LDS doubles per staged record
+
+__global__ __launch_bounds__(kBlk) void k_jacobians(SceneDev sc, const int64_t *ptr_p,
+                                                    const int32_t *slot_obs,
+                                                    const int32_t *slot_cam,
+                                                    const int32_t *slot_pt, double *rec,
+                                                    double *jp_out, double *jx_out, DevStatus *ds) {
+  __shared__ double tile[kBlk * kJacPitch];
+  const int64_t count = ptr_p[sc.m];
+  const int64_t s0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t s = s0 + threadIdx.x;
+  double val[24];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) cam[k] = sc.cams[9 * (int64_t)i + k];
+  for (int k = 0; k < 24; ++k) val[k] = 0.0;
+  auto compute = [&]() {
+    const int32_t o = slot_obs[s];
+    const int i = slot_cam[s], j = slot_pt[s];
+    double cam[9], X[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) X[k] = sc.pts[3 * (int64_t)j + k];
-  if (!finite9(cam, 9) || !finite9(X, 3)) {
-    report_error(ds, UCOV_EINVAL, o);
-    return;
-  }
-  double l00 = 1.0, l01 = 0.0, l11 = 1.0;
-  if (sc.info) {
-    const double ia = sc.info[3 * (int64_t)o], ib = sc.info[3 * (int64_t)o + 1],
-                 ic = sc.info[3 * (int64_t)o + 2];
-    if (!(ia > 0.0) || !(ia * ic - ib * ib > 0.0) || !isfinite(ia + ib + ic)) {
+    for (int k = 0; k < 9; ++k) cam[k] = sc.cams[9 * (int64_t)i + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[k] = sc.pts[3 * (int64_t)j + k];
+    if (!finite9(cam, 9) || !finite9(X, 3)) {
       report_error(ds, UCOV_EINVAL, o);
       return;
     }
-    l00 = sqrt(ia);
-    l01 = ib / l00;
-    l11 = sqrt(ic - l01 * l01);
-  }
-  Jac J;
-  projection_jacobian(cam, X, J);
-  if (!(J.x[2] > 0.0)) {
-    report_error(ds, UCOV_EINVAL, o);
-    return;
-  }
-  if (jp_out) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) jp_out[18 * (int64_t)o + 9 * p + k] = J.jp[p][k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) jx_out[6 * (int64_t)o + 3 * p + k] = J.jx[p][k];
+    double l00 = 1.0, l01 = 0.0, l11 = 1.0;
+    if (sc.info) {
+      const double ia = sc.info[3 * (int64_t)o], ib = sc.info[3 * (int64_t)o + 1],
+                   ic = sc.info[3 * (int64_t)o + 2];
+      if (!(ia > 0.0) || !(ia * ic - ib * ib > 0.0) || !isfinite(ia + ib + ic)) {
+        report_error(ds, UCOV_EINVAL, o);
+        return;
+      }
+      l00 = sqrt(ia);
+      l01 = ib / l00;
+      l11 = sqrt(ic - l01 * l01);
     }
-  }
-  double *r = rec + s * kRec;
+    Jac J;
+    projection_jacobian(cam, X, J);
+    if (!(J.x[2] > 0.0)) {
+      report_error(ds, UCOV_EINVAL, o);
+      return;
+    }
+    if (jp_out) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    r[kRecJP + k] = l00 * J.jp[0][k] + l01 * J.jp[1][k];
-    r[kRecJP + 9 + k] = l11 * J.jp[1][k];
-  }
+      for (int p = 0; p < 2; ++p) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    r[kRecJX + k] = l00 * J.jx[0][k] + l01 * J.jx[1][k];
-    r[kRecJX + 3 + k] = l11 * J.jx[1][k];
+        for (int k = 0; k < 9; ++k) jp_out[18 * (int64_t)o + 9 * p + k] = J.jp[p][k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) jx_out[6 * (int64_t)o + 3 * p + k] = J.jx[p][k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      val[kRecJP + k] = l00 * J.jp[0][k] + l01 * J.jp[1][k];
+      val[kRecJP + 9 + k] = l11 * J.jp[1][k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      val[kRecJX + k] = l00 * J.jx[0][k] + l01 * J.jx[1][k];
+      val[kRecJX + 3 + k] = l11 * J.jx[1][k];
+    }
+  };
+  if (s < count) compute();
+#pragma unroll
+  for (int k = 0; k < 24; ++k) tile[threadIdx.x * kJacPitch + k] = val[k];
+  __syncthreads();
+  const int64_t nslots = min((int64_t)blockDim.x, count - s0);
+  for (int64_t e = threadIdx.x; e < nslots * 24; e += blockDim.x) {
+    const int64_t sl = e / 24, k = e % 24;
+    rec[(s0 + sl) * kRec + k] = tile[sl * kJacPitch + k];
   }
 }
 
