@@ -136,26 +136,30 @@ __global__ void k_count_points(SceneDev sc, int32_t *cnt_p, DevStatus *ds) {
   atomicAdd(&cnt_p[j], 1);
 }
 
+// Each observation takes a slot of its point, with the sort key
+// (camera << 32 | observation) of k_sort_points.
 __global__ void k_fill_slots(SceneDev sc, const int64_t *ptr_p, int32_t *cur_p,
-                             int32_t *slot_obs) {
+                             int64_t *slot_key) {
   int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= sc.t) return;
   int c = sc.oc[o], j = sc.op[o];
   if (c < 0 || c >= sc.n || j < 0 || j >= sc.m) return;
   int64_t pos = ptr_p[j] + atomicAdd(&cur_p[j], 1);
-  slot_obs[pos] = (int32_t)o;
+  slot_key[pos] = ((int64_t)c << 32) | (uint32_t)o;
 }
 
 // One thread per point: order its observations by camera, reject duplicate
 // cameras and points with fewer than two observations.  Tracks of up to
 // kSortCap observations are sorted as (camera, observation) keys in LDS
-// (interleaved across the threads); longer ones in place in global memory.
+// (interleaved across the threads, read eight at a time); longer ones in
+// place in global memory.
 constexpr int kSortThreads = 128;
 constexpr int kSortCap = 32;
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_points(SceneDev sc, const int64_t *ptr_p,
-                                                              int32_t *slot_obs, int32_t *slot_cam,
-                                                              int32_t *slot_pt, DevStatus *ds) {
+                                                              int64_t *slot_key, int32_t *slot_obs,
+                                                              int32_t *slot_cam, int32_t *slot_pt,
+                                                              DevStatus *ds) {
   __shared__ int64_t keys[kSortCap * kSortThreads];
   const int tid = threadIdx.x;
   int j = blockIdx.x * blockDim.x + tid;
@@ -166,9 +170,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_points(SceneDev sc, const
     report_error(ds, UCOV_EPOINT, j);
   }
   if (t <= kSortCap) {
-    for (int a = 0; a < t; ++a) {
-      const int32_t o = slot_obs[p0 + a];
-      keys[a * kSortThreads + tid] = ((int64_t)sc.oc[o] << 32) | (uint32_t)o;
+    for (int a0 = 0; a0 < t; a0 += 8) {
+      int64_t kk[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kk[u] = a0 + u < t ? slot_key[p0 + a0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (a0 + u < t) keys[(a0 + u) * kSortThreads + tid] = kk[u];
     }
     for (int a = 1; a < t; ++a) {
       const int64_t k = keys[a * kSortThreads + tid];
@@ -191,22 +199,23 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_points(SceneDev sc, const
     }
     return;
   }
-  // insertion sort of a long segment by camera id
+  // insertion sort of a long segment's keys in place
   for (int64_t a = p0 + 1; a < p1; ++a) {
-    int32_t o = slot_obs[a];
-    int32_t c = sc.oc[o];
+    const int64_t k = slot_key[a];
     int64_t b = a - 1;
-    while (b >= p0 && sc.oc[slot_obs[b]] > c) {
-      slot_obs[b + 1] = slot_obs[b];
+    while (b >= p0 && slot_key[b] > k) {
+      slot_key[b + 1] = slot_key[b];
       --b;
     }
-    slot_obs[b + 1] = o;
+    slot_key[b + 1] = k;
   }
   int32_t prev = -1;
   for (int64_t a = p0; a < p1; ++a) {
-    int32_t c = sc.oc[slot_obs[a]];
-    if (c == prev) report_error(ds, UCOV_EINVAL, slot_obs[a]);
+    const int64_t k = slot_key[a];
+    const int32_t c = (int32_t)(k >> 32), o = (int32_t)(k & 0xffffffff);
+    if (c == prev) report_error(ds, UCOV_EINVAL, o);
     prev = c;
+    slot_obs[a] = o;
     slot_cam[a] = c;
     slot_pt[a] = j;
   }
@@ -1249,9 +1258,9 @@ void launch_count_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStr
 
 void launch_group_points(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_slots, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
-                     w.ptr_p, w.cur_p, w.slot_obs);
+                     w.ptr_p, w.cur_p, w.slot_key);
   hipLaunchKernelGGL(k_sort_points, dim3(blocks_for(sc.m, kSortThreads)), dim3(kSortThreads), 0,
-                     st, sc, w.ptr_p, w.slot_obs, w.slot_cam, w.slot_pt, ds);
+                     st, sc, w.ptr_p, w.slot_key, w.slot_obs, w.slot_cam, w.slot_pt, ds);
 }
 
 void launch_jacobians(const SceneDev &sc, SceneWork &w, double *jp_out, double *jx_out,

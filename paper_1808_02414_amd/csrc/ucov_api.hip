@@ -45,7 +45,7 @@ struct ucov_ctx {
   int64_t n_nonzero = 0;         // non-empty bins of the last scene stage
   hipEvent_t ev[8] = {};
   // workspace
-  Buf cnt_p, ptr_p, cur_p, slot_obs, slot_cam, slot_pt, rec;
+  Buf cnt_p, ptr_p, cur_p, slot_key, slot_obs, slot_cam, slot_pt, rec;
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos;
   Buf cam_iota, cam_keys, cam_slots, cam_ptr, cam_tmp;  // slots grouped by camera
   Buf zdiag, hc, q, s, alpha, amat, tmat;
@@ -155,6 +155,7 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   UCOV_TRY(ensure(c, c->cnt_p, 4 * m));
   UCOV_TRY(ensure(c, c->ptr_p, 8 * (m + 1)));
   UCOV_TRY(ensure(c, c->cur_p, 4 * m));
+  UCOV_TRY(ensure(c, c->slot_key, 8 * t));
   UCOV_TRY(ensure(c, c->slot_obs, 4 * t));
   UCOV_TRY(ensure(c, c->slot_cam, 4 * t));
   UCOV_TRY(ensure(c, c->slot_pt, 4 * t));
@@ -164,6 +165,7 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.cnt_p = as<int32_t>(c->cnt_p);
   w.ptr_p = as<int64_t>(c->ptr_p);
   w.cur_p = as<int32_t>(c->cur_p);
+  w.slot_key = as<int64_t>(c->slot_key);
   w.slot_obs = as<int32_t>(c->slot_obs);
   w.slot_cam = as<int32_t>(c->slot_cam);
   w.slot_pt = as<int32_t>(c->slot_pt);
@@ -245,6 +247,7 @@ SceneWork scene_work(ucov_ctx *c) {
   w.cnt_p = as<int32_t>(c->cnt_p);
   w.ptr_p = as<int64_t>(c->ptr_p);
   w.cur_p = as<int32_t>(c->cur_p);
+  w.slot_key = as<int64_t>(c->slot_key);
   w.slot_obs = as<int32_t>(c->slot_obs);
   w.slot_cam = as<int32_t>(c->slot_cam);
   w.slot_pt = as<int32_t>(c->slot_pt);
@@ -436,7 +439,7 @@ void ucov_destroy(ucov_ctx *c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_obs, &c->slot_cam, &c->slot_pt,
+  Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_key, &c->slot_obs, &c->slot_cam, &c->slot_pt,
                  &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount, &c->nzpos,
                  &c->cam_iota, &c->cam_keys, &c->cam_slots, &c->cam_ptr, &c->cam_tmp,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,

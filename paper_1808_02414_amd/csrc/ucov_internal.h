@@ -82,6 +82,7 @@ struct SceneWork {
   int32_t *cnt_p;     // m
   int64_t *ptr_p;     // m + 1
   int32_t *cur_p;     // m
+  int64_t *slot_key;  // t: (camera << 32 | observation) of each slot before the sort
   int32_t *slot_obs;  // t: observation id of each slot
   int32_t *slot_cam;  // t
   int32_t *slot_pt;   // t
