@@ -492,18 +492,19 @@ __global__ __launch_bounds__(kCamThreads) void k_pair_count_cam(
 __global__ __launch_bounds__(kCamThreads) void k_pair_fill_cam(
     SceneDev sc, const int64_t *cam_ptr, const int32_t *cam_slots, const int64_t *ptr_p,
     const int32_t *slot_cam, const int32_t *slot_pt, const int64_t *bin_ptr, int2 *pairs) {
-  extern __shared__ int32_t cur[];
+  extern __shared__ int32_t cur[];  // next position of each bin, from the row's start
   const int i = blockIdx.x;
   const int c0 = sc.cam_scene ? sc.cam_off[sc.cam_scene[i]] : 0;
   const int nk = i - c0 + 1;
-  for (int k = threadIdx.x; k < nk; k += blockDim.x) cur[k] = 0;
-  __syncthreads();
   const int64_t row = bin_of(sc, i, c0);
+  const int64_t base = bin_ptr[row];  // int32 offsets: the host launches this below 2^31 pairs
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) cur[k] = (int32_t)(bin_ptr[row + k] - base);
+  __syncthreads();
   for (int64_t e = cam_ptr[i] + threadIdx.x; e < cam_ptr[i + 1]; e += blockDim.x) {
     const int a = cam_slots[e];
     for (int64_t b = ptr_p[slot_pt[a]]; b <= a; ++b) {
       const int k = slot_cam[b] - c0;
-      pairs[bin_ptr[row + k] + atomicAdd(&cur[k], 1)] = make_int2(a, (int)b);
+      pairs[base + atomicAdd(&cur[k], 1)] = make_int2(a, (int)b);
     }
   }
 }

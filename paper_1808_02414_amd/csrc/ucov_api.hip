@@ -234,7 +234,8 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.pairs = as<int2>(c->pairs);
   w.zdiag = as<double>(c->zdiag);
   w.hc = as<double>(c->hc);
-  if (cam_major) launch_pair_fill_cam(sc, w, (int)mc, st);
+  // the camera-major fill keeps LDS cursors as int32 offsets within a row
+  if (cam_major && npairs < ((int64_t)1 << 31)) launch_pair_fill_cam(sc, w, (int)mc, st);
   else launch_pair_fill(sc, w, st);
   hipEventRecord(c->ev[1], st);
   launch_camera_diag(sc, w, c->ds, st);

@@ -133,7 +133,8 @@ void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStr
 void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st);
 // Camera-major bins for scenes of at most kCamHistMax cameras (LDS counters
 // per camera): the camera lists, then every bin count (no prior zero fill),
-// then the pairs.  camera_lists_scratch: bytes of sort scratch for t slots;
+// then the pairs (fewer than 2^31 in all; else launch_pair_fill).
+// camera_lists_scratch: bytes of sort scratch for t slots;
 // launch_camera_lists returns nonzero when the sort cannot be launched.
 constexpr int kCamHistMax = 16384;
 size_t camera_lists_scratch(int64_t t);
