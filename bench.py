@@ -1,22 +1,24 @@
 """Throughput of the exact camera covariance on one MI355X.
 
-Default workload (``--workload spiral500``): the 500-camera spiral scene
-(50 000 points, ~300 000 observations, Z 4500 x 4500, seed 0).  One step is
-one call of the whole hot path (Jacobians, point blocks and Schur scatter,
-nullspace and gauge, dense inverse, block extraction) on a scene already
-resident in HBM, ending with the n x 81 FP64 covariance blocks in HBM.
+Default workload (``--workload clustered3000``): the large scene, 10 sites of
+300 cameras (500 000 points, Zipf track lengths, ~3.4 million observations,
+Z 27000 x 27000, seed 0).  One step is one call of the whole hot path
+(Jacobians, point blocks and Schur scatter, nullspace and gauge, dense
+inverse, block extraction) on a scene already resident in HBM, ending with
+the n x 81 FP64 covariance blocks in HBM.
+
+``--workload spiral500``: the 500-camera spiral scene (50 000 points, ~300 000
+observations, Z 4500 x 4500, seed 0), one call per step.
 
 ``--workload batch256``: 256 independent sub-reconstructions (20-400 cameras,
 100 points per camera), one batched call per step.
 
-``--workload clustered3000``: the large scene, 10 sites of 300 cameras
-(500 000 points, Zipf track lengths, ~3.4 million observations, Z 27000 x
-27000, seed 0), one call per step.
-
 Prints one JSON line with the throughput in cameras/s, the roofline of the
-dominant stage (the FP64 dense inverse, 2N^3/3 algorithmic flops per scene
-and step, timed with HIP events on the library's stream) and the CPU oracle
-timed on the host cores on (a bounded sample of) the same workload.
+dominant stage (the dense inverse, 2N^3/3 algorithmic flops per scene and
+step, timed with HIP events on the library's stream), the CPU oracle timed on
+the host cores on a bounded sample of the same workload, and the largest
+per-block relative error of the timed call's output against the oracle
+(exit status 1 above 1e-6).
 """
 from __future__ import annotations
 
@@ -38,7 +40,12 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "cameras/s of exact covariance + MFMA util on Z^-1, at 1e-6 rel err vs FP64"
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_inverse_fp64_spiral500_hbm_counters.md")
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "clustered3000_blocks.json")
+TOLERANCE = 1e-6  # per-block relative Frobenius error against the FP64 oracle
+
+
+def traffic_profile(workload):
+    return os.path.join(ROOT, "profiles", f"dense_inverse_fp64_{workload}_hbm_counters.md")
 DEFAULT_TILE_THRESHOLD = 4096  # the library's untuned 32 x 32-tile threshold
 
 
@@ -64,12 +71,13 @@ def tile_schedule(n, small):
 DENSE_SOURCE = os.path.join(ROOT, "paper_1808_02414_amd", "csrc", "dense_kernels.hip")
 
 
-def recorded_traffic():
+def recorded_traffic(workload):
     """HBM bytes per step of the dense stage from the committed counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
-    dense kernels have changed since they were taken."""
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there
+    are none for this workload or the dense kernels have changed since they
+    were taken."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(traffic_profile(workload)).read()
         src = hashlib.sha256(open(DENSE_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -90,15 +98,18 @@ def _threads():
 
 def cpu_baseline(scenes, budget_s=20.0):
     """Time the FP64 oracle (as it stands) on the host: whole scenes of the
-    workload in order until about ``budget_s`` seconds have been spent."""
+    workload in order until about ``budget_s`` seconds have been spent.
+    Returns the baseline and the oracle's blocks of the scenes it solved."""
     import numpy as np
     import oracle
     cams, dt, k = 0, 0.0, 0
+    ref = []
     for s in scenes:
         t0 = time.perf_counter()
         out = oracle.camera_covariance(s)
         dt += time.perf_counter() - t0
         assert np.all(np.isfinite(out["blocks"]))
+        ref.append(out["blocks"])
         cams += s.n_cams
         k += 1
         if dt >= budget_s:
@@ -106,13 +117,80 @@ def cpu_baseline(scenes, budget_s=20.0):
     what = (f"one full oracle solve of the benchmark scene ({cams} cameras)" if len(scenes) == 1
             else f"full oracle solves of the first {k} of {len(scenes)} scenes ({cams} cameras)")
     return {"value": cams / dt, "unit": "cameras/s", "cores": _threads(),
-            "kind": "oracle", "seconds": dt, "sample": what}
+            "kind": "oracle", "seconds": dt, "sample": what}, ref
+
+
+def cpu_baseline_large(scene, point_stride=10, block=9000):
+    """The oracle on the large scene in bounded pieces, each scaled by its
+    cost law (one whole solve takes minutes on the host):
+
+    * the scene stage (Jacobians, normal-equation blocks, point-block
+      inverses, the Schur complement Z and the nullspace basis) on the
+      observations of every ``point_stride``-th point, times point_stride
+      (its cost is linear in the observations);
+    * the oracle's whole-inverse mode (Jacobi-scaled Cholesky factorisation of
+      Z + aQQ^T and its solve against the identity) on the leading
+      ``block`` x ``block`` block of that Z, times (N / block)^3.
+    """
+    import numpy as np
+    from oracle import camera, covariance, nullspace, schur
+    import scenegen
+    sel = scene.obs_pt % point_stride == 0
+    keep_pts = np.unique(scene.obs_pt[sel])
+    remap = np.full(scene.n_pts, -1, np.int64)
+    remap[keep_pts] = np.arange(keep_pts.size)
+    sub = scenegen.Scene(scene.cams, scene.pts[keep_pts], scene.obs_cam[sel],
+                         remap[scene.obs_pt[sel]].astype(np.int32))
+    oc, op = sub.obs_cam.astype(np.int64), sub.obs_pt.astype(np.int64)
+    n, m = sub.n_cams, sub.n_pts
+    t0 = time.perf_counter()
+    JP, JX = camera.jacobians(sub.cams, sub.pts, oc, op)
+    Lam = schur.information_blocks(None, oc.size)
+    U, V, W = schur.normal_blocks(JP, JX, Lam, oc, op, n, m)
+    Vinv, _ = schur.point_block_inverses(V)
+    Z = schur.reduced_camera_matrix(U, W, Vinv, oc, op, n, m)
+    Hr = nullspace.rotation_blocks(sub.cams, sub.pts, oc, op, JP, JX)
+    Q = covariance.orthonormal_basis(nullspace.camera_rows(sub.cams, Hr))
+    t_scene = time.perf_counter() - t0
+    N = Z.shape[0]
+    b = min(block, N)
+    Zb = np.ascontiguousarray(Z[:b, :b])
+    Qb = np.ascontiguousarray(Q[:b])
+    del Z, U, V, W, JP, JX
+    t0 = time.perf_counter()
+    S = covariance.pseudo_inverse(Zb, Qb, covariance.balanced_alpha(Zb, Qb))
+    t_dense = time.perf_counter() - t0
+    assert np.all(np.isfinite(S))
+    est = point_stride * t_scene + (N / b) ** 3 * t_dense
+    return {"value": scene.n_cams / est, "unit": "cameras/s", "cores": _threads(),
+            "kind": "oracle", "seconds": t_scene + t_dense, "estimated_solve_s": est,
+            "sample": (f"oracle stages on pieces, scaled by their cost law: the scene stage "
+                       f"(Jacobians to Z and the nullspace basis) on the observations of every "
+                       f"{point_stride}th point ({t_scene:.1f} s, x{point_stride}); the "
+                       f"whole-inverse mode (scaled Cholesky factor and solve against the "
+                       f"identity) on the leading {b}x{b} block of Z ({t_dense:.1f} s, "
+                       f"x(N/{b})^3 = {(N / b) ** 3:.1f}); estimated solve {est:.0f} s for "
+                       f"{scene.n_cams} cameras")}
+
+
+def max_block_error(got, ref):
+    """Largest per-block relative Frobenius error of got against ref."""
+    import numpy as np
+    return float(max(np.linalg.norm(g - r) / np.linalg.norm(r) for g, r in zip(got, ref)))
+
+
+def golden_c3():
+    import numpy as np
+    with open(GOLDEN_C3) as f:
+        gold = json.load(f)
+    ref = np.array([[float(v) for v in b] for b in gold["blocks"]]).reshape(-1, 9, 9)
+    return gold["cameras"], ref
 
 
 def run_single(args, ucov, torch, np, scene):
     ctx = ucov.Context(0)
     dev = ucov.DeviceScene.from_scene(scene, "cuda:0")
-    prec = ucov.FP64 if args.precision == "fp64" else ucov.FP32_NS
+    prec = {"fp64": ucov.FP64, "fp32ns": ucov.FP32_NS}[args.precision]
     if prec == ucov.FP64 and not args.no_tune:
         # the library's tile-schedule tuning for this size, before the timed steps
         args.tuned_threshold = ctx.tune_dense(9 * scene.n_cams)[0]
@@ -126,7 +204,7 @@ def run_single(args, ucov, torch, np, scene):
         _, rep = ctx.camera_covariance(dev, precision=prec, out=out)
         reps.append(rep)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, reps, [9 * scene.n_cams]
+    return time.perf_counter() - t0, reps, [9 * scene.n_cams], out
 
 
 def run_batch(args, ucov, torch, np, scenes):
@@ -143,7 +221,7 @@ def run_batch(args, ucov, torch, np, scenes):
         _, _, rep = ctx.camera_covariance_batched(devs, out=out)
         reps.append(rep)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, reps, [9 * s.n_cams for s in scenes]
+    return time.perf_counter() - t0, reps, [9 * s.n_cams for s in scenes], out
 
 
 def main():
@@ -152,7 +230,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["spiral500", "batch256", "clustered3000"],
-                    default="spiral500")
+                    default="clustered3000")
     ap.add_argument("--precision", choices=["fp64", "fp32ns"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -186,20 +264,22 @@ def main():
     if args.workload == "spiral500":
         scene = scenegen.spiral_slab(0, n=args.n_cams, m=args.n_pts)
         scenes = [scene]
-        dt, reps, Ns = run_single(args, ucov, torch, np, scene)
+        dt, reps, Ns, out = run_single(args, ucov, torch, np, scene)
         workload = (f"spiral_slab: {scene.n_cams} cameras, {scene.n_pts} points, "
                     f"{scene.n_obs} observations, Z {Ns[0]}x{Ns[0]}, seed 0")
     elif args.workload == "clustered3000":
+        print("bench: generating the 3000-camera scene", file=sys.stderr, flush=True)
         scene = scenegen.clustered(0)
         scenes = [scene]
-        dt, reps, Ns = run_single(args, ucov, torch, np, scene)
+        print("bench: timing", file=sys.stderr, flush=True)
+        dt, reps, Ns, out = run_single(args, ucov, torch, np, scene)
         workload = (f"clustered: 10 sites of 300 cameras, {scene.n_pts} points, "
                     f"{scene.n_obs} observations, Z {Ns[0]}x{Ns[0]}, seed 0")
     else:
         if args.precision != "fp64":
             sys.exit("the batched workload runs in FP64")
         scenes = scenegen.batch_scenes()
-        dt, reps, Ns = run_batch(args, ucov, torch, np, scenes)
+        dt, reps, Ns, out = run_batch(args, ucov, torch, np, scenes)
         workload = (f"batch_scenes: {len(scenes)} independent spiral scenes, "
                     f"{sum(s.n_cams for s in scenes)} cameras (20-400 per scene), "
                     f"{sum(s.n_pts for s in scenes)} points, {sum(s.n_obs for s in scenes)} "
@@ -232,8 +312,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      # the counters were taken with the default tile schedule
-                     "traffic": (recorded_traffic() if args.workload == "spiral500"
-                                 and args.precision == "fp64"
+                     "traffic": (recorded_traffic(args.workload)
+                                 if args.workload != "batch256" and args.precision == "fp64"
                                  and tile_schedule(np_pad, getattr(args, "tuned_threshold",
                                                                    DEFAULT_TILE_THRESHOLD))
                                  == tile_schedule(np_pad, DEFAULT_TILE_THRESHOLD) else None),
@@ -247,15 +327,30 @@ def main():
     if args.precision == "fp32ns":
         line["ns_iters"] = int(reps[-1]["ns_iters"])
         line["ns_residual"] = float(reps[-1]["ns_residual"])
+    # the timed call's output against the oracle
+    got = out.cpu().numpy()
+    if args.workload == "clustered3000":
+        cams_checked, ref = golden_c3()
+        err = max_block_error(got[cams_checked], ref)
+        checked = f"{len(cams_checked)} cameras against stored oracle blocks"
     if args.workload == "clustered3000" and not args.no_cpu_baseline:
-        # one oracle solve of this scene takes about ten minutes on the host
-        # (27000 x 27000 dense factorisation and the Schur complement of 3.4
-        # million observations): beyond the bounded sample, so not timed here
-        line["cpu_baseline"] = {"value": None, "unit": "cameras/s", "kind": "oracle",
-                                "sample": "not run: one oracle solve of this scene takes ~600 s"}
-    elif not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(scenes)
+        print("bench: timing the oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline_large(scenes[0])
+    elif args.workload != "clustered3000":
+        print("bench: timing the oracle", file=sys.stderr, flush=True)
+        base, refs = cpu_baseline(scenes, budget_s=0.0 if args.no_cpu_baseline else 20.0)
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = base
+        ncheck = sum(r.shape[0] for r in refs)
+        err = max_block_error(got[:ncheck], np.concatenate(refs))
+        checked = (f"all {ncheck} cameras" if len(scenes) == 1
+                   else f"the {ncheck} cameras of the first {len(refs)} scenes")
+    line["check"] = {"max_rel_fro": err, "tolerance": TOLERANCE, "against": "FP64 oracle",
+                     "cameras": checked}
     print(json.dumps(line), flush=True)
+    if not err <= TOLERANCE:
+        print(f"bench: output error {err:.3e} above {TOLERANCE:g}", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -116,10 +116,13 @@ typedef struct {
   int32_t ns_iters;    /* Newton-Schulz iterations performed */
   double ns_residual;  /* final |I - A X|_F / sqrt(N) (mixed precision only) */
   int64_t n_pairs;     /* (observation, observation) pairs in the Schur scatter */
-  /* stage times in milliseconds, measured with HIP events on the stream */
-  float ms_structure;  /* index sorting and pair binning */
-  float ms_schur;      /* Jacobians, point blocks, Z assembly (steps a1, a2) */
-  float ms_gauge;      /* nullspace, orthonormalisation, scaling (step a3) */
+  /* stage times in milliseconds, measured with HIP events on the stream
+   * (host round trips inside a stage count towards it) */
+  float ms_structure;  /* grouping the observations by point, camera-pair binning */
+  float ms_schur;      /* Jacobians, point blocks, diagonal camera blocks with the
+                          rotation rows of the nullspace, assembly of the scaled
+                          Z + aQQ^T (steps a1, a2) */
+  float ms_gauge;      /* orthonormal gauge basis, weight and scaling (step a3) */
   float ms_inverse;    /* dense factorisation and inversion (step a4) */
   float ms_extract;    /* covariance block extraction (step a4) */
   int32_t bad_scene;   /* batched calls: scene of the failure, -1 if none */
@@ -222,7 +225,7 @@ int ucov_tune_dense(ucov_ctx *ctx, int64_t n, int64_t *threshold, float *ms);
  * opt->precision must be UCOV_FP64 and opt->gauge UCOV_GAUGE_CAMERA (else
  * UCOV_EINVAL).
  * rep: ms_inverse covers the dense stage of all scenes (identity padding,
- * the batched factorisation and inversion, block extraction), ms_extract is 0,
+ * the batched factorisation and inversion), ms_extract the block extraction,
  * alpha is scene 0's; on failure bad_scene names the scene and bad_index the
  * observation, point or camera within it.
  * Limits: at most 2^27 cameras and 2^31 - 1 points and observations in total. */
@@ -344,6 +347,49 @@ int ucov_screener_labels(ucov_ctx *ctx, int64_t n, const double *cov, const doub
 int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const double *scale,
                              const float *out_mean, const float *out_std, double *cov,
                              double *spread);
+
+/* Standardisation statistics of a training set of n >= 2 cameras: feat
+ * (n x 55) and their exact covariance blocks cov (n x 81).  in_mean, in_std
+ * (55 each): per feature the mean and the standard deviation (n - 1 in the
+ * denominator, at least 1e-6); scale (9): per parameter the square root of
+ * the lower median (rank (n - 1) / 2 ascending) of its variance over the
+ * blocks; out_mean, out_std (45 each): mean and standard deviation of the
+ * labels of ucov_screener_labels taken with out_mean 0 and out_std 1.  Every
+ * sum runs in a fixed order (the same bits on every call).  UCOV_EINVAL if a
+ * block is not positive definite. */
+int ucov_screener_stats(ucov_ctx *ctx, int64_t n, const float *feat, const double *cov,
+                        float *in_mean, float *in_std, double *scale, float *out_mean,
+                        float *out_std);
+
+/* A trained screener: its parameters, statistics and (optionally) the Adam
+ * state to resume training.  All arrays are device arrays of the sizes given. */
+typedef struct {
+  float *params;    /* ucov_mlp_param_count() */
+  float *in_mean;   /* 55 */
+  float *in_std;    /* 55 */
+  double *scale;    /* 9 */
+  float *out_mean;  /* 45 */
+  float *out_std;   /* 45 */
+  float *adam_m;    /* ucov_mlp_param_count(), or NULL (then adam_v NULL too) */
+  float *adam_v;    /* ucov_mlp_param_count(), or NULL */
+  int64_t step;     /* Adam steps taken so far (host value) */
+} ucov_screener;
+
+/* Write the screener to a file (host path): a 64-byte header (magic
+ * "UCOVSCR1", version 1, the network's sizes, whether the Adam moments are
+ * stored, the parameter count and step), then params, in_mean, in_std,
+ * out_mean, out_std (float32), scale (float64), adam_m, adam_v (float32, when
+ * given), then a 64-bit FNV-1a hash of that payload; little-endian.  The
+ * context's stream is synchronised first.  UCOV_EINVAL on a bad argument or
+ * an I/O failure. */
+int ucov_screener_save(ucov_ctx *ctx, const char *path, const ucov_screener *s);
+
+/* Read a file written by ucov_screener_save into the caller's device arrays
+ * (s->adam_m and s->adam_v may be NULL to skip the Adam moments; asking for
+ * them from a file without them is UCOV_EINVAL) and set s->step.  UCOV_EINVAL
+ * when the file is missing, of another network, truncated or its hash does
+ * not match. */
+int ucov_screener_load(ucov_ctx *ctx, const char *path, ucov_screener *s);
 
 /* Diagnostic, host only (no device needed): builds the launch plan that the
  * batched entry point uses for matrices of padded sizes np[0..count)

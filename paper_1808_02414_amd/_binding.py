@@ -28,6 +28,14 @@ class Scene(ctypes.Structure):
                 ("obs_info", ctypes.c_void_p)]
 
 
+class ScreenerStruct(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("in_mean", ctypes.c_void_p),
+                ("in_std", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("out_mean", ctypes.c_void_p), ("out_std", ctypes.c_void_p),
+                ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("step", ctypes.c_int64)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("alpha", ctypes.c_double), ("gauge", ctypes.c_int32)]
@@ -52,7 +60,9 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_mlp_param_count", "ucov_screener_features", "ucov_mlp_forward",
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
            "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
-           "ucov_full_covariance", "ucov_update_covariance", "ucov_tune_dense"]
+           "ucov_full_covariance", "ucov_update_covariance", "ucov_tune_dense",
+           "ucov_screener_stats", "ucov_screener_save",
+           "ucov_screener_load"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -98,6 +108,9 @@ def load(path: str = LIB_PATH):
         "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
         "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
         "ucov_plan_check": (ctypes.c_int, [P, I32, P]),
+        "ucov_screener_stats": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P]),
+        "ucov_screener_save": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(ScreenerStruct)]),
+        "ucov_screener_load": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(ScreenerStruct)]),
         "ucov_subrecon_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), I32, P,
                                                     ctypes.POINTER(Options), P, P, P,
                                                     ctypes.POINTER(Report)]),
@@ -448,6 +461,57 @@ class Context:
                                            self._dev(out_std, torch.float32), lab.data_ptr())
         self._check(rc)
         return lab
+
+    def screener_stats(self, features, covs):
+        """Standardisation statistics of a training set (features (n, 55)
+        float32, covariances (n, 9, 9) float64): in_mean, in_std, scale,
+        out_mean, out_std as device tensors."""
+        torch = self.torch
+        dev = features.device
+        n = features.shape[0]
+        in_mean = torch.empty(N_FEATURES, dtype=torch.float32, device=dev)
+        in_std = torch.empty_like(in_mean)
+        scale = torch.empty(9, dtype=torch.float64, device=dev)
+        out_mean = torch.empty(N_OUTPUTS, dtype=torch.float32, device=dev)
+        out_std = torch.empty_like(out_mean)
+        self._stream()
+        self._check(self.lib.ucov_screener_stats(
+            self.h, n, self._dev(features, torch.float32), self._dev(covs, torch.float64),
+            in_mean.data_ptr(), in_std.data_ptr(), scale.data_ptr(), out_mean.data_ptr(),
+            out_std.data_ptr()))
+        return in_mean, in_std, scale, out_mean, out_std
+
+    def _screener_struct(self, t, step=0):
+        ptr = self._ptr
+        return ScreenerStruct(ptr(t["params"]), ptr(t["in_mean"]), ptr(t["in_std"]),
+                              ptr(t["scale"]), ptr(t["out_mean"]), ptr(t["out_std"]),
+                              ptr(t.get("adam_m")), ptr(t.get("adam_v")), int(step))
+
+    def screener_save(self, path: str, tensors: dict, step: int = 0):
+        """Write a screener (dict of device tensors: params, in_mean, in_std,
+        scale, out_mean, out_std and optionally adam_m, adam_v) to ``path``."""
+        self._stream()
+        st = self._screener_struct(tensors, step)
+        self._check(self.lib.ucov_screener_save(self.h, os.fsencode(path), ctypes.byref(st)))
+
+    def screener_load(self, path: str, adam: bool = False, device="cuda"):
+        """Read a screener file into new device tensors; returns (dict, step)."""
+        torch = self.torch
+        P = self.mlp_param_count()
+        f32, f64 = torch.float32, torch.float64
+        t = {"params": torch.empty(P, dtype=f32, device=device),
+             "in_mean": torch.empty(N_FEATURES, dtype=f32, device=device),
+             "in_std": torch.empty(N_FEATURES, dtype=f32, device=device),
+             "scale": torch.empty(9, dtype=f64, device=device),
+             "out_mean": torch.empty(N_OUTPUTS, dtype=f32, device=device),
+             "out_std": torch.empty(N_OUTPUTS, dtype=f32, device=device)}
+        if adam:
+            t["adam_m"] = torch.empty(P, dtype=f32, device=device)
+            t["adam_v"] = torch.empty(P, dtype=f32, device=device)
+        self._stream()
+        st = self._screener_struct(t)
+        self._check(self.lib.ucov_screener_load(self.h, os.fsencode(path), ctypes.byref(st)))
+        return t, int(st.step)
 
     def screener_covariance(self, y, scale, out_mean, out_std):
         """Predicted (n, 9, 9) covariances and (n,) spreads from network outputs."""

@@ -489,7 +489,13 @@ __global__ __launch_bounds__(kCamThreads) void k_pair_count_cam(
   for (int k = threadIdx.x; k < nk; k += blockDim.x) bin_cnt[row + k] = hist[k];
 }
 
-__global__ __launch_bounds__(kCamThreads) void k_pair_fill_cam(
+// One wave per camera: every LDS cursor increment of the row then comes from
+// one wave, whose atomic instructions the LDS resolves in a fixed lane order,
+// so the pairs of a bin are placed in the same order on every call and the
+// bin sums that follow are bitwise reproducible.
+constexpr int kFillThreads = 64;
+
+__global__ __launch_bounds__(kFillThreads) void k_pair_fill_cam(
     SceneDev sc, const int64_t *cam_ptr, const int32_t *cam_slots, const int64_t *ptr_p,
     const int32_t *slot_cam, const int32_t *slot_pt, const int64_t *bin_ptr, int2 *pairs) {
   extern __shared__ int32_t cur[];  // next position of each bin, from the row's start
@@ -868,10 +874,11 @@ __global__ __launch_bounds__(kGaugeThreads) void k_gauge_scenes(SceneDev sc, con
 // grows).  Written as P P^T with P = G L_F^-T, it takes the place of a Q Q^T.
 // ---------------------------------------------------------------------------
 
-// F += H_p^T V_j^-1 H_p per point (V_j from the point's whitened J_X rows),
-// 28 upper-triangle values reduced per workgroup and added to f.
+// F_j = H_p^T V_j^-1 H_p per point (V_j from the point's whitened J_X rows),
+// 28 upper-triangle values summed per workgroup into fpart (28 per
+// workgroup); k_paper_fsum adds the workgroups' sums in a fixed order.
 __global__ __launch_bounds__(256) void k_paper_f(SceneDev sc, const int64_t *ptr_p,
-                                                const double *rec, double *f) {
+                                                const double *rec, double *fpart) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[28];
 #pragma unroll
@@ -922,7 +929,29 @@ __global__ __launch_bounds__(256) void k_paper_f(SceneDev sc, const int64_t *ptr
   __syncthreads();
   if (threadIdx.x < 28) {
     const int k = threadIdx.x;
-    atomicAdd(&f[k], part[0][k] + part[1][k] + part[2][k] + part[3][k]);
+    fpart[28 * (int64_t)blockIdx.x + k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+  }
+}
+
+// f[k] = sum over the nb workgroup sums of k_paper_f, in a fixed order (each
+// thread a fixed stride of workgroups, then a fixed tree): the same bits on
+// every call.
+constexpr int kFsumThreads = 256;
+
+__global__ __launch_bounds__(kFsumThreads) void k_paper_fsum(int64_t nb, const double *fpart,
+                                                           double *f) {
+  __shared__ double red[kFsumThreads];
+  for (int k = 0; k < 28; ++k) {
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += kFsumThreads) v += fpart[28 * b + k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kFsumThreads / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) f[k] = red[0];
+    __syncthreads();
   }
 }
 
@@ -1330,7 +1359,7 @@ void launch_pair_count_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
 
 void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_pair_fill_cam, dim3(sc.n), dim3(kCamThreads),
+  hipLaunchKernelGGL(k_pair_fill_cam, dim3(sc.n), dim3(kFillThreads),
                      sizeof(int32_t) * max_scene_cams, st, sc, w.cam_ptr, w.cam_slots, w.ptr_p,
                      w.slot_cam, w.slot_pt, w.bin_ptr, w.pairs);
 }
@@ -1355,12 +1384,15 @@ void launch_concat_scenes(int n_scenes, const BatchEntry *tab, int64_t max_elems
                      info, oc, op, cam_scene, ds);
 }
 
+int64_t paper_gauge_doubles(int64_t m) { return kPaperF + 28 * blocks_for(m, 256); }
+
 void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *ds,
                         hipStream_t st) {
   const int64_t N = 9 * (int64_t)sc.n;
-  fill_f64(f, 0.0, 28, st);
-  hipLaunchKernelGGL(k_paper_f, dim3(blocks_for(sc.m, 256)), dim3(256), 0, st, sc, w.ptr_p, w.rec,
-                     f);
+  const int64_t nb = blocks_for(sc.m, 256);
+  double *fpart = f + kPaperF;
+  hipLaunchKernelGGL(k_paper_f, dim3(nb), dim3(256), 0, st, sc, w.ptr_p, w.rec, fpart);
+  hipLaunchKernelGGL(k_paper_fsum, dim3(1), dim3(kFsumThreads), 0, st, nb, fpart, f);
   hipLaunchKernelGGL(k_paper_g, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs, w.rec,
                      w.slot_pt, w.hc, w.q);
   hipLaunchKernelGGL(k_paper_p, dim3(1), dim3(1024), 0, st, N, f, w.q, w.alpha, ds);

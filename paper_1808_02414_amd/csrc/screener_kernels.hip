@@ -350,11 +350,94 @@ __global__ void k_predicted_cov(int64_t n, const float *y, const double *D, cons
   if (spread) spread[i] = tr;
 }
 
+// ---------------------------------------------------------------------------
+// standardisation statistics of a training set
+// ---------------------------------------------------------------------------
+constexpr int kStatThreads = 256;
+
+// Fixed-order sum over the workgroup: each thread its strided share, then a
+// tree in LDS (the same bits on every call).
+__device__ inline double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kStatThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per column c of x (n x cols, row-major FP32): mean and the
+// standard deviation with n - 1 in the denominator, at least 1e-6.
+__global__ __launch_bounds__(kStatThreads) void k_col_stats(int64_t n, int cols, const float *x,
+                                                          float *mean, float *stdv) {
+  __shared__ double red[kStatThreads];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) s += (double)x[i * cols + c];
+  const double mu = block_sum(s, red) / (double)n;
+  double q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+    const double d = (double)x[i * cols + c] - mu;
+    q += d * d;
+  }
+  const double var = block_sum(q, red) / (double)(n - 1);
+  if (threadIdx.x == 0) {
+    mean[c] = (float)mu;
+    stdv[c] = fmaxf((float)sqrt(var), 1e-6f);
+  }
+}
+
+// Order-preserving unsigned key of a double.
+__device__ inline uint64_t order_key(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// One workgroup per diagonal entry a: D[a] = sqrt of the lower median of
+// cov[81 i + 10 a] over the n blocks (the value of rank (n - 1) / 2 in
+// ascending order), found bit by bit on the order-preserving keys.
+__global__ __launch_bounds__(kStatThreads) void k_diag_median(int64_t n, const double *cov,
+                                                            double *D) {
+  __shared__ double red[kStatThreads];
+  const int a = blockIdx.x;
+  uint64_t prefix = 0;
+  int64_t rank = (n - 1) / 2;  // rank among the values that share the prefix
+  for (int bit = 63; bit >= 0; --bit) {
+    const uint64_t hi_mask = bit == 63 ? 0 : ~((1ull << (bit + 1)) - 1);
+    int64_t cnt = 0;  // values with the prefix and a 0 at this bit
+    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+      const uint64_t k = order_key(cov[81 * i + 10 * a]);
+      cnt += ((k & hi_mask) == prefix) && !((k >> bit) & 1ull);
+    }
+    const int64_t zeros = (int64_t)block_sum((double)cnt, red);
+    if (rank >= zeros) {
+      rank -= zeros;
+      prefix |= 1ull << bit;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t b = (prefix >> 63) ? (prefix & 0x7fffffffffffffffull) : ~prefix;
+    D[a] = sqrt(__longlong_as_double((long long)b));
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+
+void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *stdv,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(kStatThreads), 0, st, n, cols, x, mean, stdv);
+}
+
+void launch_diag_median(int64_t n, const double *cov, double *D, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_median, dim3(9), dim3(kStatThreads), 0, st, n, cov, D);
+}
 
 void launch_screener_features(const SceneDev &sc, const SceneWork &w, int32_t *hist,
                               double *ang, int32_t *covis, float *feat, hipStream_t st) {

@@ -33,6 +33,24 @@ const char *code_name(int code) {
   }
 }
 
+// Stage marks of a call: HIP events recorded on the context's stream between
+// the launches of the stages the report times.
+enum EvMark {
+  kEvStart,      // before the first kernel
+  kEvGrouped,    // observations grouped and sorted by point
+  kEvPoints,     // Jacobians and point blocks done
+  kEvBins,       // camera-pair bins built and filled
+  kEvDiag,       // diagonal camera blocks and rotation nullspace rows done
+  kEvGauge,      // gauge basis, weight and scaling done
+  kEvAssembled,  // scaled regularised matrix assembled and padded
+  kEvInverse,    // dense factorisation and inversion done
+  kEvEnd,        // outputs written
+  kEvBatch,      // batched calls: before the concatenation of the scenes
+  kEvTune0,
+  kEvTune1,
+  kEvCount
+};
+
 }  // namespace
 
 struct ucov_ctx {
@@ -43,7 +61,7 @@ struct ucov_ctx {
   DevStatus *ds_host = nullptr;  // pinned host mirror
   int64_t *i64_host = nullptr;   // pinned host scalars [0] pairs, [1] non-empty bins
   int64_t n_nonzero = 0;         // non-empty bins of the last scene stage
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[kEvCount] = {};
   // workspace
   Buf cnt_p, ptr_p, cur_p, slot_key, slot_obs, slot_cam, slot_pt, rec;
   Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos;
@@ -58,8 +76,8 @@ struct ucov_ctx {
   DevStatus *h_ds = nullptr;  // pinned host copy of the per-scene status
   size_t h_ds_cap = 0;
   // learned screener
-  Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad;
-  Buf pg_f;  // the paper gauge's F (28 upper values), then L_F (7 x 7 row-major)
+  Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad, f_lab, f_zero;
+  Buf pg_f;  // the paper gauge's F (28 upper values), L_F (7 x 7 row-major), partial sums
   // dense stage: the tuned 32 x 32-tile threshold per padded size
   std::map<int64_t, int64_t> small_tiles;
   int64_t small_for(int64_t np) const {
@@ -141,6 +159,29 @@ int check_scene(ucov_ctx *c, const ucov_scene *s) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+float ev_ms(ucov_ctx *c, int a, int b) {
+  float t = 0.0f;
+  if (hipEventElapsedTime(&t, c->ev[a], c->ev[b]) != hipSuccess) {
+    hipGetLastError();
+    t = 0.0f;
+  }
+  return t;
+}
+
+// Stage times of a call that ran the whole scene stage: index grouping and
+// pair binning are "structure"; Jacobians, point blocks, the diagonal camera
+// blocks and the assembly of the Schur complement are "schur"; the gauge
+// basis, weight and scaling are "gauge".
+void report_stages(ucov_ctx *c, ucov_report *rep) {
+  if (!rep) return;
+  rep->ms_structure = ev_ms(c, kEvStart, kEvGrouped) + ev_ms(c, kEvPoints, kEvBins);
+  rep->ms_schur = ev_ms(c, kEvGrouped, kEvPoints) + ev_ms(c, kEvBins, kEvDiag) +
+                  ev_ms(c, kEvGauge, kEvAssembled);
+  rep->ms_gauge = ev_ms(c, kEvDiag, kEvGauge);
+  rep->ms_inverse = ev_ms(c, kEvAssembled, kEvInverse);
+  rep->ms_extract = ev_ms(c, kEvInverse, kEvEnd);
+}
+
 // Steps a1-a2 up to the per-camera diagonal blocks and the nullspace rows.
 // On return the slot records, pair bins, zdiag and hc are valid.
 // nbins: camera-pair bins, n(n+1)/2 for one scene, the sum over the scenes of
@@ -173,12 +214,13 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.scan_tmp = as<int64_t>(c->scan_tmp);
   hipStream_t st = c->stream;
 
-  hipEventRecord(c->ev[0], st);
+  hipEventRecord(c->ev[kEvStart], st);
   fill_i32(w.cnt_p, 0, m, st);
   fill_i32(w.cur_p, 0, m, st);
   launch_count_points(sc, w, c->ds, st);
   exclusive_scan(w.cnt_p, w.ptr_p, m, w.scan_tmp, st);
   launch_group_points(sc, w, c->ds, st);
+  hipEventRecord(c->ev[kEvGrouped], st);
   launch_jacobians(sc, w, jp_out, jx_out, c->ds, st);
   UCOV_TRY(check_hip(c, "jacobian kernels"));
   if (jac_only) return sync_status(c, rep, "jacobians");
@@ -196,6 +238,7 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.nzcount = as<int64_t>(c->nzcount);
   w.nzpos = as<int64_t>(c->nzpos);
   launch_point_blocks(sc, w, c->ds, st);
+  hipEventRecord(c->ev[kEvPoints], st);
   // camera-pair bins: camera-major with LDS counters where the largest
   // scene's cameras fit them, else one global atomic per pair
   const int64_t mc = max_scene_cams < 0 ? n : max_scene_cams;
@@ -237,8 +280,9 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   // the camera-major fill keeps LDS cursors as int32 offsets within a row
   if (cam_major && npairs < ((int64_t)1 << 31)) launch_pair_fill_cam(sc, w, (int)mc, st);
   else launch_pair_fill(sc, w, st);
-  hipEventRecord(c->ev[1], st);
+  hipEventRecord(c->ev[kEvBins], st);
   launch_camera_diag(sc, w, c->ds, st);
+  hipEventRecord(c->ev[kEvDiag], st);
   UCOV_TRY(check_hip(c, "schur kernels"));
   return UCOV_OK;
 }
@@ -366,7 +410,7 @@ int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double 
              o.tol, it);
     return c->fail(UCOV_ENOCONV, buf);
   }
-  hipEventRecord(c->ev[4], st);
+  hipEventRecord(c->ev[kEvInverse], st);
   launch_extract_full(N, as<double>(c->m_x64), Np, as<double>(c->s), as<double>(c->q), N,
                       as<double>(c->alpha), o.gauge != UCOV_GAUGE_PAPER, cov_out, st);
   return UCOV_OK;
@@ -379,24 +423,20 @@ int run_dense_stage(ucov_ctx *c, int64_t N, const ucov_options &o, double *cov_o
   hipStream_t st = c->stream;
   double *A = as<double>(c->amat);
   launch_pad_identity(N, Np, A, Np, st);
-  hipEventRecord(c->ev[3], st);
+  hipEventRecord(c->ev[kEvAssembled], st);
   if (o.precision == UCOV_FP64) {
     UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
     spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st, c->small_for(Np));
-    hipEventRecord(c->ev[4], st);
+    hipEventRecord(c->ev[kEvInverse], st);
     launch_extract(N, A, Np, as<double>(c->s), as<double>(c->q), N, as<double>(c->alpha),
                    o.gauge != UCOV_GAUGE_PAPER, cov_out, st);
   } else {
     UCOV_TRY(run_mixed(c, N, Np, o, cov_out, rep));
   }
-  hipEventRecord(c->ev[5], st);
+  hipEventRecord(c->ev[kEvEnd], st);
   UCOV_TRY(check_hip(c, "dense kernels"));
   UCOV_TRY(sync_status(c, rep, "dense inverse"));
-  if (rep) {
-    hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
-    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
-    hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
-  }
+  if (rep) hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
   return UCOV_OK;
 }
 
@@ -447,7 +487,7 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
                  &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
-                 &c->mlp_ws, &c->mlp_grad, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
+                 &c->mlp_ws, &c->mlp_grad, &c->f_lab, &c->f_zero, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
                  &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
                  &c->fc_xq, &c->fc_k, &c->up_idx, &c->up_z, &c->up_jt, &c->up_b,
                  &c->up_t, &c->up_s, &c->up_tmp, &c->up_nj, &c->up_jn, &c->up_u, &c->up_g,
@@ -510,7 +550,11 @@ int ucov_gauge_basis(ucov_ctx *c, const ucov_scene *scene, double *hc, double *q
   return sync_status(c, nullptr, "gauge basis");
 }
 
-int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
+}  // extern "C"
+
+namespace {
+
+int camera_covariance_impl(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
                            double *cov_out, ucov_report *rep) {
   if (!c) return UCOV_EINVAL;
   UCOV_TRY(check_scene(c, scene));
@@ -530,26 +574,34 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   const int64_t Np = round_up(N, kTile);
   UCOV_TRY(ensure(c, c->q, 8 * 7 * N));
   UCOV_TRY(ensure(c, c->s, 8 * N));
+  UCOV_TRY(ensure(c, c->alpha, 8));
   UCOV_TRY(ensure(c, c->amat, 8 * Np * Np));
+  if (o.gauge == UCOV_GAUGE_PAPER)
+    UCOV_TRY(ensure(c, c->pg_f, 8 * paper_gauge_doubles(scene->n_pts)));
   SceneWork w = scene_work(c);
-  hipEventRecord(c->ev[2], c->stream);
   if (o.gauge == UCOV_GAUGE_PAPER) {
-    UCOV_TRY(ensure(c, c->pg_f, 8 * kPaperF));
     launch_paper_gauge(sc, w, as<double>(c->pg_f), c->ds, c->stream);
     launch_gauge(N, nullptr, w.q, w.zdiag, nullptr, 0, 1.0, w.s, w.alpha, c->ds, c->stream);
   } else {
     launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, c->stream);
   }
+  hipEventRecord(c->ev[kEvGauge], c->stream);
   launch_assemble(sc, w, 1, as<double>(c->amat), Np, c->n_nonzero, c->stream);
   UCOV_TRY(check_hip(c, "assemble"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
-  if (rep) {
-    hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[1]);
-    hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
-    hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
-  }
+  report_stages(c, rep);
   return UCOV_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
+                           double *cov_out, ucov_report *rep) {
+  return camera_covariance_impl(c, scene, opt, cov_out, rep);
+}
+
 
 int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const double *q,
                      const ucov_options *opt, double *cov_out, ucov_report *rep) {
@@ -569,7 +621,7 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
   hipStream_t st = c->stream;
   fill_i32(reinterpret_cast<int32_t *>(c->ds), 0, 2, st);
   hipMemcpyAsync(c->q.p, q, 8 * 7 * N, hipMemcpyDeviceToDevice, st);
-  hipEventRecord(c->ev[2], st);
+  hipEventRecord(c->ev[kEvDiag], st);
   launch_gauge(N, nullptr, as<double>(c->q), nullptr, z, ldz, o.alpha, as<double>(c->s),
                as<double>(c->alpha), c->ds, st);
   launch_scale_dense(N, z, ldz, as<double>(c->q), as<double>(c->s), as<double>(c->alpha),
@@ -577,7 +629,11 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
   o.gauge = UCOV_GAUGE_CAMERA;  // the caller's q is an orthonormal gauge basis
   UCOV_TRY(check_hip(c, "scale"));
   UCOV_TRY(run_dense_stage(c, N, o, cov_out, rep));
-  if (rep) hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
+  if (rep) {
+    rep->ms_gauge = ev_ms(c, kEvDiag, kEvAssembled);
+    rep->ms_inverse = ev_ms(c, kEvAssembled, kEvInverse);
+    rep->ms_extract = ev_ms(c, kEvInverse, kEvEnd);
+  }
   return UCOV_OK;
 }
 
@@ -610,7 +666,7 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
   UCOV_TRY(ensure(c, c->fc_x, 8 * Np * Np));
   UCOV_TRY(ensure(c, c->tmat, 8 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
   if (paper) {
-    UCOV_TRY(ensure(c, c->pg_f, 8 * kPaperF));
+    UCOV_TRY(ensure(c, c->pg_f, 8 * paper_gauge_doubles(scene->n_pts)));
     if (pt_cov) {
       UCOV_TRY(ensure(c, c->fc_part, 8 * 7 * N * xq_splits(N)));
       UCOV_TRY(ensure(c, c->fc_xq, 8 * 7 * N));
@@ -619,21 +675,21 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
   }
   SceneWork w = scene_work(c);
   hipStream_t st = c->stream;
-  hipEventRecord(c->ev[2], st);
   if (paper) {
     launch_paper_gauge(sc, w, as<double>(c->pg_f), c->ds, st);
     launch_gauge(N, nullptr, w.q, w.zdiag, nullptr, 0, 1.0, w.s, w.alpha, c->ds, st);
   } else {
     launch_gauge(N, w.hc, w.q, w.zdiag, nullptr, 0, o.alpha, w.s, w.alpha, c->ds, st);
   }
+  hipEventRecord(c->ev[kEvGauge], st);
   double *A = as<double>(c->amat), *X = as<double>(c->fc_x);
   launch_assemble(sc, w, 1, A, Np, c->n_nonzero, st);
   launch_pad_identity(N, Np, A, Np, st);
   UCOV_TRY(check_hip(c, "assemble"));
-  hipEventRecord(c->ev[3], st);
+  hipEventRecord(c->ev[kEvAssembled], st);
   spd_lower_inverse_fp64(A, Np, Np, as<double>(c->tmat), c->ds, st, c->small_for(Np));
   spd_inverse_from_factor(A, Np, Np, X, Np, st);
-  hipEventRecord(c->ev[4], st);
+  hipEventRecord(c->ev[kEvInverse], st);
   if (cam_cov) launch_full_camera(N, X, Np, w.s, w.q, w.alpha, !paper, cam_cov, ldc, st);
   if (pt_cov) {
     if (paper) {
@@ -644,17 +700,11 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
       launch_point_cov(sc, w, X, Np, w.q, nullptr, nullptr, false, pt_cov, st);
     }
   }
-  hipEventRecord(c->ev[5], st);
+  hipEventRecord(c->ev[kEvEnd], st);
   UCOV_TRY(check_hip(c, "whole covariance kernels"));
   UCOV_TRY(sync_status(c, rep, "whole covariance"));
-  if (rep) {
-    hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
-    hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[1]);
-    hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
-    hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
-    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
-    hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
-  }
+  if (rep) hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
+  report_stages(c, rep);
   return UCOV_OK;
 }
 
@@ -733,7 +783,7 @@ int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
   double *Zp = as<double>(c->up_z), *jt = as<double>(c->up_jt), *B = as<double>(c->up_b),
          *T = as<double>(c->up_t), *S = as<double>(c->up_s), *jn = as<double>(c->up_jn),
          *nj = as<double>(c->up_nj);
-  hipEventRecord(c->ev[2], st);
+  hipEventRecord(c->ev[kEvGauge], st);
   launch_copy_in(N, Np, cam_cov, ldc, Zp, st);
   fill_f64(jt, 0.0, Np * Kp, st);
   fill_f64(S, 0.0, Kp * Kp, st);
@@ -744,7 +794,7 @@ int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
   launch_pad_identity(2 * n_new, Kp, S, Kp, st);
   UCOV_TRY(check_hip(c, "update rows"));
   UCOV_TRY(sync_status(c, rep, "new observations"));
-  hipEventRecord(c->ev[3], st);
+  hipEventRecord(c->ev[kEvAssembled], st);
   // B = Z^+ JtT, S += JtT^T B (lower), S = L L^T -> L^-1, T = B L^-T, Z^+ -= T T^T
   gemm_f64(false, false, false, Np, Kp, Np, Zp, Np, jt, Np, B, Np, 1.0, 0.0, kGemmFull, st);
   gemm_f64(true, false, true, Kp, Kp, Np, jt, Np, B, Np, S, Kp, 1.0, 1.0, kGemmFull, st);
@@ -763,20 +813,20 @@ int ucov_update_covariance(ucov_ctx *c, const ucov_scene *scene, int64_t n_new,
     gemm_f64(false, true, false, Np, Np, 64, Wm, Np, Wm, Np, Zp, Np, 1.0, 1.0, kGemmFull, st);
     if (new_cov) hipMemcpyAsync(new_cov, cn, 8 * 81, hipMemcpyDeviceToDevice, st);
   }
-  hipEventRecord(c->ev[4], st);
+  hipEventRecord(c->ev[kEvInverse], st);
   // errors found on the device (a factor that does not exist, a new camera
   // its observations do not determine) leave the caller's matrix untouched
   UCOV_TRY(check_hip(c, "update products"));
   UCOV_TRY(sync_status(c, rep, "covariance update"));
   launch_copy_out(N, Np, Zp, cam_cov, ldc, st);
-  hipEventRecord(c->ev[5], st);
+  hipEventRecord(c->ev[kEvEnd], st);
   UCOV_TRY(check_hip(c, "update copy"));
   UCOV_TRY(sync_status(c, rep, "covariance update"));
   if (rep) {
-    hipEventElapsedTime(&rep->ms_structure, c->ev[0], c->ev[2]);
-    hipEventElapsedTime(&rep->ms_schur, c->ev[2], c->ev[3]);
-    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
-    hipEventElapsedTime(&rep->ms_extract, c->ev[4], c->ev[5]);
+    rep->ms_structure = ev_ms(c, kEvStart, kEvGauge);
+    rep->ms_schur = ev_ms(c, kEvGauge, kEvAssembled);
+    rep->ms_inverse = ev_ms(c, kEvAssembled, kEvInverse);
+    rep->ms_extract = ev_ms(c, kEvInverse, kEvEnd);
   }
   return UCOV_OK;
 }
@@ -801,12 +851,12 @@ int ucov_tune_dense(ucov_ctx *c, int64_t n, int64_t *threshold, float *ms) {
     float t_min = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       launch_tuning_matrix(Np, as<double>(c->amat), Np, st);
-      hipEventRecord(c->ev[6], st);
+      hipEventRecord(c->ev[kEvTune0], st);
       spd_lower_inverse_fp64(as<double>(c->amat), Np, Np, as<double>(c->tmat), c->ds, st, small);
-      hipEventRecord(c->ev[7], st);
-      if (hipEventSynchronize(c->ev[7]) != hipSuccess) return c->fail(UCOV_EDEVICE, "tuning run");
-      float t = 0.0f;
-      hipEventElapsedTime(&t, c->ev[6], c->ev[7]);
+      hipEventRecord(c->ev[kEvTune1], st);
+      if (hipEventSynchronize(c->ev[kEvTune1]) != hipSuccess)
+        return c->fail(UCOV_EDEVICE, "tuning run");
+      const float t = ev_ms(c, kEvTune0, kEvTune1);
       if (rep == 0 || t < t_min) t_min = t;
     }
     if (best_ms == 0.0f || t_min < best_ms) {
@@ -916,7 +966,7 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   UCOV_TRY(ensure(c, c->b_ds, sizeof(DevStatus) * S));
   if (any_info) UCOV_TRY(ensure(c, c->b_info, 8 * 3 * t));
   char *dt = static_cast<char *>(c->b_tab.p);
-  hipEventRecord(c->ev[6], st);
+  hipEventRecord(c->ev[kEvBatch], st);
   hipMemcpyAsync(dt, hs, total, hipMemcpyHostToDevice, st);
   clear_status(c);
   launch_concat_scenes(S, reinterpret_cast<const BatchEntry *>(dt), max_elems,
@@ -976,9 +1026,10 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   UCOV_TRY(ensure(c, c->alpha, 8 * S));
   UCOV_TRY(ensure(c, c->amat, 8 * std::max<int64_t>(1, a_off[S])));
   SceneWork w = scene_work(c);
-  hipEventRecord(c->ev[2], st);
   launch_gauge_scenes(sc, w.hc, w.q, w.zdiag, o.alpha, w.s, w.alpha, c->ds, st);
+  hipEventRecord(c->ev[kEvGauge], st);
   launch_assemble(sc, w, 1, as<double>(c->amat), 0, c->n_nonzero, st, max_cams);
+  hipEventRecord(c->ev[kEvAssembled], st);
   UCOV_TRY(check_hip(c, "batched assemble"));
   {
     const int rc = sync_status(c, rep, "batched gauge");
@@ -1009,13 +1060,14 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
       return c->fail(UCOV_ENOMEM, "batched inverse plan tables");
     }
   }
+  hipEventRecord(c->ev[kEvTune0], st);
   fill_i32(reinterpret_cast<int32_t *>(bds), 0, 2 * (int64_t)S, st);
-  hipEventRecord(c->ev[3], st);
   launch_pad_identity_scenes(S, max_np, sc.cam_off, sc.a_off, sc.a_ld, amat, st);
   spd_plan_run(c->plan, st);
+  hipEventRecord(c->ev[kEvInverse], st);
   launch_extract_scenes(n, sc.cam_scene, sc.cam_off, sc.a_off, sc.a_ld, amat, w.s, w.q, w.alpha,
                         cov_out, st);
-  hipEventRecord(c->ev[4], st);
+  hipEventRecord(c->ev[kEvEnd], st);
   UCOV_TRY(check_hip(c, "batched dense kernels"));
   // per-scene status of the dense stage
   if (c->h_ds_cap < (size_t)S) {
@@ -1045,11 +1097,9 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   if (alphas) hipMemcpy(alphas, c->alpha.p, 8 * (size_t)S, hipMemcpyDeviceToHost);
   if (rep) {
     hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
-    hipEventElapsedTime(&rep->ms_structure, c->ev[6], c->ev[1]);
-    hipEventElapsedTime(&rep->ms_schur, c->ev[1], c->ev[2]);
-    hipEventElapsedTime(&rep->ms_gauge, c->ev[2], c->ev[3]);
-    hipEventElapsedTime(&rep->ms_inverse, c->ev[3], c->ev[4]);
-    rep->ms_extract = 0.0f;
+    report_stages(c, rep);
+    rep->ms_structure += ev_ms(c, kEvBatch, kEvStart);
+    rep->ms_inverse = ev_ms(c, kEvTune0, kEvInverse);
   }
   return UCOV_OK;
 }
@@ -1293,6 +1343,157 @@ int ucov_screener_covariance(ucov_ctx *c, int64_t n, const float *y, const doubl
   launch_predicted_cov(n, y, scale, out_mean, out_std, cov, spread, c->stream);
   UCOV_TRY(check_hip(c, "screener covariance"));
   if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "screener covariance");
+  return UCOV_OK;
+}
+
+int ucov_screener_stats(ucov_ctx *c, int64_t n, const float *feat, const double *cov,
+                        float *in_mean, float *in_std, double *scale, float *out_mean,
+                        float *out_std) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 2 || !feat || !cov || !in_mean || !in_std || !scale || !out_mean || !out_std)
+    return c->fail(UCOV_EINVAL, "bad statistics arguments (n >= 2, every array given)");
+  hipSetDevice(c->device);
+  hipStream_t st = c->stream;
+  UCOV_TRY(ensure(c, c->f_lab, 4 * UCOV_SCREENER_OUTPUTS * (size_t)n));
+  UCOV_TRY(ensure(c, c->f_zero, 8 * UCOV_SCREENER_OUTPUTS));
+  float *zero = as<float>(c->f_zero), *one = zero + UCOV_SCREENER_OUTPUTS;
+  clear_status(c);
+  fill_i32(reinterpret_cast<int32_t *>(zero), 0, UCOV_SCREENER_OUTPUTS, st);
+  fill_i32(reinterpret_cast<int32_t *>(one), 0x3f800000, UCOV_SCREENER_OUTPUTS, st);  // 1.0f
+  launch_col_stats(n, UCOV_SCREENER_FEATURES, feat, in_mean, in_std, st);
+  launch_diag_median(n, cov, scale, st);
+  launch_labels(n, cov, scale, zero, one, as<float>(c->f_lab), c->ds, st);
+  launch_col_stats(n, UCOV_SCREENER_OUTPUTS, as<float>(c->f_lab), out_mean, out_std, st);
+  UCOV_TRY(check_hip(c, "screener statistics"));
+  return sync_status(c, nullptr, "screener statistics (covariance not positive definite)");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Screener file: a 64-byte header, the payload, and an FNV-1a hash of the
+// payload (all little-endian as written by the host).
+struct ScreenerHeader {
+  char magic[8];      // "UCOVSCR1"
+  uint32_t version;   // 1
+  uint32_t n_in, n_hidden, n_out, n_scale;
+  uint32_t has_adam;  // 1: Adam moments follow the statistics
+  int64_t n_params;
+  int64_t step;
+  char pad[64 - 8 - 6 * 4 - 2 * 8];
+};
+static_assert(sizeof(ScreenerHeader) == 64, "screener header is 64 bytes");
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t len) {
+  const unsigned char *b = static_cast<const unsigned char *>(p);
+  for (size_t i = 0; i < len; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct Part {
+  void *dev;
+  size_t bytes;
+};
+
+std::vector<Part> screener_parts(const ucov_screener *s, bool adam) {
+  const size_t P = (size_t)mlp_param_count();
+  std::vector<Part> v = {{s->params, 4 * P},
+                         {s->in_mean, 4 * UCOV_SCREENER_FEATURES},
+                         {s->in_std, 4 * UCOV_SCREENER_FEATURES},
+                         {s->out_mean, 4 * UCOV_SCREENER_OUTPUTS},
+                         {s->out_std, 4 * UCOV_SCREENER_OUTPUTS},
+                         {s->scale, 8 * 9}};
+  if (adam) {
+    v.push_back({s->adam_m, 4 * P});
+    v.push_back({s->adam_v, 4 * P});
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ucov_screener_save(ucov_ctx *c, const char *path, const ucov_screener *s) {
+  if (!c) return UCOV_EINVAL;
+  if (!path || !s || !s->params || !s->in_mean || !s->in_std || !s->scale || !s->out_mean ||
+      !s->out_std || (s->adam_m == nullptr) != (s->adam_v == nullptr) || s->step < 0)
+    return c->fail(UCOV_EINVAL, "bad screener arguments");
+  hipSetDevice(c->device);
+  const bool adam = s->adam_m != nullptr;
+  const std::vector<Part> parts = screener_parts(s, adam);
+  size_t total = 0;
+  for (const Part &p : parts) total += p.bytes;
+  std::vector<unsigned char> payload(total);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "screener save");
+  size_t off = 0;
+  for (const Part &p : parts) {
+    if (hipMemcpy(payload.data() + off, p.dev, p.bytes, hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(c, "screener save (device read)");
+    off += p.bytes;
+  }
+  ScreenerHeader h{};
+  memcpy(h.magic, "UCOVSCR1", 8);
+  h.version = 1;
+  h.n_in = UCOV_SCREENER_FEATURES;
+  h.n_hidden = 256;
+  h.n_out = UCOV_SCREENER_OUTPUTS;
+  h.n_scale = 9;
+  h.has_adam = adam ? 1 : 0;
+  h.n_params = mlp_param_count();
+  h.step = s->step;
+  const uint64_t hash = fnv1a(1469598103934665603ull, payload.data(), payload.size());
+  FILE *f = fopen(path, "wb");
+  if (!f) return c->fail(UCOV_EINVAL, std::string("cannot open ") + path + " for writing");
+  const bool ok = fwrite(&h, sizeof h, 1, f) == 1 &&
+                  fwrite(payload.data(), 1, payload.size(), f) == payload.size() &&
+                  fwrite(&hash, sizeof hash, 1, f) == 1;
+  if (fclose(f) != 0 || !ok) return c->fail(UCOV_EINVAL, std::string("cannot write ") + path);
+  return UCOV_OK;
+}
+
+int ucov_screener_load(ucov_ctx *c, const char *path, ucov_screener *s) {
+  if (!c) return UCOV_EINVAL;
+  if (!path || !s || !s->params || !s->in_mean || !s->in_std || !s->scale || !s->out_mean ||
+      !s->out_std || (s->adam_m == nullptr) != (s->adam_v == nullptr))
+    return c->fail(UCOV_EINVAL, "bad screener arguments");
+  hipSetDevice(c->device);
+  FILE *f = fopen(path, "rb");
+  if (!f) return c->fail(UCOV_EINVAL, std::string("cannot open ") + path);
+  ScreenerHeader h{};
+  if (fread(&h, sizeof h, 1, f) != 1 || memcmp(h.magic, "UCOVSCR1", 8) != 0 || h.version != 1 ||
+      h.n_in != UCOV_SCREENER_FEATURES || h.n_hidden != 256 || h.n_out != UCOV_SCREENER_OUTPUTS ||
+      h.n_scale != 9 || h.n_params != mlp_param_count() || h.has_adam > 1 || h.step < 0) {
+    fclose(f);
+    return c->fail(UCOV_EINVAL, std::string(path) + " is not a screener file of this network");
+  }
+  const bool want_adam = s->adam_m != nullptr;
+  if (want_adam && !h.has_adam) {
+    fclose(f);
+    return c->fail(UCOV_EINVAL, std::string(path) + " holds no Adam moments");
+  }
+  const std::vector<Part> parts = screener_parts(s, h.has_adam != 0);
+  size_t total = 0;
+  for (const Part &p : parts) total += p.bytes;
+  std::vector<unsigned char> payload(total);
+  uint64_t hash = 0;
+  const bool ok = fread(payload.data(), 1, total, f) == total && fread(&hash, sizeof hash, 1, f) == 1;
+  fclose(f);
+  if (!ok || hash != fnv1a(1469598103934665603ull, payload.data(), payload.size()))
+    return c->fail(UCOV_EINVAL, std::string(path) + " is truncated or corrupt");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "screener load");
+  size_t off = 0;
+  for (const Part &p : parts) {
+    const bool skip = !want_adam && (p.dev == s->adam_m || p.dev == s->adam_v);
+    if (!skip && hipMemcpy(p.dev, payload.data() + off, p.bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return check_hip(c, "screener load (device write)");
+    off += p.bytes;
+  }
+  s->step = h.step;
   return UCOV_OK;
 }
 

@@ -157,10 +157,12 @@ void launch_gauge_scenes(const SceneDev &sc, const double *hc, double *q, const 
                          double user_alpha, double *s, double *alpha, DevStatus *ds,
                          hipStream_t st);
 // The paper's gauge (M^+)_cc: q <- G L_F^-T (N x 7) with G = H_c - W V^-1 H_p
-// and F = H_p^T V^-1 H_p = L_F L_F^T (f: kPaperF doubles, F's upper triangle
-// then L_F row-major), alpha <- 1, so that (Z + q q^T)^-1 is the covariance.
+// and F = H_p^T V^-1 H_p = L_F L_F^T (f: paper_gauge_doubles(m) doubles, F's
+// upper triangle, then L_F row-major, then scratch), alpha <- 1, so that (Z + q q^T)^-1 is the covariance.
 // Needs hc from the scene stage.
 constexpr int kPaperF = 28 + 49;
+// Doubles of f for a scene of m points (kPaperF, then per-workgroup sums).
+int64_t paper_gauge_doubles(int64_t m);
 void launch_paper_gauge(const SceneDev &sc, SceneWork &w, double *f, DevStatus *ds,
                         hipStream_t st);
 // mode 0: write Z (both triangles) into out; mode 1: write the lower triangle of
@@ -198,6 +200,11 @@ void mlp_gradient(const float *params, int64_t batch, const float *x, const floa
                   hipStream_t st);
 void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr,
               int64_t step, hipStream_t st);
+// Per column of x (n x cols FP32): mean and standard deviation (n - 1, at
+// least 1e-6); per diagonal entry of n 9 x 9 blocks: D = sqrt(lower median).
+void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *stdv,
+                      hipStream_t st);
+void launch_diag_median(int64_t n, const double *cov, double *D, hipStream_t st);
 void launch_labels(int64_t n, const double *cov, const double *D, const float *mean,
                    const float *stdv, float *lab, DevStatus *ds, hipStream_t st);
 void launch_predicted_cov(int64_t n, const float *y, const double *D, const float *mean,
@@ -292,6 +299,15 @@ void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, d
 // x += x r with the correction on FP32 MFMA.
 void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32, float *d32,
                   hipStream_t st);
+
+// Split-BF16 correction (split_bf16_kernels.hip): x (n x n, leading
+// dimension n, n a multiple of 64) += x r with the product formed from
+// kSplitSlices 8-bit slices of x (per row) and r (per column) on BF16 MFMA,
+// exact FP32 chunk sums accumulated in FP64; scratch: split_bf16_scratch(n)
+// bytes.
+constexpr int kSplitSlices = 3;
+size_t split_bf16_scratch(int64_t n);
+void split_bf16_update(int64_t n, double *x, const double *r, void *scratch, hipStream_t st);
 
 // ---- whole covariance (point_kernels.hip) -----------------------------------
 // cov (N x N, ld ldc) = S X S - [subtract] Q Q^T / alpha from the scaled

@@ -4,11 +4,11 @@ A network predicts each camera's 9x9 covariance from 55 features; cameras
 whose predicted spread (trace of the normalised covariance) exceeds a
 threshold fall back to the exact computation.  Every numeric step runs in the
 library's kernels: features (``ucov_screener_features``), the network's
-forward, gradient and Adam steps (``ucov_mlp_*``) and the label transforms
-(``ucov_screener_labels`` / ``ucov_screener_covariance``).  This module holds
-the training loop and the statistics that standardise inputs and outputs
-(means and deviations over the training set, reduced with torch on the
-device).
+forward, gradient and Adam steps (``ucov_mlp_*``), the statistics that
+standardise inputs and outputs (``ucov_screener_stats``), the label
+transforms (``ucov_screener_labels`` / ``ucov_screener_covariance``) and the
+screener file (``ucov_screener_save`` / ``ucov_screener_load``).  This module
+holds the training loop: the learning-rate schedule and the sample order.
 
 The exact covariances that label the training set come from
 ``Context.camera_covariance`` and remain the reference for the network's error.
@@ -44,6 +44,9 @@ class Screener:
     scale: object       # (9,) float64: per-parameter scale D
     out_mean: object    # (45,) float32
     out_std: object     # (45,) float32
+    adam_m: object = None   # (P,) float32 Adam moments, to resume training
+    adam_v: object = None
+    step: int = 0           # Adam steps taken
 
     def predict(self, ctx: Context, features):
         """Predicted covariances (n, 9, 9) and spreads (n,) for features (n, 55)."""
@@ -57,25 +60,27 @@ class Screener:
         spreads and the fallback mask."""
         feats = ctx.screener_features(scene)
         cov, spread = self.predict(ctx, feats)
-        fallback = spread > threshold
+        # a spread that is not a number (a network output out of range) also
+        # falls back
+        fallback = ~(spread <= threshold)
         if bool(fallback.any()):
             exact, _ = ctx.camera_covariance(scene)
             cov[fallback] = exact[fallback]
         return cov, spread, fallback
 
-    def state_dict(self):
-        return {k: getattr(self, k) for k in ("params", "in_mean", "in_std", "scale",
-                                              "out_mean", "out_std")}
+    def tensors(self):
+        names = ("params", "in_mean", "in_std", "scale", "out_mean", "out_std", "adam_m", "adam_v")
+        return {k: getattr(self, k) for k in names if getattr(self, k) is not None}
 
-    def save(self, path: str):
-        from safetensors.torch import save_file
-        save_file({k: v.contiguous().cpu() for k, v in self.state_dict().items()}, path)
+    def save(self, ctx: Context, path: str):
+        """Write the screener file (``ucov_screener_save``), Adam state included
+        when the screener carries it."""
+        ctx.screener_save(path, self.tensors(), self.step)
 
     @classmethod
-    def load(cls, path: str, device="cuda:0"):
-        from safetensors.torch import load_file
-        d = load_file(path)
-        return cls(**{k: v.to(device) for k, v in d.items()})
+    def load(cls, ctx: Context, path: str, adam: bool = False, device="cuda"):
+        t, step = ctx.screener_load(path, adam=adam, device=device)
+        return cls(step=step, **t)
 
 
 def fit(ctx: Context, features, covs, init, epochs: int = 30, batch: int = 512,
@@ -93,16 +98,9 @@ def fit(ctx: Context, features, covs, init, epochs: int = 30, batch: int = 512,
     P = ctx.mlp_param_count()
     params = torch.as_tensor(np.asarray(init), dtype=torch.float32).to(dev).contiguous()
     assert params.numel() == P, (params.numel(), P)
-    in_mean = features.mean(0).contiguous()
-    in_std = features.std(0).clamp_min(1e-6).contiguous()
-    diag = torch.diagonal(covs, dim1=1, dim2=2)
-    scale = diag.median(0).values.sqrt().contiguous()
-    zeros = torch.zeros(N_OUTPUTS, dtype=torch.float32, device=dev)
-    ones = torch.ones(N_OUTPUTS, dtype=torch.float32, device=dev)
-    raw = ctx.screener_labels(covs.contiguous(), scale, zeros, ones)
-    out_mean = raw.mean(0).contiguous()
-    out_std = raw.std(0).clamp_min(1e-6).contiguous()
-    labels = ctx.screener_labels(covs.contiguous(), scale, out_mean, out_std)
+    covs = covs.contiguous()
+    in_mean, in_std, scale, out_mean, out_std = ctx.screener_stats(features.contiguous(), covs)
+    labels = ctx.screener_labels(covs, scale, out_mean, out_std)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     gen = torch.Generator(device="cpu").manual_seed(seed)
@@ -119,7 +117,7 @@ def fit(ctx: Context, features, covs, init, epochs: int = 30, batch: int = 512,
         history.append(float(losses.mean().item()))
         if log:
             log(f"epoch {ep}: lr {rate:.2e} loss {history[-1]:.4f}")
-    return Screener(params, in_mean, in_std, scale, out_mean, out_std), history
+    return Screener(params, in_mean, in_std, scale, out_mean, out_std, m, v, step - 1), history
 
 
 __all__ = ["Screener", "fit", "training_set", "N_FEATURES", "N_OUTPUTS"]

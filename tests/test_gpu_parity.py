@@ -62,6 +62,20 @@ def test_reduced_camera_matrix(ucov, maker):
     Z = ref["Z"]
     assert np.linalg.norm(z - Z) / np.linalg.norm(Z) < 1e-12
     assert np.array_equal(z, z.T)
+    # per entry, scaled by the diagonal (the parameter types differ by orders
+    # of magnitude, so a whole-matrix norm would hide a wrong rotation or
+    # distortion entry; reordering the oracle's sums moves this by ~4e-15)
+    d = np.sqrt(np.diag(Z))
+    assert np.max(np.abs(z - Z) / np.outer(d, d)) < 1e-12
+    # per 9 x 9 camera-pair block: empty blocks exactly zero, the others to
+    # a relative Frobenius 1e-11 (reordering: ~2e-15)
+    n = s.n_cams
+    zb = z.reshape(n, 9, n, 9).transpose(0, 2, 1, 3)
+    Zb = Z.reshape(n, 9, n, 9).transpose(0, 2, 1, 3)
+    nrm = np.linalg.norm(Zb, axis=(2, 3))
+    assert np.all(zb[nrm == 0] == 0)
+    rel = np.linalg.norm(zb - Zb, axis=(2, 3))[nrm > 0] / nrm[nrm > 0]
+    assert rel.max() < 1e-11, rel.max()
     Hc = ref["Hc"]
     assert np.abs(z @ Hc).max() <= 1e-13 * np.abs(z).max() * np.abs(Hc).max()
 
@@ -199,19 +213,24 @@ def test_covariance_full_medium_scene(ucov):
     assert fro < 1e-6, (fro, scaled)
 
 
-def test_repeat_calls_agree(ucov):
+@pytest.mark.parametrize("gauge", ["camera", "paper"])
+def test_repeat_calls_bitwise_equal(ucov, gauge):
+    """Repeated calls give the same bits: the camera-pair bins are filled in a
+    fixed order and every floating-point sum runs in a fixed order."""
     u, ctx = ucov
-    s = sg.spiral_slab(12, n=40, m=2000)
+    g = u.GAUGE_CAMERA if gauge == "camera" else u.GAUGE_PAPER
+    s = sg.spiral_slab(12, n=140, m=9000)
     d = dev(u, s)
-    a, _ = ctx.camera_covariance(d)
+    a, _ = ctx.camera_covariance(d, gauge=g)
     a = a.cpu().numpy()
     small = dev(u, sg.tiny_circle(1))
-    ctx.camera_covariance(small)  # a smaller call in between reuses the workspace
-    b, _ = ctx.camera_covariance(d)
-    fro, _ = block_errors(b.cpu().numpy(), a)
-    # the Schur scatter sums each camera-pair bin in arrival order, so repeated
-    # calls agree to rounding, not bit for bit
-    assert fro < 1e-9
+    ctx.camera_covariance(small, gauge=g)  # a smaller call in between reuses the workspace
+    for _ in range(3):
+        b, _ = ctx.camera_covariance(d, gauge=g)
+        assert np.array_equal(b.cpu().numpy(), a)
+    z1, _ = ctx.reduced_camera_matrix(d)
+    z2, _ = ctx.reduced_camera_matrix(d)
+    assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
 
 
 def test_errors(ucov):
@@ -251,7 +270,8 @@ def test_errors(ucov):
     assert block_errors(got.cpu().numpy(), ref)[0] < 1e-6
 
 
-@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(5), lambda: sg.spiral_slab(13, n=150, m=15000)])
+@pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(5), lambda: sg.spiral_slab(13, n=150, m=15000),
+                                   lambda: sg.spiral_slab(0)])
 def test_covariance_mixed_precision(ucov, maker):
     """FP32 MFMA initial inverse + Newton-Schulz with FP64 residuals."""
     u, ctx = ucov
@@ -259,10 +279,15 @@ def test_covariance_mixed_precision(ucov, maker):
     print(f"mixed {s.name} n={s.n_cams}", flush=True)
     got, rep = ctx.camera_covariance(dev(u, s), precision=u.FP32_NS)
     ref = oracle_cov(s)["blocks"]
-    fro, scaled = block_errors(got.cpu().numpy(), ref)
+    got = got.cpu().numpy()
+    fro, scaled = block_errors(got, ref)
     print(f"  ns_iters {rep['ns_iters']} residual {rep['ns_residual']:.2e} fro {fro:.2e} scaled {scaled:.2e}")
     assert rep["ns_iters"] >= 1 and rep["ns_residual"] <= 1e-10
     assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    # and against the FP64 GPU path
+    f64, _ = ctx.camera_covariance(dev(u, s))
+    fro64, _ = block_errors(got, f64.cpu().numpy())
+    assert fro64 < 1e-6, fro64
 
 
 @pytest.mark.parametrize("N,kappa", [(576, 1e3), (1161, 1e5)])
