@@ -147,6 +147,31 @@ int ucov_camera_covariance(ucov_ctx *ctx, const ucov_scene *scene,
                            const ucov_options *opt, double *cov_out,
                            ucov_report *rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation as ucov_camera_covariance in UCOV_FP64 (either gauge), with
+ * every work buffer carved from one static device array of
+ * UCOV_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the context's workspace.  The call makes
+ * no hipMalloc, hipFree or other allocating call; the context (made by
+ * ucov_create, which does allocate) supplies its status word, pinned
+ * readback scalars and events.  The caller passes inputs and outputs as for
+ * ucov_camera_covariance.
+ * Limits and errors: UCOV_ENOMEM (nothing is launched past the failing stage,
+ * cov_out unspecified) when the scene's work buffers exceed the scratch --
+ * roughly 8 Np^2 * 1.5 bytes for the dense stage (Np = 9 n_cams rounded up to
+ * 64) plus about 300 bytes per observation and 8 bytes per observation pair,
+ * e.g. scenes up to ~1500 cameras with a few hundred thousand observations;
+ * UCOV_EINVAL for any precision other than UCOV_FP64.
+ * Every call on one GPU shares that GPU's array (whatever context it comes
+ * from) and leaves its contents behind; each call clears what it needs.
+ * Calls that overlap on one GPU (two host threads, or two streams in flight)
+ * race on the array: serialise them. */
+#define UCOV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ucov_camera_covariance_noalloc(ucov_ctx *ctx, const ucov_scene *scene,
+                                   const ucov_options *opt, double *cov_out,
+                                   ucov_report *rep);
+
 /* The whole camera covariance and the covariance of every point (Sec. 5.2:
  * the points are eliminated by block inversion, M = L diag(Z, V) L^T with
  * L = [[I, W V^-1], [0, I]], and their blocks recovered from the camera

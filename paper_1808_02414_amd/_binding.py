@@ -61,7 +61,7 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_mlp_gradient", "ucov_mlp_train", "ucov_screener_labels",
            "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
            "ucov_full_covariance", "ucov_update_covariance", "ucov_tune_dense",
-           "ucov_screener_stats", "ucov_screener_save",
+           "ucov_camera_covariance_noalloc", "ucov_screener_stats", "ucov_screener_save",
            "ucov_screener_load"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
@@ -85,6 +85,9 @@ def load(path: str = LIB_PATH):
         "ucov_destroy": (None, [P]),
         "ucov_camera_covariance": (ctypes.c_int, [P, ctypes.POINTER(Scene), ctypes.POINTER(Options),
                                                   P, ctypes.POINTER(Report)]),
+        "ucov_camera_covariance_noalloc": (ctypes.c_int, [P, ctypes.POINTER(Scene),
+                                                          ctypes.POINTER(Options), P,
+                                                          ctypes.POINTER(Report)]),
         "ucov_camera_covariance_batched": (ctypes.c_int, [P, I32, ctypes.POINTER(Scene),
                                                           ctypes.POINTER(Options), P,
                                                           ctypes.POINTER(D), ctypes.POINTER(Report)]),
@@ -235,6 +238,24 @@ class Context:
         sc = scene.struct()
         rc = self.lib.ucov_camera_covariance(self.h, ctypes.byref(sc), ctypes.byref(opt),
                                              out.data_ptr(), ctypes.byref(rep))
+        self._check(rc, rep)
+        return out, rep.as_dict()
+
+    def camera_covariance_noalloc(self, scene: DeviceScene, out, alpha=0.0,
+                                  gauge=GAUGE_CAMERA):
+        """``camera_covariance`` in FP64 with the library's static scratch
+        instead of its workspace (no device allocation in the call); ``out``
+        is the caller's (n, 9, 9) float64 device tensor.  Returns out and the
+        report."""
+        torch = self.torch
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+        assert out.shape == (scene.n_cams, 9, 9)
+        opt = Options(FP64, 0, 0.0, alpha, gauge)
+        rep = Report()
+        self._stream()
+        sc = scene.struct()
+        rc = self.lib.ucov_camera_covariance_noalloc(self.h, ctypes.byref(sc), ctypes.byref(opt),
+                                                     out.data_ptr(), ctypes.byref(rep))
         self._check(rc, rep)
         return out, rep.as_dict()
 

@@ -6,6 +6,7 @@
 #include <string>
 #include <unordered_map>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "ucov_internal.h"
@@ -19,6 +20,16 @@ struct Buf {
   void *p = nullptr;
   size_t cap = 0;
 };
+
+}  // namespace
+
+// Static scratch of the allocation-free entry point (one array on every GPU
+// the library runs on, held until the process ends).  Host code never uses
+// its name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device when a context is created.
+static __device__ __align__(256) unsigned char scratch[UCOV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
 
 const char *code_name(int code) {
   switch (code) {
@@ -50,6 +61,28 @@ enum EvMark {
   kEvTune1,
   kEvCount
 };
+
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// This device's address of the static scratch; the device must be current.
+int scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return UCOV_EDEVICE;
+  if (!g_scratch[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      hipGetLastError();
+      return UCOV_EDEVICE;
+    }
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return UCOV_OK;
+}
+
+constexpr int kArenaSlots = 64;
 
 }  // namespace
 
@@ -90,6 +123,18 @@ struct ucov_ctx {
   // sub-reconstructions: index maps, the gathered sub-scenes and their blocks
   Buf sr_idx, sr_cams, sr_pts, sr_info, sr_cand, sr_chosen;
 
+  // Allocation-free calls: while `on`, ensure() carves every buffer from
+  // this device's static scratch (base, cap) and remembers the context's own
+  // buffer, which is put back when the call ends.
+  struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    bool on = false;
+    int n_saved = 0;
+    Buf *who[kArenaSlots] = {};
+    Buf was[kArenaSlots] = {};
+  } arena;
+
   int fail(int code, const std::string &msg) {
     last_error = std::string(code_name(code)) + ": " + msg;
     return code;
@@ -100,6 +145,27 @@ namespace {
 
 int ensure(ucov_ctx *c, Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 8;
+  if (c->arena.on) {
+    auto &a = c->arena;
+    int k = 0;
+    while (k < a.n_saved && a.who[k] != &b) ++k;
+    if (k < a.n_saved && b.cap >= bytes) return UCOV_OK;  // carved earlier in this call
+    const size_t off = (a.off + 255) & ~(size_t)255;
+    if (off > a.cap || bytes > a.cap - off)
+      return c->fail(UCOV_ENOMEM, "the scene needs more than the " +
+                                      std::to_string((size_t)UCOV_NOALLOC_SCRATCH_BYTES) +
+                                      " bytes of static scratch of the allocation-free call");
+    if (k == a.n_saved) {
+      if (a.n_saved == kArenaSlots) return c->fail(UCOV_EDEVICE, "internal: scratch table full");
+      a.who[k] = &b;
+      a.was[k] = b;
+      ++a.n_saved;
+    }
+    b.p = a.base + off;
+    b.cap = bytes;
+    a.off = off + bytes;
+    return UCOV_OK;
+  }
   if (b.cap >= bytes) return UCOV_OK;
   if (b.p) hipFree(b.p);
   b.p = nullptr;
@@ -116,6 +182,22 @@ template <class T>
 T *as(Buf &b) {
   return reinterpret_cast<T *>(b.p);
 }
+
+// Carves the buffers of one call from the static scratch; the context's own
+// buffers are put back when the scope ends.
+struct ArenaScope {
+  ucov_ctx *c;
+  explicit ArenaScope(ucov_ctx *ctx) : c(ctx) {
+    c->arena.on = true;
+    c->arena.off = 0;
+    c->arena.n_saved = 0;
+  }
+  ~ArenaScope() {
+    for (int k = c->arena.n_saved - 1; k >= 0; --k) *c->arena.who[k] = c->arena.was[k];
+    c->arena.n_saved = 0;
+    c->arena.on = false;
+  }
+};
 
 #define UCOV_TRY(expr)          \
   do {                          \
@@ -465,6 +547,13 @@ int ucov_create(ucov_ctx **ctx, int device) {
     ucov_destroy(c);
     return UCOV_ENOMEM;
   }
+  void *sp = nullptr;
+  if (scratch_address(device, &sp) != UCOV_OK) {
+    ucov_destroy(c);
+    return UCOV_EDEVICE;
+  }
+  c->arena.base = static_cast<char *>(sp);
+  c->arena.cap = UCOV_NOALLOC_SCRATCH_BYTES;
   *ctx = c;
   return UCOV_OK;
 }
@@ -602,6 +691,18 @@ int ucov_camera_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
   return camera_covariance_impl(c, scene, opt, cov_out, rep);
 }
 
+// The same path with every buffer carved from the static scratch: no device
+// or pinned allocation happens in this call (the status word, the pinned
+// readback scalars and the events were made by ucov_create).
+int ucov_camera_covariance_noalloc(ucov_ctx *c, const ucov_scene *scene,
+                                   const ucov_options *opt, double *cov_out, ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  if (opt && opt->precision != UCOV_FP64)
+    return c->fail(UCOV_EINVAL, "the allocation-free call supports UCOV_FP64 only");
+  if (!c->arena.base) return c->fail(UCOV_EDEVICE, "no static scratch on this device");
+  ArenaScope scope(c);
+  return camera_covariance_impl(c, scene, opt, cov_out, rep);
+}
 
 int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const double *q,
                      const ucov_options *opt, double *cov_out, ucov_report *rep) {
