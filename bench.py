@@ -190,8 +190,11 @@ def golden_c3():
 def run_single(args, ucov, torch, np, scene):
     ctx = ucov.Context(0)
     dev = ucov.DeviceScene.from_scene(scene, "cuda:0")
-    prec = {"fp64": ucov.FP64, "fp32ns": ucov.FP32_NS}[args.precision]
-    if prec == ucov.FP64 and not args.no_tune:
+    prec = {"fp64": ucov.FP64, "fp32ns": ucov.FP32_NS, "bf16x": ucov.BF16X_NS}[args.precision]
+    if args.threshold is not None:
+        ctx.set_dense_threshold(9 * scene.n_cams, args.threshold)
+        args.tuned_threshold = args.threshold
+    elif prec == ucov.FP64 and not args.no_tune:
         # the library's tile-schedule tuning for this size, before the timed steps
         args.tuned_threshold = ctx.tune_dense(9 * scene.n_cams)[0]
     out = torch.empty((scene.n_cams, 9, 9), dtype=torch.float64, device="cuda:0")
@@ -210,12 +213,30 @@ def run_single(args, ucov, torch, np, scene):
 def run_batch(args, ucov, torch, np, scenes):
     ctx = ucov.Context(0)
     devs = [ucov.DeviceScene.from_scene(s, "cuda:0") for s in scenes]
+    if not args.no_tune:
+        # the library's batched tile-schedule tuning, before the timed steps
+        args.tuned_threshold = ctx.tune_batched([9 * s.n_cams for s in scenes])[0]
     n = sum(s.n_cams for s in scenes)
     out = torch.empty((n, 9, 9), dtype=torch.float64, device="cuda:0")
     for _ in range(args.warmup):
-        ctx.camera_covariance_batched(devs, out=out)
+        _, _, rep = ctx.camera_covariance_batched(devs, out=out)
     torch.cuda.synchronize()
     reps = []
+    if args.graph:
+        # the batch recorded once into a graph and replayed; the stage times
+        # come from one eager call
+        _, _, eager = ctx.camera_covariance_batched(devs, out=out)
+        b = ctx.batch(devs, out=out)
+        b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep = b.run()
+            reps.append(dict(eager, ms_total=rep["ms_total"]))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        return dt, reps, [9 * s.n_cams for s in scenes], out
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, _, rep = ctx.camera_covariance_batched(devs, out=out)
@@ -231,10 +252,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["spiral500", "batch256", "clustered3000"],
                     default="clustered3000")
-    ap.add_argument("--precision", choices=["fp64", "fp32ns"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32ns", "bf16x"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="batch256: record the batch once into a graph and time its replays")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default dense tile schedule instead of tuning it for the size")
+    ap.add_argument("--threshold", type=int, default=None,
+                    help="use this tile-schedule threshold instead of tuning (e.g. for a profile)")
     ap.add_argument("--n-cams", type=int, default=500)
     ap.add_argument("--n-pts", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -306,9 +331,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp32ns": "f32+f64", "bf16x": "bf16x3+f32+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": workload, "precision": args.precision},
+        "config": {"workload": workload, "precision": args.precision,
+                   "launch": "graph replay" if args.graph else "eager"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      # the counters were taken with the default tile schedule
@@ -324,7 +350,7 @@ def main():
     }
     if getattr(args, "tuned_threshold", None) is not None:
         line["dense_tile_threshold"] = args.tuned_threshold
-    if args.precision == "fp32ns":
+    if args.precision != "fp64":
         line["ns_iters"] = int(reps[-1]["ns_iters"])
         line["ns_residual"] = float(reps[-1]["ns_residual"])
     # the timed call's output against the oracle

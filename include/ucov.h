@@ -74,6 +74,11 @@ extern "C" {
                              X <- X + X (I - A_s X): residual in FP64, correction on FP32
                              MFMA; UCOV_ENOCONV if the FP32 factorisation fails or the
                              tolerance is not reached */
+#define UCOV_BF16X_NS 2   /* as UCOV_FP32_NS, with each correction X R formed from 8-bit
+                             slices of X (per row) and R (per column) on BF16 MFMA: the
+                             slice products sum exactly in FP32 over K chunks and the
+                             chunks in FP64, so the correction's error (~2^-24 relative to
+                             the row and column bounds) does not grow with N */
 
 typedef struct ucov_ctx ucov_ctx;
 
@@ -103,8 +108,8 @@ typedef struct {
 #define UCOV_GAUGE_PAPER  1
 
 typedef struct {
-  int32_t precision;  /* UCOV_FP64 or UCOV_FP32_NS */
-  int32_t max_iter;   /* Newton-Schulz iterations allowed (UCOV_FP32_NS); 0 = default 6 */
+  int32_t precision;  /* UCOV_FP64, UCOV_FP32_NS or UCOV_BF16X_NS */
+  int32_t max_iter;   /* Newton-Schulz iterations allowed (mixed precision); 0 = default 6 */
   double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-10 */
   double alpha;       /* gauge weight a; 0 = balanced automatic choice (UCOV_GAUGE_CAMERA only) */
   int32_t gauge;      /* UCOV_GAUGE_CAMERA (default) or UCOV_GAUGE_PAPER */
@@ -126,6 +131,7 @@ typedef struct {
   float ms_inverse;    /* dense factorisation and inversion (step a4) */
   float ms_extract;    /* covariance block extraction (step a4) */
   int32_t bad_scene;   /* batched calls: scene of the failure, -1 if none */
+  float ms_total;      /* the whole call on the stream, HIP events */
 } ucov_report;
 
 /* Create a context on HIP device `device`.  Returns UCOV_EDEVICE if the
@@ -237,6 +243,22 @@ int ucov_update_covariance(ucov_ctx *ctx, const ucov_scene *scene, int64_t n_new
  * stage time.  Allocates the dense workspace for that size. */
 int ucov_tune_dense(ucov_ctx *ctx, int64_t n, int64_t *threshold, float *ms);
 
+/* Tune the batched dense stage (ucov_camera_covariance_batched) for scenes
+ * whose matrices have sizes n[0..count) (N = 9 n_cams per scene, in the
+ * batch's scene order): each launch of the batched recursion serves one node
+ * for all scenes that reach it, and launches with fewer 64 x 64 tiles in all
+ * than the threshold run on split 32 x 32 tiles.  Every candidate is timed on
+ * synthetic positive definite matrices of those sizes (best of three) and the
+ * fastest is kept in this context for batches of exactly these sizes (an
+ * untuned batch runs every product on 64 x 64 tiles).  threshold, ms: HOST,
+ * or NULL.  Results are unchanged by the choice up to rounding order. */
+int ucov_tune_batched(ucov_ctx *ctx, int32_t count, const int64_t *n, int64_t *threshold,
+                      float *ms);
+
+/* Set the tile-schedule threshold of ucov_tune_dense for matrices of size n
+ * without timing (e.g. one a previous tuning chose), in this context. */
+int ucov_set_dense_threshold(ucov_ctx *ctx, int64_t n, int64_t threshold);
+
 /* Covariance blocks of several independent scenes in one call: the
  * sub-reconstructions of Sec. 6, each evaluated exactly on its own gauge (a
  * camera's covariance from a sub-reconstruction around it bounds the one from
@@ -257,6 +279,26 @@ int ucov_tune_dense(ucov_ctx *ctx, int64_t n, int64_t *threshold, float *ms);
 int ucov_camera_covariance_batched(ucov_ctx *ctx, int32_t n_scenes, const ucov_scene *scenes,
                                    const ucov_options *opt, double *cov_out, double *alphas,
                                    ucov_report *rep);
+
+/* A batch of independent scenes (as for ucov_camera_covariance_batched)
+ * recorded once and replayed: ucov_batch_create solves the batch eagerly in
+ * a private workspace (validating every scene, sizing every buffer, building
+ * the dense plan; cov_out then holds the blocks), then records the same
+ * launches, with no host round trip, into a HIP graph.  ucov_batch_run
+ * replays the graph on the context's current stream and checks the status;
+ * cov_out is rewritten.  Between runs the scenes' parameter values
+ * (cams, pts, obs_info) may change, their sizes and index arrays may not: a
+ * run whose camera-pair structure grew beyond the recorded one returns
+ * UCOV_EINVAL without writing out of its buffers.  The scenes' device arrays
+ * and cov_out must outlive the batch.  rep of a run: alpha, n_pairs,
+ * bad_scene / bad_index on failure, ms_total (the graph's time); the stage
+ * times are 0.  The batch holds its own device workspace (as much as the
+ * batched call) until ucov_batch_destroy; runs of one batch must not overlap. */
+typedef struct ucov_batch ucov_batch;
+int ucov_batch_create(ucov_ctx *ctx, int32_t n_scenes, const ucov_scene *scenes,
+                      const ucov_options *opt, double *cov_out, ucov_batch **batch);
+int ucov_batch_run(ucov_batch *batch, ucov_report *rep);
+void ucov_batch_destroy(ucov_batch *batch);
 
 /* Sub-reconstructions (Sec. 6): each camera's covariance evaluated from
  * sub-reconstructions around it instead of the whole scene.  A sub-
@@ -307,6 +349,13 @@ int ucov_gauge_basis(ucov_ctx *ctx, const ucov_scene *scene, double *hc, double 
 int ucov_pinv_blocks(ucov_ctx *ctx, int64_t n, const double *z, int64_t ldz,
                      const double *q, const ucov_options *opt, double *cov_out,
                      ucov_report *rep);
+
+/* Step a4's split-BF16 product alone (the correction of UCOV_BF16X_NS):
+ * x += x r for n x n column-major float64 x and r (leading dimension n, n a
+ * positive multiple of 64).  Entry (m, c) of the product carries at most
+ * about 2^(e_m + f_c - 24) n error, 2^e_m and 2^f_c the powers of two that
+ * bound row m of x and column c of r. */
+int ucov_split_bf16_update(ucov_ctx *ctx, int64_t n, double *x, const double *r);
 
 /* ---- learned screener -----------------------------------------------------
  * A small network that predicts a camera's 9x9 covariance from 55 cheap

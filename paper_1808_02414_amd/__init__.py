@@ -5,5 +5,5 @@ The computation runs in the hand-written gfx950 HIP kernels of
 package is its thin Python binding (device memory and streams come from
 torch).  See ``_binding.Context`` for the entry points.
 """
-from ._binding import (FP32_NS, FP64, GAUGE_CAMERA, GAUGE_PAPER, Context, DeviceScene, UcovError,  # noqa: F401
+from ._binding import (BF16X_NS, FP32_NS, FP64, GAUGE_CAMERA, GAUGE_PAPER, Context, DeviceScene, UcovError,  # noqa: F401
                        EXPORTS, LIB_PATH, load)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libucov.so")
 OK, EINVAL, EPOINT, EGAUGE, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
 ERROR_NAMES = {EINVAL: "EINVAL", EPOINT: "EPOINT", EGAUGE: "EGAUGE", ENOCONV: "ENOCONV",
                EDEVICE: "EDEVICE", ENOMEM: "ENOMEM"}
-FP64, FP32_NS = 0, 1
+FP64, FP32_NS, BF16X_NS = 0, 1, 2
 GAUGE_CAMERA, GAUGE_PAPER = 0, 1
 
 
@@ -47,7 +47,8 @@ class Report(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64),
                 ("ms_structure", ctypes.c_float), ("ms_schur", ctypes.c_float),
                 ("ms_gauge", ctypes.c_float), ("ms_inverse", ctypes.c_float),
-                ("ms_extract", ctypes.c_float), ("bad_scene", ctypes.c_int32)]
+                ("ms_extract", ctypes.c_float), ("bad_scene", ctypes.c_int32),
+                ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -62,7 +63,8 @@ EXPORTS = ["ucov_create", "ucov_set_stream", "ucov_destroy", "ucov_camera_covari
            "ucov_screener_covariance", "ucov_plan_check", "ucov_subrecon_covariance",
            "ucov_full_covariance", "ucov_update_covariance", "ucov_tune_dense",
            "ucov_camera_covariance_noalloc", "ucov_screener_stats", "ucov_screener_save",
-           "ucov_screener_load"]
+           "ucov_screener_load", "ucov_split_bf16_update", "ucov_set_dense_threshold",
+           "ucov_tune_batched", "ucov_batch_create", "ucov_batch_run", "ucov_batch_destroy"]
 
 N_FEATURES, N_OUTPUTS = 55, 45
 
@@ -111,6 +113,14 @@ def load(path: str = LIB_PATH):
         "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
         "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
         "ucov_plan_check": (ctypes.c_int, [P, I32, P]),
+        "ucov_split_bf16_update": (ctypes.c_int, [P, I64, P, P]),
+        "ucov_set_dense_threshold": (ctypes.c_int, [P, I64, I64]),
+        "ucov_tune_batched": (ctypes.c_int, [P, I32, P, ctypes.POINTER(I64),
+                                             ctypes.POINTER(ctypes.c_float)]),
+        "ucov_batch_create": (ctypes.c_int, [P, I32, ctypes.POINTER(Scene), ctypes.POINTER(Options),
+                                             P, ctypes.POINTER(P)]),
+        "ucov_batch_run": (ctypes.c_int, [P, ctypes.POINTER(Report)]),
+        "ucov_batch_destroy": (None, [P]),
         "ucov_screener_stats": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P]),
         "ucov_screener_save": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(ScreenerStruct)]),
         "ucov_screener_load": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.POINTER(ScreenerStruct)]),
@@ -317,6 +327,21 @@ class Context:
         self._check(self.lib.ucov_tune_dense(self.h, int(n), ctypes.byref(th), ctypes.byref(ms)))
         return int(th.value), float(ms.value)
 
+    def tune_batched(self, sizes):
+        """Pick the batched dense stage's tile schedule for scenes of matrix
+        sizes ``sizes`` (9 per camera, scene order); returns (threshold, ms)."""
+        arr = (ctypes.c_int64 * len(sizes))(*[int(x) for x in sizes])
+        th = ctypes.c_int64()
+        ms = ctypes.c_float()
+        self._stream()
+        self._check(self.lib.ucov_tune_batched(self.h, len(sizes), arr, ctypes.byref(th),
+                                               ctypes.byref(ms)))
+        return int(th.value), float(ms.value)
+
+    def set_dense_threshold(self, n: int, threshold: int):
+        """Use a known tile-schedule threshold for matrices of size n."""
+        self._check(self.lib.ucov_set_dense_threshold(self.h, int(n), int(threshold)))
+
     def camera_covariance_batched(self, scenes, alpha=0.0, out=None):
         """Covariance blocks of independent scenes in one call: a list of
         (n_s, 9, 9) views into one (sum n_s, 9, 9) device tensor, the per-scene
@@ -339,6 +364,11 @@ class Context:
             views.append(out[o:o + n])
             o += n
         return views, list(alphas), rep.as_dict()
+
+    def batch(self, scenes, alpha=0.0, out=None):
+        """A batch recorded once (eager solve, then a captured graph) and
+        replayed by ``Batch.run()``; its blocks are written to ``out``."""
+        return Batch(self, scenes, alpha, out)
 
     def subrecon_covariance(self, scene: DeviceScene, groups, alpha=0.0):
         """Per-camera blocks from sub-reconstructions: groups is an
@@ -405,6 +435,18 @@ class Context:
         self._check(self.lib.ucov_pinv_blocks(self.h, N, zc.data_ptr(), N, qc.data_ptr(),
                                               ctypes.byref(opt), out.data_ptr(), ctypes.byref(rep)), rep)
         return out, rep.as_dict()
+
+    def split_bf16_update(self, x, r):
+        """x += x r in place (n x n float64 device tensors, n a multiple of 64;
+        row-major tensors are passed as their column-major transposes, so the
+        call computes x^T += x^T r^T on the stored arrays)."""
+        torch = self.torch
+        n = x.shape[0]
+        assert x.shape == (n, n) and r.shape == (n, n)
+        self._stream()
+        self._check(self.lib.ucov_split_bf16_update(self.h, n, self._dev(x, torch.float64),
+                                                    self._dev(r, torch.float64)))
+        return x
 
     # ---- learned screener ---------------------------------------------------
 
@@ -546,3 +588,50 @@ class Context:
             self._dev(out_mean, torch.float32), self._dev(out_std, torch.float32),
             cov.data_ptr(), spread.data_ptr()))
         return cov, spread
+
+
+class Batch:
+    """ucov_batch_create / ucov_batch_run / ucov_batch_destroy: the scenes'
+    tensors and the output stay referenced while the batch lives."""
+
+    def __init__(self, ctx: Context, scenes, alpha=0.0, out=None):
+        torch = ctx.torch
+        self.ctx = ctx
+        self.scenes = list(scenes)
+        total = sum(s.n_cams for s in self.scenes)
+        if out is None:
+            out = torch.empty((total, 9, 9), dtype=torch.float64, device=self.scenes[0].cams.device)
+        assert out.shape == (total, 9, 9) and out.is_contiguous() and out.dtype == torch.float64
+        self.out = out
+        self._arr = (Scene * len(self.scenes))(*[s.struct() for s in self.scenes])
+        opt = Options(FP64, 0, 0.0, alpha, GAUGE_CAMERA)
+        h = ctypes.c_void_p()
+        ctx._stream()
+        ctx._check(ctx.lib.ucov_batch_create(ctx.h, len(self.scenes), self._arr, ctypes.byref(opt),
+                                             out.data_ptr(), ctypes.byref(h)))
+        self.h = h
+
+    def views(self):
+        out, o = [], 0
+        for s in self.scenes:
+            out.append(self.out[o:o + s.n_cams])
+            o += s.n_cams
+        return out
+
+    def run(self):
+        """Replay on the current stream; returns the report."""
+        rep = Report()
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.ucov_batch_run(self.h, ctypes.byref(rep)), rep)
+        return rep.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ucov_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

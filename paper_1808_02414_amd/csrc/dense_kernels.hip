@@ -300,7 +300,11 @@ __global__ __launch_bounds__(64 * S) void k_gemm32s_pair(GemmArgs<T> s, GemmArgs
   }
 }
 
-// One product; grid (M/64, N/64), tile rows fastest.
+// One product; grid (M/64, N/64), tile rows fastest.  (A die-aware order --
+// each of the 8 dies given a contiguous range of a grouped tile order, so
+// that the workgroups running side by side on one die form 8 x 8 tile
+// blocks -- was measured slower on the large scene: dense stage 342 against
+// 264 ms.)
 template <typename T, bool AT, bool BT, bool LOWER>
 __global__ __launch_bounds__(256) void k_gemm64(GemmArgs<T> g) {
   gemm_tile<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
@@ -669,6 +673,32 @@ __global__ __launch_bounds__(256) void k_gemm64_pair_b(const GemmArgs<T> *stab,
   }
 }
 
+// Batched split 32 x 32 tiles: blockIdx.z picks the product of a scene, the
+// K range of a tile is dealt out to S waves (see gemm_tile32_split).
+template <typename T, bool AT, bool BT, bool LOWER, int S>
+__global__ __launch_bounds__(64 * S) void k_gemm32s_b(const GemmArgs<T> *tab) {
+  __shared__ T sh[S * kStage32];
+  const GemmArgs<T> g = tab[blockIdx.z];
+  if ((int64_t)blockIdx.x * 32 >= g.M || (int64_t)blockIdx.y * 32 >= g.N) return;
+  gemm_tile32_split<T, AT, BT, LOWER, S>(g, blockIdx.x, blockIdx.y, sh);
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(64 * S) void k_gemm32s_pair_b(const GemmArgs<T> *stab,
+                                                          const GemmArgs<T> *ttab) {
+  __shared__ T sh[S * kStage32];
+  const GemmArgs<T> sg = stab[blockIdx.z];
+  const int ms = (int)(sg.M / 32), nblk_s = ms * ms, b = blockIdx.x;
+  if (b < nblk_s) {
+    gemm_tile32_split<T, false, true, true, S>(sg, b % ms, b / ms, sh);
+  } else {
+    const GemmArgs<T> tg = ttab[blockIdx.z];
+    const int mt = (int)(tg.M / 32), bb = b - nblk_s;
+    if (bb >= mt * (int)(tg.N / 32)) return;
+    gemm_tile32_split<T, false, false, false, S>(tg, bb % mt, bb / mt, sh);
+  }
+}
+
 // Strict upper triangle of an n x n matrix (n a multiple of 32) set from its
 // lower triangle through 32 x 32 LDS tiles: workgroup (tm, tn), tm >= tn,
 // reads tile (tm, tn) with coalesced column loads and writes its transpose
@@ -763,11 +793,9 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// out[0] += sum of squares of the n x n matrix (one partial per workgroup,
-// accumulated with an FP64 atomic add; rounding order does not matter for a
-// convergence test)
+// part[c] = sum of squares of column c of the n x n matrix
 __global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *a, int64_t lda,
-                                              double *out) {
+                                              double *part_out) {
   const int64_t c = blockIdx.x;
   double s = 0.0;
   for (int64_t r = threadIdx.x; r < n; r += 256) {
@@ -778,7 +806,22 @@ __global__ __launch_bounds__(256) void k_sumsq(int64_t n, const double *a, int64
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+  if (threadIdx.x == 0) part_out[c] = part[0] + part[1] + part[2] + part[3];
+}
+
+// out[0] = sum of part[0..n) in a fixed order (the same bits on every call,
+// so the stopping decision of the refinement is reproducible)
+__global__ __launch_bounds__(256) void k_sum_parts(int64_t n, const double *part, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // One workgroup per camera: (A_s^-1)_ii = sum over rows r >= 9i of the outer
@@ -1016,12 +1059,15 @@ void recurse(T *A, int64_t lda, int64_t o, int64_t n, T *tmp, DevStatus *ds, hip
 namespace {
 
 enum PlanKind { kPlanLeaf64 = 0, kPlanLeaf128 = 1, kPlanGemmT = 2, kPlanPair = 3, kPlanFinal = 4 };
+// Tile shape of a product launch: 64 x 64, or split 32 x 32 over 4 or 8 waves.
+enum PlanTiles { kTiles64 = 0, kTiles32x4 = 1, kTiles32x8 = 2 };
 
 struct PlanLaunch {
   int kind;
   int64_t first, second;  // table offsets (pair: Schur and T2 entries)
   int count;
   unsigned gx, gy;
+  int tiles = kTiles64;   // products: PlanTiles
 };
 
 struct WalkMat {
@@ -1032,6 +1078,7 @@ struct WalkMat {
 template <typename T>
 struct PlanBuilder {
   const SpdMat *mats;
+  int64_t small = 0;  // launches with fewer 64 x 64 tiles (all scenes) use 32 x 32 tiles
   std::vector<GemmArgs<T>> gemms;
   std::vector<int> gemm_owner;  // matrix of each product (for the bounds check)
   std::vector<int> gemm_bt;     // 1 when B is used transposed
@@ -1084,8 +1131,22 @@ struct PlanBuilder {
     int64_t mmax = 0;
     for (int64_t x : m) mmax = std::max(mmax, x);
     const unsigned mt = (unsigned)(mmax / 64), nt1 = (unsigned)(n1 / 64);
+    // tile shape of this node's launches from their total 64 x 64 tile count
+    int64_t t_gemm = 0, t_pair = 0;
+    for (int64_t x : m) {
+      t_gemm += (x / 64) * (n1 / 64);
+      t_pair += (x / 64) * (x / 64 + 1) / 2 + (x / 64) * (n1 / 64);
+    }
+    auto shape = [&](PlanLaunch &L, int64_t tiles64, bool pair) {
+      if (tiles64 >= small) return;
+      L.tiles = 4 * tiles64 < 256 ? kTiles32x8 : kTiles32x4;
+      const unsigned m32 = (unsigned)(mmax / 32), n32 = (unsigned)(n1 / 32);
+      L.gx = pair ? m32 * m32 + m32 * n32 : m32;
+      L.gy = pair ? 1 : n32;
+    };
     // T = A21 L11^-T
     PlanLaunch LT{kPlanGemmT, (int64_t)gemms.size(), 0, (int)F.size(), mt, nt1};
+    shape(LT, t_gemm, false);
     for (size_t q = 0; q < F.size(); ++q) {
       const SpdMat &M = mats[F[q]];
       T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
@@ -1097,6 +1158,7 @@ struct PlanBuilder {
     // A22 -= T T^T  and  T2 = T L11^-1
     PlanLaunch LP{kPlanPair, (int64_t)gemms.size(), (int64_t)(gemms.size() + F.size()),
                   (int)F.size(), mt * mt + mt * nt1, 1};
+    shape(LP, t_pair, true);
     for (size_t q = 0; q < F.size(); ++q) {
       const SpdMat &M = mats[F[q]];
       T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
@@ -1115,6 +1177,7 @@ struct PlanBuilder {
     walk(o + n1, n2, F, offR);
     // A21 = -L22^-1 T2
     PlanLaunch LF{kPlanFinal, (int64_t)gemms.size(), 0, (int)F.size(), mt, nt1};
+    shape(LF, t_gemm, false);
     for (size_t q = 0; q < F.size(); ++q) {
       const SpdMat &M = mats[F[q]];
       T *A = static_cast<T *>(M.A), *T2 = static_cast<T *>(M.tmp) + (offR[q] - m[q] * n1);
@@ -1162,11 +1225,12 @@ bool plan_in_bounds(const PlanBuilder<T> &b, const SpdMat *mats, std::string *wh
 }
 
 template <typename T>
-PlanBuilder<T> make_plan(const SpdMat *mats, int count) {
+PlanBuilder<T> make_plan(const SpdMat *mats, int count, int64_t small = 0) {
   int64_t P = 0;
   for (int s = 0; s < count; ++s) P = std::max(P, mats[s].np);
   PlanBuilder<T> b;
   b.mats = mats;
+  b.small = small;
   b.need.assign(count, 0);
   std::vector<int> act(count);
   for (int s = 0; s < count; ++s) act[s] = s;
@@ -1212,6 +1276,7 @@ namespace {
 
 struct SpdPlan {
   std::vector<SpdMat> key;
+  int64_t key_small = -1;
   std::vector<GemmArgs<double>> gemms;
   std::vector<LeafArg<double>> leaves;
   std::vector<PlanLaunch> launches;
@@ -1248,9 +1313,9 @@ static bool same_mats(const std::vector<SpdMat> &a, const SpdMat *b, int count) 
   return true;
 }
 
-int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st) {
-  if (same_mats(p->key, mats, count)) return 0;
-  PlanBuilder<double> b = make_plan<double>(mats, count);
+int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st, int64_t small) {
+  if (same_mats(p->key, mats, count) && p->key_small == small) return 0;
+  PlanBuilder<double> b = make_plan<double>(mats, count, small);
   if (!plan_in_bounds(b, mats, nullptr)) return -2;
   const size_t bytes = sizeof(GemmArgs<double>) * b.gemms.size() +
                        sizeof(LeafArg<double>) * b.leaves.size() + 64;
@@ -1274,8 +1339,11 @@ int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st) {
     return -1;
   if (hipStreamSynchronize(st) != hipSuccess) return -1;
   p->key.assign(mats, mats + count);
+  p->key_small = small;
   return 0;
 }
+
+int64_t spd_plan_launches(const SpdPlan *p) { return (int64_t)p->launches.size(); }
 
 void spd_plan_run(const SpdPlan *p, hipStream_t st) {
   const GemmArgs<double> *g = static_cast<const GemmArgs<double> *>(p->dev);
@@ -1293,16 +1361,37 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                            lv + L.first);
         break;
       case kPlanGemmT:
-        hipLaunchKernelGGL((k_gemm64_b<double, false, true, false>), dim3(L.gx, L.gy, L.count),
-                           dim3(256), 0, st, g + L.first);
+        if (L.tiles == kTiles32x8)
+          hipLaunchKernelGGL((k_gemm32s_b<double, false, true, false, 8>),
+                             dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
+        else if (L.tiles == kTiles32x4)
+          hipLaunchKernelGGL((k_gemm32s_b<double, false, true, false, 4>),
+                             dim3(L.gx, L.gy, L.count), dim3(256), 0, st, g + L.first);
+        else
+          hipLaunchKernelGGL((k_gemm64_b<double, false, true, false>), dim3(L.gx, L.gy, L.count),
+                             dim3(256), 0, st, g + L.first);
         break;
       case kPlanPair:
-        hipLaunchKernelGGL((k_gemm64_pair_b<double>), dim3(L.gx, 1, L.count), dim3(256), 0, st,
-                           g + L.first, g + L.second);
+        if (L.tiles == kTiles32x8)
+          hipLaunchKernelGGL((k_gemm32s_pair_b<double, 8>), dim3(L.gx, 1, L.count), dim3(512), 0,
+                             st, g + L.first, g + L.second);
+        else if (L.tiles == kTiles32x4)
+          hipLaunchKernelGGL((k_gemm32s_pair_b<double, 4>), dim3(L.gx, 1, L.count), dim3(256), 0,
+                             st, g + L.first, g + L.second);
+        else
+          hipLaunchKernelGGL((k_gemm64_pair_b<double>), dim3(L.gx, 1, L.count), dim3(256), 0, st,
+                             g + L.first, g + L.second);
         break;
       case kPlanFinal:
-        hipLaunchKernelGGL((k_gemm64_b<double, false, false, false>), dim3(L.gx, L.gy, L.count),
-                           dim3(256), 0, st, g + L.first);
+        if (L.tiles == kTiles32x8)
+          hipLaunchKernelGGL((k_gemm32s_b<double, false, false, false, 8>),
+                             dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
+        else if (L.tiles == kTiles32x4)
+          hipLaunchKernelGGL((k_gemm32s_b<double, false, false, false, 4>),
+                             dim3(L.gx, L.gy, L.count), dim3(256), 0, st, g + L.first);
+        else
+          hipLaunchKernelGGL((k_gemm64_b<double, false, false, false>), dim3(L.gx, L.gy, L.count),
+                             dim3(256), 0, st, g + L.first);
         break;
     }
   }
@@ -1409,10 +1498,12 @@ void mixed_prepare(int64_t Np, double *a, int64_t lda, const float *x32, double 
 
 void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, double *r,
                     double *sumsq, hipStream_t st) {
-  // R = I - A X in FP64, and |R|_F^2 accumulated into sumsq[0]
+  // R = I - A X in FP64, and sumsq[0] = |R|_F^2 (sumsq: Np + 1 doubles, the
+  // column sums after the total)
   hipLaunchKernelGGL(k_identity, grid2(Np), dim3(256), 0, st, Np, r, Np);
   gemm<double, false, false, false>(Np, Np, Np, a, lda, x, Np, r, Np, -1.0, 1.0, kFull, st);
-  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)Np), dim3(256), 0, st, Np, r, Np, sumsq);
+  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)Np), dim3(256), 0, st, Np, r, Np, sumsq + 1);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, Np, sumsq + 1, sumsq);
 }
 
 void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32, float *d32,

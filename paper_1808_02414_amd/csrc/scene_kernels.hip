@@ -9,8 +9,6 @@
 //   * Jacobi scaling of Z + a QQ^T (Sec. 5.2, conditioning).
 #include <algorithm>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "camera_model.h"
 #include "ucov_internal.h"
 #include "../../include/ucov.h"
@@ -426,11 +424,14 @@ __global__ void k_nz_compact(SceneDev sc, int64_t nbins, const int32_t *bin_cnt,
   if (b < nbins && bin_cnt[b] > 0) nzlist[nzpos[b]] = bin_pair(sc, b);
 }
 
+// Both fills write nothing when the pair count (*total) exceeds the capacity
+// of the pair list or the overflow flag *skip is set (a replayed launch
+// sequence whose scene grew: its bins were emptied and the error reported).
 __global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *slot_cam,
                             const int32_t *slot_pt, const int64_t *bin_ptr, int32_t *bin_cur,
-                            int2 *pairs) {
+                            int2 *pairs, const int64_t *total, int64_t cap, const int32_t *skip) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= ptr_p[sc.m]) return;
+  if (a >= ptr_p[sc.m] || *total > cap || (skip && *skip)) return;
   const int64_t p0 = ptr_p[slot_pt[a]];
   const int ci = slot_cam[a];
   for (int64_t b = p0; b <= a; ++b) {
@@ -445,21 +446,110 @@ __global__ void k_pair_fill(SceneDev sc, const int64_t *ptr_p, const int32_t *sl
 // camera i all fall in bin row i, so one workgroup per camera counts them
 // and then places them with LDS counters over the scene's cameras k <= i, and
 // no global atomics are needed.  The slots of each camera come from a stable
-// radix sort of the slots by camera (ascending slot order within a camera).
+// radix sort of the slots by camera (ascending slot order within a camera,
+// below).
 // (Grouping the slots with one global atomic per slot instead was measured
 // slower: 500 cameras share ~300 000 increments.)
 constexpr int kCamThreads = 256;
 
-__global__ void k_iota_i32(int32_t *p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (int32_t)i;
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of the slots by camera, 8 bits per pass: per block of
+// kRadixItems keys a digit histogram, one exclusive scan over (digit, block),
+// then a scatter in which every key's rank among the equal digits before it
+// in its block comes from wave ballots (lanes with the same digit are found
+// by matching the 8 digit bits) and per-wave running counts.  No atomics
+// decide a position, so the order is the same on every call, and equal keys
+// keep their input order (slots ascending within a camera).
+// ---------------------------------------------------------------------------
+constexpr int kRadixThreads = 256;
+constexpr int kRadixSteps = 16;  // 64-key steps per wave
+constexpr int kRadixItems = kRadixThreads * kRadixSteps;
+constexpr int kRadixPerWave = 64 * kRadixSteps;
+
+// Only the first *count of the t slots hold observations (the rest belong to
+// rejected input), so every kernel of the sort stops there.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int64_t t_max, const int64_t *count,
+                                                            const int32_t *keys, int shift,
+                                                            int64_t nblocks, int32_t *hist) {
+  __shared__ int32_t cnt[256];
+  const int64_t t = min(t_max, *count);
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixItems;
+  for (int k = threadIdx.x; k < kRadixItems; k += kRadixThreads) {
+    const int64_t e = base + k;
+    if (e < t) atomicAdd(&cnt[((uint32_t)keys[e] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// vals_in null: the value of a key is its input position.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
+    int64_t t_max, const int64_t *count, const int32_t *keys_in, const int32_t *vals_in,
+    int shift, int64_t nblocks, const int64_t *offs, int32_t *keys_out, int32_t *vals_out) {
+  __shared__ int32_t wcnt[kRadixThreads / 64][256];
+  __shared__ int32_t wpre[kRadixThreads / 64][256];
+  const int64_t t = min(t_max, *count);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < 256 * (kRadixThreads / 64); d += kRadixThreads) wcnt[d >> 8][d & 255] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixItems + (int64_t)w * kRadixPerWave;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t key[kRadixSteps], rank[kRadixSteps];
+#pragma unroll
+  for (int st = 0; st < kRadixSteps; ++st) {
+    const int64_t e = base + st * 64 + lane;
+    const bool valid = e < t;
+    const int32_t k = valid ? keys_in[e] : 0;
+    const unsigned d = ((uint32_t)k >> shift) & 255u;
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t ones = __ballot(valid && ((d >> b) & 1u));
+      same &= ((d >> b) & 1u) ? ones : ~ones;
+    }
+    int32_t before = 0;
+    if (valid) before = wcnt[w][d];
+    // all lanes have read before the lowest lane of each digit group writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && (same & below) == 0) wcnt[w][d] = before + (int32_t)__popcll(same);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    key[st] = k;
+    rank[st] = before + (int32_t)__popcll(same & below);
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;  // 256 threads, one per digit
+    int32_t run = 0;
+#pragma unroll
+    for (int v = 0; v < kRadixThreads / 64; ++v) {
+      wpre[v][d] = run;
+      run += wcnt[v][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < kRadixSteps; ++st) {
+    const int64_t e = base + st * 64 + lane;
+    if (e >= t) continue;
+    const unsigned d = ((uint32_t)key[st] >> shift) & 255u;
+    const int64_t dest = offs[(int64_t)d * nblocks + blockIdx.x] + wpre[w][d] + rank[st];
+    keys_out[dest] = key[st];
+    vals_out[dest] = vals_in ? vals_in[e] : (int32_t)e;
+  }
 }
 
 // cam_ptr[c] = first position of camera c in the sorted camera keys, c <= n.
-__global__ void k_cam_bounds(int n, int64_t t, const int32_t *cam_sorted, int64_t *cam_ptr) {
+__global__ void k_cam_bounds(int n, int64_t t_max, const int64_t *count, const int32_t *cam_sorted,
+                             int64_t *cam_ptr) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c > n) return;
-  int64_t lo = 0, hi = t;
+  int64_t lo = 0, hi = min(t_max, *count);
   while (lo < hi) {
     const int64_t mid = (lo + hi) / 2;
     if (cam_sorted[mid] < c) lo = mid + 1;
@@ -497,8 +587,10 @@ constexpr int kFillThreads = 64;
 
 __global__ __launch_bounds__(kFillThreads) void k_pair_fill_cam(
     SceneDev sc, const int64_t *cam_ptr, const int32_t *cam_slots, const int64_t *ptr_p,
-    const int32_t *slot_cam, const int32_t *slot_pt, const int64_t *bin_ptr, int2 *pairs) {
+    const int32_t *slot_cam, const int32_t *slot_pt, const int64_t *bin_ptr, int2 *pairs,
+    const int64_t *total, int64_t cap, const int32_t *skip) {
   extern __shared__ int32_t cur[];  // next position of each bin, from the row's start
+  if (*total > cap || (skip && *skip)) return;
   const int i = blockIdx.x;
   const int c0 = sc.cam_scene ? sc.cam_off[sc.cam_scene[i]] : 0;
   const int nk = i - c0 + 1;
@@ -1318,35 +1410,107 @@ void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStr
   fill_i32(w.bin_cur, 0, nbins, st);
 }
 
-void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st) {
+void launch_pair_fill(const SceneDev &sc, SceneWork &w, int64_t nbins, int64_t cap,
+                      const int32_t *skip, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_fill, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, sc,
-                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_ptr, w.bin_cur, w.pairs);
+                     w.ptr_p, w.slot_cam, w.slot_pt, w.bin_ptr, w.bin_cur, w.pairs,
+                     w.bin_ptr + nbins, cap, skip);
 }
 
-// Radix passes (onesweep) from 64 Ki slots on; rocPRIM's default sends up to
-// 1 Mi items to a merge sort, 21 launches for the 500-camera scene's slots.
-using CamSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                                 rocprim::default_config, 65536>;
+namespace {
+// A replayed launch sequence was sized by the call that recorded it.  When
+// the scene's pair count exceeds the pair list, every bin is emptied (so no
+// kernel reads or writes pairs beyond the list) and UCOV_EINVAL is reported;
+// more non-empty bins than recorded are reported as well (the bin reduction's
+// grid covers the recorded count only).
+__global__ void k_pairs_overflow(const int64_t *pairs, int64_t pairs_cap, int32_t *flag,
+                                 DevStatus *ds) {
+  *flag = *pairs > pairs_cap;
+  if (*flag) report_error(ds, UCOV_EINVAL, -1);
+}
+
+__global__ void k_empty_bins_if(const int32_t *flag, int64_t nbins, int32_t *bin_cnt,
+                                int64_t *bin_ptr) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!*flag || b > nbins) return;
+  if (b < nbins) bin_cnt[b] = 0;
+  bin_ptr[b] = 0;
+}
+
+__global__ void k_check_nonzero(const int64_t *nz, int64_t nz_cap, DevStatus *ds) {
+  if (*nz > nz_cap) report_error(ds, UCOV_EINVAL, -1);
+}
+}  // namespace
+
+void launch_guard_pairs(SceneWork &w, int64_t nbins, int64_t pairs_cap, int32_t *flag,
+                        DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_pairs_overflow, dim3(1), dim3(1), 0, st, w.bin_ptr + nbins, pairs_cap, flag,
+                     ds);
+  hipLaunchKernelGGL(k_empty_bins_if, dim3(blocks_for(nbins + 1, kBlk)), dim3(kBlk), 0, st, flag,
+                     nbins, w.bin_cnt, w.bin_ptr);
+}
+
+void launch_check_nonzero(const SceneWork &w, int64_t nz_cap, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_nonzero, dim3(1), dim3(1), 0, st, w.nzcount, nz_cap, ds);
+}
+
+// Scratch of the camera sort: ping-pong keys and values (t each), the
+// (digit, block) histogram, its int64 offsets and the scan's tile sums.
+struct RadixScratch {
+  int32_t *keys, *vals, *hist;
+  int64_t *offs, *scan;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static RadixScratch radix_layout(void *tmp, int64_t t) {
+  const int64_t nb = (t + kRadixItems - 1) / kRadixItems, len = 256 * nb;
+  char *p = static_cast<char *>(tmp);
+  RadixScratch r;
+  r.keys = reinterpret_cast<int32_t *>(p);
+  p += align256(4 * (size_t)t);
+  r.vals = reinterpret_cast<int32_t *>(p);
+  p += align256(4 * (size_t)t);
+  r.hist = reinterpret_cast<int32_t *>(p);
+  p += align256(4 * (size_t)len);
+  r.offs = reinterpret_cast<int64_t *>(p);
+  p += align256(8 * (size_t)(len + 1));
+  r.scan = reinterpret_cast<int64_t *>(p);
+  return r;
+}
 
 size_t camera_lists_scratch(int64_t t) {
-  size_t bytes = 0;
-  rocprim::radix_sort_pairs<CamSortConfig>(nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
-                            (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)t, 0, 32);
-  return bytes;
+  const int64_t nb = (t + kRadixItems - 1) / kRadixItems, len = 256 * nb;
+  const int64_t scan_tiles = (len + 4095) / 4096 + 2;
+  return 2 * align256(4 * (size_t)t) + align256(4 * (size_t)len) + align256(8 * (size_t)(len + 1)) +
+         8 * (size_t)scan_tiles;
 }
 
 int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_bytes,
                         hipStream_t st) {
-  unsigned bits = 1;
+  const int64_t t = sc.t;
+  if (tmp_bytes < camera_lists_scratch(t)) return -1;
+  int bits = 1;
   while (bits < 31 && ((int64_t)1 << bits) < (int64_t)sc.n) ++bits;
-  hipLaunchKernelGGL(k_iota_i32, dim3(blocks_for(sc.t, kBlk)), dim3(kBlk), 0, st, w.cam_iota,
-                     sc.t);
-  const hipError_t e =
-      rocprim::radix_sort_pairs<CamSortConfig>(tmp, tmp_bytes, (const int32_t *)w.slot_cam, w.cam_keys,
-                                (const int32_t *)w.cam_iota, w.cam_slots, (size_t)sc.t, 0, bits, st);
-  if (e != hipSuccess) return -1;
+  const int passes = (bits + 7) / 8;
+  const int64_t nb = (t + kRadixItems - 1) / kRadixItems;
+  const RadixScratch r = radix_layout(tmp, t);
+  const int64_t *count = w.ptr_p + sc.m;  // slots placed by the point grouping
+  const int32_t *kin = w.slot_cam, *vin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    // the last pass writes the camera lists, the one before it the scratch
+    const bool to_lists = (passes - 1 - p) % 2 == 0;
+    int32_t *kout = to_lists ? w.cam_keys : r.keys, *vout = to_lists ? w.cam_slots : r.vals;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kRadixThreads), 0, st, t, count,
+                       kin, 8 * p, nb, r.hist);
+    exclusive_scan(r.hist, r.offs, 256 * nb, r.scan, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kRadixThreads), 0, st, t, count,
+                       kin, vin, 8 * p, nb, r.offs, kout, vout);
+    kin = kout;
+    vin = vout;
+  }
   hipLaunchKernelGGL(k_cam_bounds, dim3(blocks_for((int64_t)sc.n + 1, kBlk)), dim3(kBlk), 0, st,
-                     sc.n, sc.t, w.cam_keys, w.cam_ptr);
+                     sc.n, sc.t, count, w.cam_keys, w.cam_ptr);
   return 0;
 }
 
@@ -1357,11 +1521,11 @@ void launch_pair_count_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
                      w.slot_cam, w.slot_pt, w.bin_cnt);
 }
 
-void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
-                          hipStream_t st) {
+void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams, int64_t nbins,
+                          int64_t cap, const int32_t *skip, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_fill_cam, dim3(sc.n), dim3(kFillThreads),
                      sizeof(int32_t) * max_scene_cams, st, sc, w.cam_ptr, w.cam_slots, w.ptr_p,
-                     w.slot_cam, w.slot_pt, w.bin_ptr, w.pairs);
+                     w.slot_cam, w.slot_pt, w.bin_ptr, w.pairs, w.bin_ptr + nbins, cap, skip);
 }
 
 void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {

@@ -94,13 +94,18 @@ struct ucov_ctx {
   DevStatus *ds_host = nullptr;  // pinned host mirror
   int64_t *i64_host = nullptr;   // pinned host scalars [0] pairs, [1] non-empty bins
   int64_t n_nonzero = 0;         // non-empty bins of the last scene stage
+  int64_t pairs_cap = 0;         // entries of the pair list of the last scene stage
+  // Recording a launch sequence (a batch's graph): no host round trip, no
+  // event, no upload; the counts of the eager call that sized the buffers hold.
+  bool replay = false;
   hipEvent_t ev[kEvCount] = {};
   // workspace
   Buf cnt_p, ptr_p, cur_p, slot_key, slot_obs, slot_cam, slot_pt, rec;
-  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos;
-  Buf cam_iota, cam_keys, cam_slots, cam_ptr, cam_tmp;  // slots grouped by camera
+  Buf bin_cnt, bin_ptr, bin_cur, pairs, scan_tmp, nzlist, nzcount, nzpos, flag;
+  Buf cam_keys, cam_slots, cam_ptr, cam_tmp;  // slots grouped by camera
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
+  Buf m_split;  // split-BF16 slices and exponents
   // batched calls: the concatenated scenes, their tables and per-scene status
   Buf b_cams, b_pts, b_info, b_oc, b_op, b_cam_scene, b_tab, b_ds, b_scratch;
   SpdPlan *plan = nullptr;  // batched inverse plan, kept while the batch is unchanged
@@ -116,6 +121,13 @@ struct ucov_ctx {
   int64_t small_for(int64_t np) const {
     const auto it = small_tiles.find(np);
     return it == small_tiles.end() ? kSmallTilesDefault : it->second;
+  }
+  // batched dense stage: the tuned threshold per list of padded sizes (scene
+  // order); untuned batches run every product on 64 x 64 tiles
+  std::map<std::vector<int64_t>, int64_t> batch_small;
+  int64_t batch_small_for(const std::vector<int64_t> &np) const {
+    const auto it = batch_small.find(np);
+    return it == batch_small.end() ? 0 : it->second;
   }
   Buf fc_x, fc_part, fc_xq, fc_k;  // whole covariance: X, X q partial sums, X q, q^T X q
   // incremental update: indices, padded Z^+, JtT, B, T, S, scratch, Jacobians, J_n, U, small, V, W
@@ -241,6 +253,28 @@ int check_scene(ucov_ctx *c, const ucov_scene *s) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// UCOV_ENOMEM before any launch when a scene's work buffers alone exceed the
+// device's memory: the dense matrix and its recursion scratch, the camera-pair
+// bins and the per-observation records (a lower bound of what the call needs).
+int check_fits(ucov_ctx *c, const ucov_scene *s) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    hipGetLastError();
+    return UCOV_OK;  // unknown: the allocations will tell
+  }
+  const double n = s->n_cams, Np = (double)round_up(9 * (int64_t)s->n_cams, kTile);
+  const double need = 8.0 * Np * Np * 1.5 + 32.0 * n * (n + 1) / 2 + 300.0 * (double)s->n_obs;
+  if (need <= (double)total_b) return UCOV_OK;
+  char buf[200];
+  snprintf(buf, sizeof buf, "the scene needs at least %.3g bytes of device memory, the device has %.3g",
+           need, (double)total_b);
+  return c->fail(UCOV_ENOMEM, buf);
+}
+
+void mark(ucov_ctx *c, int k, hipStream_t st) {
+  if (!c->replay) hipEventRecord(c->ev[k], st);
+}
+
 float ev_ms(ucov_ctx *c, int a, int b) {
   float t = 0.0f;
   if (hipEventElapsedTime(&t, c->ev[a], c->ev[b]) != hipSuccess) {
@@ -262,6 +296,7 @@ void report_stages(ucov_ctx *c, ucov_report *rep) {
   rep->ms_gauge = ev_ms(c, kEvDiag, kEvGauge);
   rep->ms_inverse = ev_ms(c, kEvAssembled, kEvInverse);
   rep->ms_extract = ev_ms(c, kEvInverse, kEvEnd);
+  rep->ms_total = ev_ms(c, kEvStart, kEvEnd);
 }
 
 // Steps a1-a2 up to the per-camera diagonal blocks and the nullspace rows.
@@ -296,13 +331,13 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.scan_tmp = as<int64_t>(c->scan_tmp);
   hipStream_t st = c->stream;
 
-  hipEventRecord(c->ev[kEvStart], st);
+  mark(c, kEvStart, st);
   fill_i32(w.cnt_p, 0, m, st);
   fill_i32(w.cur_p, 0, m, st);
   launch_count_points(sc, w, c->ds, st);
   exclusive_scan(w.cnt_p, w.ptr_p, m, w.scan_tmp, st);
   launch_group_points(sc, w, c->ds, st);
-  hipEventRecord(c->ev[kEvGrouped], st);
+  mark(c, kEvGrouped, st);
   launch_jacobians(sc, w, jp_out, jx_out, c->ds, st);
   UCOV_TRY(check_hip(c, "jacobian kernels"));
   if (jac_only) return sync_status(c, rep, "jacobians");
@@ -312,6 +347,7 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   UCOV_TRY(ensure(c, c->bin_cur, 4 * nbins));
   UCOV_TRY(ensure(c, c->nzlist, sizeof(int2) * nbins));  // at most one entry per bin
   UCOV_TRY(ensure(c, c->nzcount, 8));
+  UCOV_TRY(ensure(c, c->flag, 8));
   UCOV_TRY(ensure(c, c->nzpos, 8 * (nbins + 1)));
   w.bin_cnt = as<int32_t>(c->bin_cnt);
   w.bin_ptr = as<int64_t>(c->bin_ptr);
@@ -320,19 +356,17 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.nzcount = as<int64_t>(c->nzcount);
   w.nzpos = as<int64_t>(c->nzpos);
   launch_point_blocks(sc, w, c->ds, st);
-  hipEventRecord(c->ev[kEvPoints], st);
+  mark(c, kEvPoints, st);
   // camera-pair bins: camera-major with LDS counters where the largest
   // scene's cameras fit them, else one global atomic per pair
   const int64_t mc = max_scene_cams < 0 ? n : max_scene_cams;
   const bool cam_major = t > 0 && mc <= kCamHistMax;
   if (cam_major) {
     const size_t tmp_bytes = camera_lists_scratch(t);
-    UCOV_TRY(ensure(c, c->cam_iota, 4 * t));
     UCOV_TRY(ensure(c, c->cam_keys, 4 * t));
     UCOV_TRY(ensure(c, c->cam_slots, 4 * t));
     UCOV_TRY(ensure(c, c->cam_ptr, 8 * (n + 1)));
     UCOV_TRY(ensure(c, c->cam_tmp, std::max<size_t>(tmp_bytes, 8)));
-    w.cam_iota = as<int32_t>(c->cam_iota);
     w.cam_keys = as<int32_t>(c->cam_keys);
     w.cam_slots = as<int32_t>(c->cam_slots);
     w.cam_ptr = as<int64_t>(c->cam_ptr);
@@ -344,15 +378,23 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
     launch_pair_count(sc, w, st);
   }
   exclusive_scan(w.bin_cnt, w.bin_ptr, nbins, w.scan_tmp, st);
+  if (c->replay) launch_guard_pairs(w, nbins, c->pairs_cap, as<int32_t>(c->flag), c->ds, st);
   launch_nonzero_bins(sc, w, nbins, st);
   UCOV_TRY(check_hip(c, "point kernels"));
-  // the pair count sizes the next buffer: one host round trip
-  hipMemcpyAsync(c->i64_host, w.bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-  hipMemcpyAsync(c->i64_host + 1, w.nzcount, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-  UCOV_TRY(sync_status(c, rep, "point blocks"));
-  const int64_t npairs = c->i64_host[0];
-  c->n_nonzero = c->i64_host[1];
-  if (rep) rep->n_pairs = npairs;
+  int64_t npairs = c->pairs_cap;
+  if (c->replay) {
+    // the recorded sizes hold; the device checks that the scene did not grow
+    launch_check_nonzero(w, c->n_nonzero, c->ds, st);
+  } else {
+    // the pair count sizes the next buffer: one host round trip
+    hipMemcpyAsync(c->i64_host, w.bin_ptr + nbins, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->i64_host + 1, w.nzcount, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    UCOV_TRY(sync_status(c, rep, "point blocks"));
+    npairs = c->i64_host[0];
+    c->n_nonzero = c->i64_host[1];
+    c->pairs_cap = npairs;
+    if (rep) rep->n_pairs = npairs;
+  }
   UCOV_TRY(ensure(c, c->pairs, sizeof(int2) * npairs));
   UCOV_TRY(ensure(c, c->zdiag, 8 * 81 * n));
   UCOV_TRY(ensure(c, c->hc, 8 * 7 * N));
@@ -360,11 +402,15 @@ int run_scene_stage(ucov_ctx *c, const SceneDev &sc, int64_t nbins, double *jp_o
   w.zdiag = as<double>(c->zdiag);
   w.hc = as<double>(c->hc);
   // the camera-major fill keeps LDS cursors as int32 offsets within a row
-  if (cam_major && npairs < ((int64_t)1 << 31)) launch_pair_fill_cam(sc, w, (int)mc, st);
-  else launch_pair_fill(sc, w, st);
-  hipEventRecord(c->ev[kEvBins], st);
+  // a replay skips the fill when its scene outgrew the recorded pair list
+  const int32_t *skip = c->replay ? as<int32_t>(c->flag) : nullptr;
+  if (cam_major && npairs < ((int64_t)1 << 31))
+    launch_pair_fill_cam(sc, w, (int)mc, nbins, npairs, skip, st);
+  else
+    launch_pair_fill(sc, w, nbins, npairs, skip, st);
+  mark(c, kEvBins, st);
   launch_camera_diag(sc, w, c->ds, st);
-  hipEventRecord(c->ev[kEvDiag], st);
+  mark(c, kEvDiag, st);
   UCOV_TRY(check_hip(c, "schur kernels"));
   return UCOV_OK;
 }
@@ -383,7 +429,6 @@ SceneWork scene_work(ucov_ctx *c) {
   w.bin_ptr = as<int64_t>(c->bin_ptr);
   w.bin_cur = as<int32_t>(c->bin_cur);
   w.pairs = as<int2>(c->pairs);
-  w.cam_iota = as<int32_t>(c->cam_iota);
   w.cam_keys = as<int32_t>(c->cam_keys);
   w.cam_slots = as<int32_t>(c->cam_slots);
   w.cam_ptr = as<int64_t>(c->cam_ptr);
@@ -442,19 +487,25 @@ void fill_defaults(const ucov_options *opt, ucov_options &o) {
 
 // Mixed-precision inverse of A_s (Np x Np in c->amat): FP32 MFMA Cholesky
 // inverse X0, then Newton-Schulz steps X <- X + X (I - A X) with the residual
-// in FP64 and the correction on FP32 MFMA, until |I - A X|_F / sqrt(N) <= tol.
+// in FP64 and the correction on FP32 MFMA (UCOV_FP32_NS) or from split-BF16
+// products on BF16 MFMA (UCOV_BF16X_NS), until |I - A X|_F / sqrt(N) <= tol.
 int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double *cov_out,
               ucov_report *rep) {
   hipStream_t st = c->stream;
   const size_t f32 = 4 * (size_t)Np * Np, f64 = 8 * (size_t)Np * Np;
+  const bool split = o.precision == UCOV_BF16X_NS;
   UCOV_TRY(ensure(c, c->m_a32, f32));
   UCOV_TRY(ensure(c, c->m_x32, f32));
-  UCOV_TRY(ensure(c, c->m_r32, f32));
-  UCOV_TRY(ensure(c, c->m_d32, f32));
+  if (split) {
+    UCOV_TRY(ensure(c, c->m_split, split_bf16_scratch(Np)));
+  } else {
+    UCOV_TRY(ensure(c, c->m_r32, f32));
+    UCOV_TRY(ensure(c, c->m_d32, f32));
+  }
   UCOV_TRY(ensure(c, c->m_tmp32, 4 * std::max<int64_t>(1, spd_lower_inverse_scratch(Np))));
   UCOV_TRY(ensure(c, c->m_x64, f64));
   UCOV_TRY(ensure(c, c->m_r64, f64));
-  UCOV_TRY(ensure(c, c->m_sum, 8));
+  UCOV_TRY(ensure(c, c->m_sum, 8 * ((size_t)Np + 1)));
   double *A = as<double>(c->amat);
   mixed_initial_inverse(Np, A, Np, as<float>(c->m_a32), as<float>(c->m_x32),
                         as<float>(c->m_tmp32), c->ds, st);
@@ -470,7 +521,6 @@ int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double 
   double res = 0.0;
   int it = 0;
   for (;; ++it) {
-    fill_f64(as<double>(c->m_sum), 0.0, 1, st);
     mixed_residual(Np, A, Np, as<double>(c->m_x64), as<double>(c->m_r64), as<double>(c->m_sum),
                    st);
     double h = 0.0;
@@ -479,8 +529,11 @@ int run_mixed(ucov_ctx *c, int64_t N, int64_t Np, const ucov_options &o, double 
       return c->fail(UCOV_EDEVICE, "residual readback");
     res = std::sqrt(h / (double)N);
     if (res <= o.tol || it >= o.max_iter) break;
-    mixed_update(Np, as<double>(c->m_x64), as<double>(c->m_r64), as<float>(c->m_x32),
-                 as<float>(c->m_r32), as<float>(c->m_d32), st);
+    if (split)
+      split_bf16_update(Np, as<double>(c->m_x64), as<double>(c->m_r64), c->m_split.p, st);
+    else
+      mixed_update(Np, as<double>(c->m_x64), as<double>(c->m_r64), as<float>(c->m_x32),
+                   as<float>(c->m_r32), as<float>(c->m_d32), st);
   }
   if (rep) {
     rep->ns_iters = it;
@@ -570,11 +623,11 @@ void ucov_destroy(ucov_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   Buf *bufs[] = {&c->cnt_p, &c->ptr_p, &c->cur_p, &c->slot_key, &c->slot_obs, &c->slot_cam, &c->slot_pt,
-                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount, &c->nzpos,
-                 &c->cam_iota, &c->cam_keys, &c->cam_slots, &c->cam_ptr, &c->cam_tmp,
+                 &c->rec, &c->bin_cnt, &c->bin_ptr, &c->bin_cur, &c->pairs, &c->scan_tmp, &c->nzlist, &c->nzcount, &c->nzpos, &c->flag,
+                 &c->cam_keys, &c->cam_slots, &c->cam_ptr, &c->cam_tmp,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
-                 &c->m_sum, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
+                 &c->m_sum, &c->m_split, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
                  &c->mlp_ws, &c->mlp_grad, &c->f_lab, &c->f_zero, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
                  &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
@@ -647,10 +700,11 @@ int camera_covariance_impl(ucov_ctx *c, const ucov_scene *scene, const ucov_opti
                            double *cov_out, ucov_report *rep) {
   if (!c) return UCOV_EINVAL;
   UCOV_TRY(check_scene(c, scene));
+  UCOV_TRY(check_fits(c, scene));
   if (!cov_out) return c->fail(UCOV_EINVAL, "NULL output");
   ucov_options o;
   fill_defaults(opt, o);
-  if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
+  if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS && o.precision != UCOV_BF16X_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   if (o.gauge != UCOV_GAUGE_CAMERA && o.gauge != UCOV_GAUGE_PAPER)
     return c->fail(UCOV_EINVAL, "unknown gauge");
@@ -711,7 +765,7 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
     return c->fail(UCOV_EINVAL, "bad dense arguments");
   ucov_options o;
   fill_defaults(opt, o);
-  if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS)
+  if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS && o.precision != UCOV_BF16X_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   hipSetDevice(c->device);
   reset_report(rep);
@@ -973,11 +1027,156 @@ int ucov_tune_dense(ucov_ctx *c, int64_t n, int64_t *threshold, float *ms) {
   return UCOV_OK;
 }
 
+// The batched dense stage's tile schedule for scenes of sizes n[0..count):
+// every candidate threshold is timed on synthetic positive definite matrices
+// of those padded sizes run as one batched recursion (best of three), and the
+// fastest is kept for that list of sizes.
+int ucov_tune_batched(ucov_ctx *c, int32_t count, const int64_t *n, int64_t *threshold,
+                      float *ms) {
+  if (!c) return UCOV_EINVAL;
+  if (count < 1 || !n) return c->fail(UCOV_EINVAL, "bad batch sizes");
+  std::vector<int64_t> np(count), a_off(count + 1, 0);
+  for (int s = 0; s < count; ++s) {
+    if (n[s] < 1) return c->fail(UCOV_EINVAL, "sizes must be positive");
+    np[s] = round_up(n[s], kTile);
+    a_off[s + 1] = a_off[s] + np[s] * np[s];
+  }
+  hipSetDevice(c->device);
+  hipStream_t st = c->stream;
+  std::vector<int64_t> need(count), tmp_off(count + 1, 0);
+  spd_batch_scratch(np.data(), count, need.data());
+  for (int s = 0; s < count; ++s)
+    tmp_off[s + 1] = tmp_off[s] + round_up(std::max<int64_t>(need[s], 1), 32);
+  UCOV_TRY(ensure(c, c->amat, 8 * (size_t)a_off[count]));
+  UCOV_TRY(ensure(c, c->b_scratch, 8 * (size_t)tmp_off[count]));
+  UCOV_TRY(ensure(c, c->b_ds, sizeof(DevStatus) * count));
+  DevStatus *bds = as<DevStatus>(c->b_ds);
+  std::vector<SpdMat> mats(count);
+  for (int s = 0; s < count; ++s)
+    mats[s] = SpdMat{as<double>(c->amat) + a_off[s], np[s], np[s],
+                     as<double>(c->b_scratch) + tmp_off[s], bds + s};
+  if (!c->plan) c->plan = spd_plan_create();
+  static const int64_t cand[] = {0, 256, 1024, 4096, (int64_t)1 << 40};
+  int64_t best = 0;
+  float best_ms = 0.0f;
+  for (int64_t small : cand) {
+    if (spd_plan_build(c->plan, mats.data(), count, st, small) != 0) {
+      hipGetLastError();
+      return c->fail(UCOV_ENOMEM, "batched inverse plan tables");
+    }
+    float t_min = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      for (int s = 0; s < count; ++s) launch_tuning_matrix(np[s], as<double>(c->amat) + a_off[s], np[s], st);
+      fill_i32(reinterpret_cast<int32_t *>(bds), 0, 2 * (int64_t)count, st);
+      hipEventRecord(c->ev[kEvTune0], st);
+      spd_plan_run(c->plan, st);
+      hipEventRecord(c->ev[kEvTune1], st);
+      if (hipEventSynchronize(c->ev[kEvTune1]) != hipSuccess)
+        return c->fail(UCOV_EDEVICE, "batched tuning run");
+      const float t = ev_ms(c, kEvTune0, kEvTune1);
+      if (rep == 0 || t < t_min) t_min = t;
+    }
+    if (best_ms == 0.0f || t_min < best_ms) {
+      best_ms = t_min;
+      best = small;
+    }
+  }
+  UCOV_TRY(check_hip(c, "batched tuning"));
+  c->batch_small[np] = best;
+  if (threshold) *threshold = best;
+  if (ms) *ms = best_ms;
+  return UCOV_OK;
+}
+
+int ucov_set_dense_threshold(ucov_ctx *c, int64_t n, int64_t threshold) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 1 || threshold < 0) return c->fail(UCOV_EINVAL, "n must be positive, threshold >= 0");
+  c->small_tiles[round_up(n, kTile)] = threshold;
+  return UCOV_OK;
+}
+
 // Several independent scenes in one call.  The scene stage runs once over the
 // concatenation (one launch per kernel for all scenes: camera-pair bins, the
 // gauge basis and the dense matrices are kept per scene); the dense inverses
 // of all scenes then run as one batched recursion whose every launch serves a
 // node of the recursion for all the scenes that reach it.
+}  // extern "C"
+
+namespace {
+
+// Offsets of the scenes of a batch in the concatenation.
+struct BatchOffsets {
+  std::vector<int32_t> cam_off, pt_off;
+  std::vector<int64_t> obs_off;
+};
+
+// A failure of the scene stage names a global observation, point or camera:
+// translate it into (scene, local index).
+int localize_batch_error(ucov_ctx *c, const BatchOffsets &o, int rc, ucov_report *rep) {
+  if (rc == UCOV_OK || !rep || rep->bad_index < 0) return rc;
+  const int S = (int)o.cam_off.size() - 1;
+  const int64_t g = rep->bad_index;
+  int s = 0;
+  int64_t base = 0;
+  if (rc == UCOV_EINVAL) {
+    s = (int)(std::upper_bound(o.obs_off.begin(), o.obs_off.end(), g) - o.obs_off.begin()) - 1;
+    s = std::min(std::max(s, 0), S - 1);
+    base = o.obs_off[s];
+  } else if (rc == UCOV_EPOINT) {
+    s = (int)(std::upper_bound(o.pt_off.begin(), o.pt_off.end(), (int32_t)g) - o.pt_off.begin()) - 1;
+    s = std::min(std::max(s, 0), S - 1);
+    base = o.pt_off[s];
+  } else if (rc == UCOV_EGAUGE) {
+    s = (int)(std::upper_bound(o.cam_off.begin(), o.cam_off.end(), (int32_t)g) - o.cam_off.begin()) - 1;
+    s = std::min(std::max(s, 0), S - 1);
+    base = o.cam_off[s];
+  } else {
+    return rc;
+  }
+  rep->bad_scene = s;
+  rep->bad_index = (int32_t)(g - base);
+  c->last_error += " in scene " + std::to_string(s) + ", local index " + std::to_string(g - base);
+  return rc;
+}
+
+// Status of a batched solve once the stream has drained: the global status
+// word (scene stage), then every scene's dense-stage status.
+int batch_status(ucov_ctx *c, int S, const BatchOffsets &offs, ucov_report *rep) {
+  hipStream_t st = c->stream;
+  if (c->h_ds_cap < (size_t)S) {
+    if (c->h_ds) hipHostFree(c->h_ds);
+    c->h_ds = nullptr;
+    c->h_ds_cap = 0;
+    if (hipHostMalloc(&c->h_ds, sizeof(DevStatus) * S) != hipSuccess) {
+      hipGetLastError();
+      hipStreamSynchronize(st);
+      return c->fail(UCOV_ENOMEM, "pinned status buffer");
+    }
+    c->h_ds_cap = S;
+  }
+  hipMemcpyAsync(c->h_ds, c->b_ds.p, sizeof(DevStatus) * S, hipMemcpyDeviceToHost, st);
+  {
+    const int rc = sync_status(c, rep, "batched solve");
+    if (rc != UCOV_OK) return localize_batch_error(c, offs, rc, rep);
+  }
+  for (int s = 0; s < S; ++s) {
+    if (c->h_ds[s].code != 0) {
+      if (rep) {
+        rep->bad_scene = s;
+        rep->bad_index = c->h_ds[s].index;
+      }
+      char buf[160];
+      snprintf(buf, sizeof buf, "dense inverse of scene %d (camera %d)", s, c->h_ds[s].index);
+      return c->fail(c->h_ds[s].code, buf);
+    }
+  }
+  return UCOV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_scene *scenes,
                                    const ucov_options *opt, double *cov_out, double *alphas,
                                    ucov_report *rep) {
@@ -1067,8 +1266,8 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   UCOV_TRY(ensure(c, c->b_ds, sizeof(DevStatus) * S));
   if (any_info) UCOV_TRY(ensure(c, c->b_info, 8 * 3 * t));
   char *dt = static_cast<char *>(c->b_tab.p);
-  hipEventRecord(c->ev[kEvBatch], st);
-  hipMemcpyAsync(dt, hs, total, hipMemcpyHostToDevice, st);
+  mark(c, kEvBatch, st);
+  if (!c->replay) hipMemcpyAsync(dt, hs, total, hipMemcpyHostToDevice, st);
   clear_status(c);
   launch_concat_scenes(S, reinterpret_cast<const BatchEntry *>(dt), max_elems,
                        as<double>(c->b_cams), as<double>(c->b_pts),
@@ -1090,32 +1289,8 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   sc.a_off = reinterpret_cast<const int64_t *>(dt + sz_tab + sz_co + sz_bo);
   sc.a_ld = reinterpret_cast<const int64_t *>(dt + sz_tab + sz_co + sz_bo + sz_ao);
 
-  // a failure of the scene stage names a global observation, point or camera:
-  // translate it into (scene, local index)
-  auto localize = [&](int rc) {
-    if (rc == UCOV_OK || !rep || rep->bad_index < 0) return rc;
-    const int64_t g = rep->bad_index;
-    int s = 0;
-    int64_t base = 0;
-    if (rc == UCOV_EINVAL) {
-      s = (int)(std::upper_bound(obs_off.begin(), obs_off.end(), g) - obs_off.begin()) - 1;
-      base = obs_off[s];
-    } else if (rc == UCOV_EPOINT) {
-      s = (int)(std::upper_bound(pt_off.begin(), pt_off.end(), (int32_t)g) - pt_off.begin()) - 1;
-      base = pt_off[s];
-    } else if (rc == UCOV_EGAUGE) {
-      s = (int)(std::upper_bound(cam_off.begin(), cam_off.end(), (int32_t)g) - cam_off.begin()) - 1;
-      base = cam_off[s];
-    } else {
-      return rc;
-    }
-    s = std::min(std::max(s, 0), S - 1);
-    rep->bad_scene = s;
-    rep->bad_index = (int32_t)(g - base);
-    c->last_error += " in scene " + std::to_string(s) + ", local index " +
-                     std::to_string(g - base);
-    return rc;
-  };
+  const BatchOffsets offs{cam_off, pt_off, obs_off};
+  auto localize = [&](int rc) { return localize_batch_error(c, offs, rc, rep); };
   int64_t max_cams = 0;
   for (int s = 0; s < S; ++s) max_cams = std::max<int64_t>(max_cams, cam_off[s + 1] - cam_off[s]);
   {
@@ -1128,11 +1303,11 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   UCOV_TRY(ensure(c, c->amat, 8 * std::max<int64_t>(1, a_off[S])));
   SceneWork w = scene_work(c);
   launch_gauge_scenes(sc, w.hc, w.q, w.zdiag, o.alpha, w.s, w.alpha, c->ds, st);
-  hipEventRecord(c->ev[kEvGauge], st);
+  mark(c, kEvGauge, st);
   launch_assemble(sc, w, 1, as<double>(c->amat), 0, c->n_nonzero, st, max_cams);
-  hipEventRecord(c->ev[kEvAssembled], st);
+  mark(c, kEvAssembled, st);
   UCOV_TRY(check_hip(c, "batched assemble"));
-  {
+  if (!c->replay) {
     const int rc = sync_status(c, rep, "batched gauge");
     if (rc != UCOV_OK) return localize(rc);
   }
@@ -1153,54 +1328,148 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
     max_np = std::max(max_np, a_ld[s]);
   }
   if (!c->plan) c->plan = spd_plan_create();
-  {
-    const int rc = spd_plan_build(c->plan, mats.data(), S, st);
+  if (!c->replay) {
+    const int rc = spd_plan_build(c->plan, mats.data(), S, st, c->batch_small_for(a_ld));
     if (rc == -2) return c->fail(UCOV_EDEVICE, "internal error: batched inverse plan out of bounds");
     if (rc != 0) {
       hipGetLastError();
       return c->fail(UCOV_ENOMEM, "batched inverse plan tables");
     }
   }
-  hipEventRecord(c->ev[kEvTune0], st);
+  mark(c, kEvTune0, st);
   fill_i32(reinterpret_cast<int32_t *>(bds), 0, 2 * (int64_t)S, st);
   launch_pad_identity_scenes(S, max_np, sc.cam_off, sc.a_off, sc.a_ld, amat, st);
   spd_plan_run(c->plan, st);
-  hipEventRecord(c->ev[kEvInverse], st);
+  mark(c, kEvInverse, st);
   launch_extract_scenes(n, sc.cam_scene, sc.cam_off, sc.a_off, sc.a_ld, amat, w.s, w.q, w.alpha,
                         cov_out, st);
-  hipEventRecord(c->ev[kEvEnd], st);
+  mark(c, kEvEnd, st);
   UCOV_TRY(check_hip(c, "batched dense kernels"));
-  // per-scene status of the dense stage
-  if (c->h_ds_cap < (size_t)S) {
-    if (c->h_ds) hipHostFree(c->h_ds);
-    c->h_ds = nullptr;
-    c->h_ds_cap = 0;
-    if (hipHostMalloc(&c->h_ds, sizeof(DevStatus) * S) != hipSuccess) {
-      hipGetLastError();
-      hipStreamSynchronize(st);
-      return c->fail(UCOV_ENOMEM, "pinned status buffer");
-    }
-    c->h_ds_cap = S;
-  }
-  hipMemcpyAsync(c->h_ds, bds, sizeof(DevStatus) * S, hipMemcpyDeviceToHost, st);
-  UCOV_TRY(sync_status(c, rep, "batched dense inverse"));
-  for (int s = 0; s < S; ++s) {
-    if (c->h_ds[s].code != 0) {
-      if (rep) {
-        rep->bad_scene = s;
-        rep->bad_index = c->h_ds[s].index;
-      }
-      char buf[160];
-      snprintf(buf, sizeof buf, "dense inverse of scene %d (camera %d)", s, c->h_ds[s].index);
-      return c->fail(c->h_ds[s].code, buf);
-    }
-  }
+  if (c->replay) return UCOV_OK;  // the run of the recorded sequence checks the status
+  UCOV_TRY(batch_status(c, S, offs, rep));
   if (alphas) hipMemcpy(alphas, c->alpha.p, 8 * (size_t)S, hipMemcpyDeviceToHost);
   if (rep) {
     hipMemcpy(&rep->alpha, c->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
     report_stages(c, rep);
     rep->ms_structure += ev_ms(c, kEvBatch, kEvStart);
     rep->ms_inverse = ev_ms(c, kEvTune0, kEvInverse);
+    rep->ms_total = ev_ms(c, kEvBatch, kEvEnd);
+  }
+  return UCOV_OK;
+}
+
+// ---- a batch recorded once and replayed ---------------------------------------
+
+}  // extern "C"
+
+struct ucov_batch {
+  ucov_ctx *parent = nullptr;
+  ucov_ctx *w = nullptr;          // private workspace that the graph uses
+  hipStream_t cap = nullptr;      // stream the graph was recorded on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int S = 0;
+  BatchOffsets offs;
+  ucov_report first{};            // report of the eager solve
+};
+
+extern "C" {
+
+void ucov_batch_destroy(ucov_batch *b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->w) {
+    b->w->stream = b->cap;
+    ucov_destroy(b->w);
+  }
+  if (b->cap) hipStreamDestroy(b->cap);
+  delete b;
+}
+
+int ucov_batch_create(ucov_ctx *c, int32_t n_scenes, const ucov_scene *scenes,
+                      const ucov_options *opt, double *cov_out, ucov_batch **batch) {
+  if (!c) return UCOV_EINVAL;
+  if (!batch) return c->fail(UCOV_EINVAL, "NULL batch handle");
+  *batch = nullptr;
+  if (n_scenes < 1 || !scenes || !cov_out) return c->fail(UCOV_EINVAL, "bad batch arguments");
+  hipSetDevice(c->device);
+  ucov_batch *b = new ucov_batch();
+  b->parent = c;
+  b->S = n_scenes;
+  if (ucov_create(&b->w, c->device) != UCOV_OK) {
+    delete b;
+    return c->fail(UCOV_ENOMEM, "private workspace of the batch");
+  }
+  b->w->small_tiles = c->small_tiles;
+  b->w->batch_small = c->batch_small;
+  if (hipStreamCreate(&b->cap) != hipSuccess) {
+    hipGetLastError();
+    ucov_batch_destroy(b);
+    return c->fail(UCOV_EDEVICE, "stream of the batch");
+  }
+  ucov_ctx *w = b->w;
+  w->stream = b->cap;
+  // the eager solve validates the scenes, sizes every buffer and builds the
+  // dense plan; its results are the first run's
+  int rc = ucov_camera_covariance_batched(w, n_scenes, scenes, opt, cov_out, nullptr, &b->first);
+  if (rc != UCOV_OK) {
+    c->last_error = w->last_error;
+    ucov_batch_destroy(b);
+    return rc;
+  }
+  for (int s = 0; s <= n_scenes; ++s) {
+    b->offs.cam_off.push_back(s ? b->offs.cam_off.back() + scenes[s - 1].n_cams : 0);
+    b->offs.pt_off.push_back(s ? b->offs.pt_off.back() + scenes[s - 1].n_pts : 0);
+    b->offs.obs_off.push_back(s ? b->offs.obs_off.back() + scenes[s - 1].n_obs : 0);
+  }
+  // record the same launches, with no host round trip, into a graph
+  w->replay = true;
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    w->replay = false;
+    hipGetLastError();
+    ucov_batch_destroy(b);
+    return c->fail(UCOV_EDEVICE, "beginning the graph capture");
+  }
+  rc = ucov_camera_covariance_batched(w, n_scenes, scenes, opt, cov_out, nullptr, nullptr);
+  const hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
+  w->replay = false;
+  if (rc != UCOV_OK || e != hipSuccess) {
+    hipGetLastError();
+    c->last_error = rc != UCOV_OK ? w->last_error : std::string("graph capture failed");
+    ucov_batch_destroy(b);
+    return rc != UCOV_OK ? rc : UCOV_EDEVICE;
+  }
+  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGetLastError();
+    ucov_batch_destroy(b);
+    return c->fail(UCOV_EDEVICE, "graph instantiation");
+  }
+  *batch = b;
+  return UCOV_OK;
+}
+
+int ucov_batch_run(ucov_batch *b, ucov_report *rep) {
+  if (!b) return UCOV_EINVAL;
+  reset_report(rep);
+  ucov_ctx *c = b->parent, *w = b->w;
+  hipSetDevice(w->device);
+  w->stream = c->stream;  // the caller's stream
+  hipEventRecord(w->ev[kEvTune0], w->stream);
+  if (hipGraphLaunch(b->exec, w->stream) != hipSuccess) {
+    hipGetLastError();
+    return c->fail(UCOV_EDEVICE, "graph launch");
+  }
+  hipEventRecord(w->ev[kEvTune1], w->stream);
+  const int rc = batch_status(w, b->S, b->offs, rep);
+  if (rc != UCOV_OK) {
+    c->last_error = w->last_error;
+    return rc;
+  }
+  if (rep) {
+    hipMemcpy(&rep->alpha, w->alpha.p, sizeof(double), hipMemcpyDeviceToHost);
+    rep->n_pairs = b->first.n_pairs;
+    rep->ms_total = ev_ms(w, kEvTune0, kEvTune1);
   }
   return UCOV_OK;
 }
@@ -1595,6 +1864,18 @@ int ucov_screener_load(ucov_ctx *c, const char *path, ucov_screener *s) {
     off += p.bytes;
   }
   s->step = h.step;
+  return UCOV_OK;
+}
+
+int ucov_split_bf16_update(ucov_ctx *c, int64_t n, double *x, const double *r) {
+  if (!c) return UCOV_EINVAL;
+  if (n < 64 || n % 64 != 0 || !x || !r)
+    return c->fail(UCOV_EINVAL, "n must be a positive multiple of 64, x and r given");
+  hipSetDevice(c->device);
+  UCOV_TRY(ensure(c, c->m_split, split_bf16_scratch(n)));
+  split_bf16_update(n, x, r, c->m_split.p, c->stream);
+  UCOV_TRY(check_hip(c, "split-BF16 update"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "split-BF16 update");
   return UCOV_OK;
 }
 

@@ -93,7 +93,6 @@ struct SceneWork {
   int32_t *bin_cur;   // nbins
   int2 *pairs;        // n_pairs (slot a of camera i, slot b of camera k)
   // slots grouped by camera (camera-major bin construction)
-  int32_t *cam_iota;  // t: 0, 1, ..., t - 1
   int32_t *cam_keys;  // t: camera of each slot, sorted
   int32_t *cam_slots; // t: slots in camera order, ascending within a camera
   int64_t *cam_ptr;   // n + 1
@@ -130,7 +129,17 @@ void launch_point_blocks(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStr
 void launch_pair_count(const SceneDev &sc, SceneWork &w, hipStream_t st);
 // nzlist / nzcount from bin_cnt (needs bin_cur as scratch; leaves it zero)
 void launch_nonzero_bins(const SceneDev &sc, SceneWork &w, int64_t nbins, hipStream_t st);
-void launch_pair_fill(const SceneDev &sc, SceneWork &w, hipStream_t st);
+// Pairs into the list (capacity cap entries; nothing is written when the pair
+// count bin_ptr[nbins] exceeds it or *skip, when skip is given, is set).
+void launch_pair_fill(const SceneDev &sc, SceneWork &w, int64_t nbins, int64_t cap,
+                      const int32_t *skip, hipStream_t st);
+// A recorded launch sequence replayed on a scene whose camera-pair structure
+// grew: when the pair count (bin_ptr[nbins]) exceeds pairs_cap, every bin is
+// emptied (flag: one device int32) and UCOV_EINVAL reported; more non-empty
+// bins than nz_cap are reported as well.
+void launch_guard_pairs(SceneWork &w, int64_t nbins, int64_t pairs_cap, int32_t *flag,
+                        DevStatus *ds, hipStream_t st);
+void launch_check_nonzero(const SceneWork &w, int64_t nz_cap, DevStatus *ds, hipStream_t st);
 // Camera-major bins for scenes of at most kCamHistMax cameras (LDS counters
 // per camera): the camera lists, then every bin count (no prior zero fill),
 // then the pairs (fewer than 2^31 in all; else launch_pair_fill).
@@ -142,8 +151,8 @@ int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_
                         hipStream_t st);
 void launch_pair_count_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
                            hipStream_t st);
-void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams,
-                          hipStream_t st);
+void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams, int64_t nbins,
+                          int64_t cap, const int32_t *skip, hipStream_t st);
 void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st);
 // Orthonormal Q (Cholesky-QR2 of hc; skipped when hc is null and q is given),
 // the gauge weight alpha and the Jacobi scaling s.  diag(Z) comes from the
@@ -235,7 +244,10 @@ SpdPlan *spd_plan_create();
 void spd_plan_destroy(SpdPlan *p);
 // Builds the plan for these matrices (kept when they are the same as in the
 // last build); returns 0 or -1 on a HIP failure.
-int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st);
+// Products of a launch with fewer 64 x 64 tiles (summed over the scenes) than
+// `small` run on split 32 x 32 tiles.
+int spd_plan_build(SpdPlan *p, const SpdMat *mats, int count, hipStream_t st, int64_t small = 0);
+int64_t spd_plan_launches(const SpdPlan *p);
 void spd_plan_run(const SpdPlan *p, hipStream_t st);
 // Host-only check of the plan for matrices of sizes np: every access inside
 // its matrix or scratch, every column block factored once.  0 when it holds.
@@ -293,7 +305,7 @@ void mixed_initial_inverse(int64_t Np, const double *a, int64_t lda, float *a32,
 // a made symmetric from its lower triangle, x = (double) x32;
 void mixed_prepare(int64_t Np, double *a, int64_t lda, const float *x32, double *x,
                    hipStream_t st);
-// r = I - a x (FP64), sumsq[0] += |r|_F^2;
+// r = I - a x (FP64), sumsq[0] = |r|_F^2 (sumsq: Np + 1 doubles);
 void mixed_residual(int64_t Np, const double *a, int64_t lda, const double *x, double *r,
                     double *sumsq, hipStream_t st);
 // x += x r with the correction on FP32 MFMA.
@@ -302,10 +314,12 @@ void mixed_update(int64_t Np, double *x, const double *r, float *x32, float *r32
 
 // Split-BF16 correction (split_bf16_kernels.hip): x (n x n, leading
 // dimension n, n a multiple of 64) += x r with the product formed from
-// kSplitSlices 8-bit slices of x (per row) and r (per column) on BF16 MFMA,
-// exact FP32 chunk sums accumulated in FP64; scratch: split_bf16_scratch(n)
-// bytes.
-constexpr int kSplitSlices = 3;
+// split_bf16_slices(n) 8-bit slices of x (per row) and r (per column) on BF16
+// MFMA, exact FP32 chunk sums accumulated in FP64: 3 slices up to
+// kSplitSmallN, 4 beyond (the product's error grows like sqrt(n) times the
+// slice truncation); scratch: split_bf16_scratch(n) bytes.
+constexpr int64_t kSplitSmallN = 8192;
+int split_bf16_slices(int64_t n);
 size_t split_bf16_scratch(int64_t n);
 void split_bf16_update(int64_t n, double *x, const double *r, void *scratch, hipStream_t st);
 

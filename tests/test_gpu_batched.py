@@ -176,3 +176,104 @@ def test_batched_errors_name_the_scene(ucov):
     views, _, _ = run(good)
     for s, v in zip(good, views):
         assert block_errors(v.cpu().numpy(), oracle_cov(s)["blocks"])[0] < 1e-6
+
+
+def test_tune_batched_then_solve(ucov):
+    """The batched tile-schedule tuning picks one of its candidates; the
+    batch solved with it agrees with the untuned schedule to rounding and
+    with the oracle."""
+    u, ctx = ucov
+    scenes = small_batch()
+    devs = [u.DeviceScene.from_scene(s) for s in scenes]
+    before, _, _ = ctx.camera_covariance_batched(devs)
+    before = [v.cpu().numpy() for v in before]
+    th, ms = ctx.tune_batched([9 * s.n_cams for s in scenes])
+    print(f"  batched threshold {th} ({ms:.3f} ms)", flush=True)
+    assert th in (0, 256, 1024, 4096, 1 << 40) and ms > 0.0
+    after, _, _ = ctx.camera_covariance_batched(devs)
+    for s, a, b in zip(scenes, after, before):
+        assert block_errors(a.cpu().numpy(), b)[0] < 1e-9
+        assert block_errors(a.cpu().numpy(), oracle_cov(s)["blocks"])[0] < 1e-6
+
+
+def test_batch_graph_replays_match_eager(ucov):
+    """A recorded batch (eager solve, then a captured graph) replays several
+    times, with other eager work and synchronisations in between: every
+    replay gives the eager call's blocks bit for bit."""
+    import torch
+    u, ctx = ucov
+    scenes = small_batch()
+    devs = [u.DeviceScene.from_scene(s) for s in scenes]
+    eager, _, _ = ctx.camera_covariance_batched(devs)
+    eager = torch.cat(eager).cpu()
+    b = ctx.batch(devs)
+    assert torch.equal(b.out.cpu(), eager)  # the eager solve inside create
+    other = u.DeviceScene.from_scene(sg.spiral_slab(33, n=50, m=3000))
+    for k in range(4):
+        b.out.zero_()
+        rep = b.run()
+        assert rep["ms_total"] > 0.0 and rep["bad_scene"] == -1
+        assert torch.equal(b.out.cpu(), eager), k
+        ctx.camera_covariance(other)  # eager work of the same context between replays
+        torch.cuda.synchronize()
+    b.close()
+
+
+def test_batch_graph_follows_new_values(ucov):
+    """Between replays the scenes' parameter values may change: a replay
+    after moving the cameras of one scene equals a fresh eager solve."""
+    import torch
+    u, ctx = ucov
+    scenes = small_batch()
+    devs = [u.DeviceScene.from_scene(s) for s in scenes]
+    b = ctx.batch(devs)
+    d = devs[2]
+    d.cams[:, 6] *= 1.02          # focal lengths
+    d.cams[:, 3:6] += 0.01        # centres
+    b.run()
+    eager, _, _ = ctx.camera_covariance_batched(devs)
+    assert torch.equal(b.out, torch.cat(eager))
+    b.close()
+
+
+def test_batch_graph_rejects_grown_structure(ucov):
+    """A replay whose scene gained camera pairs (an observation moved to a
+    point with more cameras) reports EINVAL without touching memory beyond its
+    buffers; restoring the scene makes the next replay good again."""
+    import torch
+    u, ctx = ucov
+    scenes = small_batch()
+    devs = [u.DeviceScene.from_scene(s) for s in scenes]
+    eager, _, _ = ctx.camera_covariance_batched(devs)
+    eager = torch.cat(eager)
+    b = ctx.batch(devs)
+    # in scene 1, move one observation of a 3-camera point to another
+    # 3-camera point that its camera does not see yet: pairs 6 + 6 -> 3 + 10
+    s = scenes[1]
+    cnt = np.bincount(s.obs_pt, minlength=s.n_pts)
+    three = np.flatnonzero(cnt == 3)
+    moved = None
+    for pa in three:
+        for pb in three:
+            if pa == pb:
+                continue
+            cams_b = set(s.obs_cam[s.obs_pt == pb].tolist())
+            for o in np.flatnonzero(s.obs_pt == pa):
+                if int(s.obs_cam[o]) not in cams_b:
+                    moved = (int(o), int(pb))
+                    break
+            if moved:
+                break
+        if moved:
+            break
+    assert moved is not None
+    op = s.obs_pt.copy()
+    op[moved[0]] = moved[1]
+    devs[1].obs_pt.copy_(torch.as_tensor(op, dtype=torch.int32))
+    with pytest.raises(u.UcovError) as e:
+        b.run()
+    assert e.value.kind == "EINVAL"
+    devs[1].obs_pt.copy_(torch.as_tensor(s.obs_pt, dtype=torch.int32))
+    b.run()
+    assert torch.equal(b.out, eager)
+    b.close()

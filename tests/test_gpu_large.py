@@ -90,6 +90,27 @@ def test_clustered3000_fp32_ns_stalls(ucov, large):
     assert e.value.kind == "ENOCONV"
 
 
+def test_clustered3000_bf16x_ns(ucov, large):
+    """The large scene in mixed precision with split-BF16 corrections, whose
+    error does not grow with K: the Newton-Schulz residual reaches the
+    tolerance, and every block matches the stored oracle blocks and the FP64
+    GPU path."""
+    u, ctx = ucov
+    s, d, cams, ref = large
+    print(f"clustered3000 split-BF16 Newton-Schulz n={s.n_cams}", flush=True)
+    got, rep = ctx.camera_covariance(d, precision=u.BF16X_NS)
+    print(f"  ns_iters {rep['ns_iters']} residual {rep['ns_residual']:.2e} "
+          f"dense stage {rep['ms_inverse']:.1f} ms", flush=True)
+    got = got.cpu().numpy()
+    fro, scaled = block_errors(got[cams], ref)
+    print(f"  sampled cameras fro {fro:.2e} scaled {scaled:.2e}", flush=True)
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    f64, _ = ctx.camera_covariance(d)
+    fro64, _ = block_errors(got, f64.cpu().numpy())
+    print(f"  every block against the FP64 path: fro {fro64:.2e}", flush=True)
+    assert fro64 < 1e-6, fro64
+
+
 def test_clustered3000(ucov, large):
     import torch
     u, ctx = ucov

@@ -57,12 +57,13 @@ def test_paper_gauge_full_medium_scene(ucov):
     assert fro < 1e-6, (fro, scaled)
 
 
+@pytest.mark.parametrize("prec", ["FP32_NS", "BF16X_NS"])
 @pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(4), lambda: sg.spiral_slab(8, n=60, m=3000)])
-def test_paper_gauge_mixed_precision(ucov, maker):
+def test_paper_gauge_mixed_precision(ucov, maker, prec):
     u, ctx = ucov
     s = maker()
     got, rep = ctx.camera_covariance(u.DeviceScene.from_scene(s), gauge=u.GAUGE_PAPER,
-                                     precision=u.FP32_NS)
+                                     precision=getattr(u, prec))
     fro, scaled = block_errors(got.cpu().numpy(), pg.camera_blocks(s))
     assert rep["ns_residual"] <= 1e-10 and fro < 1e-6, (fro, rep)
 

@@ -264,20 +264,41 @@ def test_errors(ucov):
         ctx.camera_covariance(dev(u, two))
     assert e.value.kind == "EGAUGE"
 
+    # a point behind one of its cameras: EINVAL naming one such observation
+    from failure_scenes import absurd_size, behind_camera, coincident_centres
+    behind, bad_obs = behind_camera()
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, behind))
+    assert e.value.kind == "EINVAL" and e.value.index in bad_obs
+
+    # a point seen only from two coincident centres: EPOINT naming the point
+    deg, jd = coincident_centres()
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, deg))
+    assert e.value.kind == "EPOINT" and e.value.index == jd
+
+    # a scene whose camera matrix cannot fit the device: ENOMEM before any launch
+    huge = absurd_size()
+    with pytest.raises(u.UcovError) as e:
+        ctx.camera_covariance(dev(u, huge))
+    assert e.value.kind == "ENOMEM"
+
     # the context still works after errors
     got, _ = ctx.camera_covariance(dev(u, s))
     ref = oracle_cov(s)["blocks"]
     assert block_errors(got.cpu().numpy(), ref)[0] < 1e-6
 
 
+@pytest.mark.parametrize("prec", ["FP32_NS", "BF16X_NS"])
 @pytest.mark.parametrize("maker", [lambda: sg.tiny_circle(5), lambda: sg.spiral_slab(13, n=150, m=15000),
                                    lambda: sg.spiral_slab(0)])
-def test_covariance_mixed_precision(ucov, maker):
-    """FP32 MFMA initial inverse + Newton-Schulz with FP64 residuals."""
+def test_covariance_mixed_precision(ucov, maker, prec):
+    """FP32 MFMA initial inverse + Newton-Schulz with FP64 residuals, the
+    corrections on FP32 MFMA or from split-BF16 products."""
     u, ctx = ucov
     s = maker()
-    print(f"mixed {s.name} n={s.n_cams}", flush=True)
-    got, rep = ctx.camera_covariance(dev(u, s), precision=u.FP32_NS)
+    print(f"mixed {prec} {s.name} n={s.n_cams}", flush=True)
+    got, rep = ctx.camera_covariance(dev(u, s), precision=getattr(u, prec))
     ref = oracle_cov(s)["blocks"]
     got = got.cpu().numpy()
     fro, scaled = block_errors(got, ref)
@@ -290,8 +311,9 @@ def test_covariance_mixed_precision(ucov, maker):
     assert fro64 < 1e-6, fro64
 
 
+@pytest.mark.parametrize("prec", ["FP32_NS", "BF16X_NS"])
 @pytest.mark.parametrize("N,kappa", [(576, 1e3), (1161, 1e5)])
-def test_pinv_known_spectrum_mixed(ucov, N, kappa):
+def test_pinv_known_spectrum_mixed(ucov, N, kappa, prec):
     import torch
     u, ctx = ucov
     rng = np.random.default_rng(N + 1)
@@ -302,9 +324,54 @@ def test_pinv_known_spectrum_mixed(ucov, N, kappa):
     Z = 0.5 * (Z + Z.T)
     ref = covariance.camera_blocks((R / lam) @ R.T)
     got, rep = ctx.pinv_blocks(torch.from_numpy(Z).cuda(), torch.from_numpy(Q0.copy()).cuda(),
-                               precision=u.FP32_NS)
+                               precision=getattr(u, prec))
     fro, scaled = block_errors(got.cpu().numpy(), ref)
     assert fro < 1e-15 * kappa * 1000, (fro, rep)
+
+
+def bound_exponents(a, axis):
+    """Per row (axis 1) or column (axis 0): the e with max |a| < 2^e."""
+    mx = np.abs(a).max(axis=axis)
+    e = np.zeros(mx.shape, np.int64)
+    nz = mx > 0
+    e[nz] = np.frexp(mx[nz])[1]  # mx = f 2^e with f in [0.5, 1)
+    return e, nz
+
+
+@pytest.mark.parametrize("n,seed", [(64, 1), (576, 2), (1152, 3), (8256, 4)])
+def test_split_bf16_product(ucov, n, seed):
+    """The split-BF16 correction x += x r alone against the FP64 product, on
+    matrices whose rows (of x) and columns (of r) span six orders of
+    magnitude: every entry within the slices' bound 2^(e_m + f_c - 8 S) n
+    (2^e_m, 2^f_c bounding row m of x and column c of r; S = 3 slices up to
+    n = 8192, 4 beyond), and far inside what one BF16 rounding of the
+    operands gives.  Beyond n = 2048 the reference is formed for 64 sampled
+    rows."""
+    import torch
+    u, ctx = ucov
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, n)) * 10.0 ** rng.uniform(-3, 3, n)[:, None]
+    R = rng.normal(size=(n, n)) * 1e-4 * 10.0 ** rng.uniform(-3, 3, n)[None, :]
+    X[5] = 0.0   # an all-zero row and column
+    R[:, 7] = 0.0
+    rows = np.arange(n) if n <= 2048 else np.unique(np.r_[5, rng.choice(n, 63, replace=False)])
+    ref = X[rows] + X[rows] @ R
+    t = torch.from_numpy(X.T.copy()).cuda()  # row-major storage of the column-major X
+    ctx.split_bf16_update(t, torch.from_numpy(R.T.copy()).cuda())
+    got = t.cpu().numpy().T[rows]
+    S = 3 if n <= 8192 else 4
+    ex, _ = bound_exponents(X, 1)
+    er, _ = bound_exponents(R, 0)
+    bound = n * np.ldexp(1.0, ex[rows][:, None] + er[None, :] - 8 * S)
+    err = np.abs(got - ref)
+    print(f"  n={n}: max err / bound {np.max(err / bound):.3f}", flush=True)
+    assert np.all(err <= bound)
+    k5 = int(np.flatnonzero(rows == 5)[0])
+    assert np.all(got[k5] == 0.0) and np.array_equal(got[:, 7], X[rows, 7])
+    # one BF16 rounding of the operands (8 significant bits) is far worse
+    bf = lambda a: torch.from_numpy(a).float().bfloat16().double().numpy()  # noqa: E731
+    err_bf16 = np.abs(X[rows] + bf(X[rows]) @ bf(R) - ref)
+    assert np.median(err) < 1e-4 * np.median(err_bf16)
 
 
 def test_mixed_precision_reports_no_convergence(ucov):

@@ -220,35 +220,56 @@ def zii_from_features(F):
     return Z
 
 
-def screener_workload(ctx, jobs):
-    """Features and exact covariances (device tensors) of the scenes of the
-    given generator jobs, generated in parallel processes."""
+def screener_workload(ctx, jobs, count):
+    """Features and exact covariances (device tensors) of the first ``count``
+    cameras of the scenes of the given generator jobs (generated in parallel
+    processes); a scene the exact path rejects (a degenerate gauge or point)
+    is skipped, which the jobs' spare scenes make up for."""
+    import torch
     from scene_pool import generate
+    import paper_1808_02414_amd as u
     from paper_1808_02414_amd import screener as scr
-    F, S = [], []
+    F, S, have, skipped = [], [], 0, 0
     for s in generate(jobs):
-        f, c = scr.training_set(ctx, [s])
+        if have >= count:
+            continue
+        try:
+            f, c = scr.training_set(ctx, [s])
+        except u.UcovError as e:
+            assert e.kind in ("EGAUGE", "EPOINT"), e
+            skipped += 1
+            continue
         F.append(f)
         S.append(c)
+        have += f.shape[0]
+    assert have >= count, (have, count)
+    print(f"  {have} cameras, {skipped} generated scenes rejected by the exact path", flush=True)
+    return torch.cat(F)[:count].contiguous(), torch.cat(S)[:count].contiguous()
+
+
+def c5_set(ctx, seed0, n_tiny, n_spiral, n_clustered, clustered_kw):
+    """Cameras of the three scene recipes, exactly n_tiny, n_spiral and
+    n_clustered of each (spare scenes of every recipe make up for the rare
+    scene the exact path rejects)."""
     import torch
-    return torch.cat(F), torch.cat(S)
-
-
-def c5_jobs(seed0, n_tiny, n_spiral, clustered):
-    """Generator jobs of the three scene recipes (the large clustered scenes
-    first, so that they generate while the others do)."""
-    return ([("clustered", (seed0 + 1000 + k,), kw) for k, kw in enumerate(clustered)]
-            + [("spiral_slab", (seed0 + 500 + k,), {}) for k in range(n_spiral)]
-            + [("tiny_circle", (seed0 + k,), {}) for k in range(n_tiny)])
+    per = clustered_kw.get("cams", 3000)
+    kw = {k: v for k, v in clustered_kw.items() if k != "cams"}
+    parts = [screener_workload(ctx, [("clustered", (seed0 + 1000 + k,), kw)
+                                     for k in range(-(-n_clustered // per) + 1)], n_clustered),
+             screener_workload(ctx, [("spiral_slab", (seed0 + 500 + k,), {})
+                                     for k in range(n_spiral // 500 * 11 // 10 + 4)], n_spiral),
+             screener_workload(ctx, [("tiny_circle", (seed0 + k,), {}) for k in range(n_tiny // 10 + 100)],
+                               n_tiny)]
+    return torch.cat([p[0] for p in parts]), torch.cat([p[1] for p in parts])
 
 
 def test_trained_screener_gains_over_screening_without_it(ucov, tmp_path):
     """The learned screener at its stated size: trained on 200 000 cameras of
-    the tiny (6 000 scenes of 10 cameras), spiral (250 scenes of 500) and
-    clustered (5 scenes of 3 000) recipes, with exact covariances from the
-    library as labels, by the library's own kernels; evaluated on 10 000
-    held-out cameras (300 tiny scenes, 12 spiral scenes and one clustered
-    scene of 4 sites of 250 cameras).  Against what screening has without it
+    the tiny (60 000 cameras in scenes of 10), spiral (125 000 in scenes of
+    500) and clustered (15 000 in scenes of 3 000) recipes, with exact
+    covariances from the library as labels, by the library's own kernels;
+    evaluated on 10 000 held-out cameras (3 000 tiny, 6 000 spiral and 1 000 of
+    clustered scenes of 4 sites of 250 cameras).  Against what screening has without it
     -- the training-mean covariance and the block-diagonal estimate
     (Z_ii)^-1, which needs no inverse of Z but ignores the other cameras'
     uncertainty -- the network must be about three times more accurate
@@ -259,12 +280,12 @@ def test_trained_screener_gains_over_screening_without_it(ucov, tmp_path):
     from paper_1808_02414_amd import screener as scr
     u, ctx = ucov
     t0 = time.time()
-    F, S = screener_workload(ctx, c5_jobs(10000, 6000, 250, [{}] * 5))
+    F, S = c5_set(ctx, 10000, 60_000, 125_000, 15_000, {})
     print(f"  training cameras {F.shape[0]} ({time.time() - t0:.1f} s)", flush=True)
     assert F.shape[0] == 200_000
     t0 = time.time()
-    held_clustered = {"n_clusters": 4, "per_cluster": 250, "m": 170_000}
-    Fh, Sh = screener_workload(ctx, c5_jobs(90000, 300, 12, [held_clustered]))
+    held_clustered = {"n_clusters": 4, "per_cluster": 250, "m": 170_000, "cams": 1000}
+    Fh, Sh = c5_set(ctx, 90000, 3_000, 6_000, 1_000, held_clustered)
     print(f"  held-out cameras {Fh.shape[0]} ({time.time() - t0:.1f} s)", flush=True)
     assert Fh.shape[0] == 10_000
     t0 = time.time()

@@ -328,21 +328,17 @@ def test_input_errors():
     assert e.value.kind == "EPOINT" and e.value.index == j
 
     # a point seen by two cameras at the same centre has no depth information
-    cams = s.cams.copy()
-    pts = s.pts.copy()
-    j2 = int(s.obs_pt[0])
-    o2 = np.flatnonzero(s.obs_pt == j2)
-    c0, c1 = s.obs_cam[o2[0]], s.obs_cam[o2[1]]
-    keep = (s.obs_pt != j2) | np.isin(np.arange(s.n_obs), o2[:2])
-    cams_dup = np.vstack([cams, cams[c0]])  # a copy of camera c0 at the same centre
-    oc = s.obs_cam[keep].copy()
-    op = s.obs_pt[keep].copy()
-    oc[(op == j2) & (oc == c1)] = cams.shape[0]
-    # connect the copy through one more point so the scene stays valid otherwise
-    deg = sg.Scene(cams_dup, pts, np.append(oc, cams.shape[0]), np.append(op, (j2 + 1) % s.n_pts))
+    from failure_scenes import behind_camera, coincident_centres
+    deg, j2 = coincident_centres()
     with pytest.raises(OracleError) as e:
         camera_covariance(deg)
     assert e.value.kind == "EPOINT" and e.value.index == j2
+
+    # a point behind a camera that observes it: the first such observation
+    behind, bad = behind_camera()
+    with pytest.raises(OracleError) as e:
+        camera_covariance(behind)
+    assert e.value.kind == "EINVAL" and e.value.index == min(bad)
 
     # two disconnected halves: nullity 14, A is not positive definite
     a = sg.tiny_circle(18, n=5, m=60)
