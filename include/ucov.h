@@ -113,7 +113,15 @@ typedef struct {
   double tol;         /* Newton-Schulz stop: |I - A X|_F / sqrt(N) <= tol; 0 = default 1e-10 */
   double alpha;       /* gauge weight a; 0 = balanced automatic choice (UCOV_GAUGE_CAMERA only) */
   int32_t gauge;      /* UCOV_GAUGE_CAMERA (default) or UCOV_GAUGE_PAPER */
+  uint32_t flags;     /* UCOV_HOST_PTRS or 0 */
 } ucov_options;
+
+/* Options flag: the scene's arrays and the output of ucov_camera_covariance
+ * (and of its allocation-free variant) are HOST memory.  The library stages
+ * them through device buffers of its workspace (copies on the context's
+ * stream; the call returns with the output on the host).  The other entry
+ * points take device pointers only (UCOV_EINVAL with this flag). */
+#define UCOV_HOST_PTRS 1u
 
 typedef struct {
   double alpha;        /* gauge weight used */

@@ -36,9 +36,13 @@ class ScreenerStruct(ctypes.Structure):
                 ("step", ctypes.c_int64)]
 
 
+HOST_PTRS = 1
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("alpha", ctypes.c_double), ("gauge", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("alpha", ctypes.c_double), ("gauge", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class Report(ctypes.Structure):
@@ -266,6 +270,26 @@ class Context:
         sc = scene.struct()
         rc = self.lib.ucov_camera_covariance_noalloc(self.h, ctypes.byref(sc), ctypes.byref(opt),
                                                      out.data_ptr(), ctypes.byref(rep))
+        self._check(rc, rep)
+        return out, rep.as_dict()
+
+    def camera_covariance_host(self, scene, precision=FP64, alpha=0.0, gauge=GAUGE_CAMERA):
+        """``camera_covariance`` on a scene held in host memory (numpy arrays of
+        a ``scenegen.Scene``: cams, pts, obs_cam, obs_pt, obs_info): the library
+        stages it through device buffers (UCOV_HOST_PTRS).  Returns (n, 9, 9)
+        float64 numpy blocks and the report."""
+        arrs = [np.ascontiguousarray(scene.cams, np.float64), np.ascontiguousarray(scene.pts, np.float64),
+                np.ascontiguousarray(scene.obs_cam, np.int32), np.ascontiguousarray(scene.obs_pt, np.int32)]
+        info = None if scene.obs_info is None else np.ascontiguousarray(scene.obs_info, np.float64)
+        out = np.empty((arrs[0].shape[0], 9, 9), np.float64)
+        sc = Scene(arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0], arrs[0].ctypes.data,
+                   arrs[1].ctypes.data, arrs[2].ctypes.data, arrs[3].ctypes.data,
+                   None if info is None else info.ctypes.data)
+        opt = Options(precision, 0, 0.0, alpha, gauge, HOST_PTRS)
+        rep = Report()
+        self._stream()
+        rc = self.lib.ucov_camera_covariance(self.h, ctypes.byref(sc), ctypes.byref(opt),
+                                             out.ctypes.data, ctypes.byref(rep))
         self._check(rc, rep)
         return out, rep.as_dict()
 

@@ -106,6 +106,7 @@ struct ucov_ctx {
   Buf zdiag, hc, q, s, alpha, amat, tmat;
   Buf m_a32, m_x32, m_r32, m_d32, m_tmp32, m_x64, m_r64, m_sum;  // mixed precision
   Buf m_split;  // split-BF16 slices and exponents
+  Buf hp_cams, hp_pts, hp_oc, hp_op, hp_info, hp_out;  // staging of UCOV_HOST_PTRS calls
   // batched calls: the concatenated scenes, their tables and per-scene status
   Buf b_cams, b_pts, b_info, b_oc, b_op, b_cam_scene, b_tab, b_ds, b_scratch;
   SpdPlan *plan = nullptr;  // batched inverse plan, kept while the batch is unchanged
@@ -476,13 +477,21 @@ void fill_defaults(const ucov_options *opt, ucov_options &o) {
   o.tol = 1e-10;
   o.alpha = 0.0;
   o.gauge = UCOV_GAUGE_CAMERA;
+  o.flags = 0;
   if (opt) {
     o.precision = opt->precision;
     if (opt->max_iter > 0) o.max_iter = opt->max_iter;
     if (opt->tol > 0) o.tol = opt->tol;
     o.alpha = opt->alpha;
     o.gauge = opt->gauge;
+    o.flags = opt->flags;
   }
+}
+
+// Entry points that take device pointers only reject UCOV_HOST_PTRS.
+int device_only(ucov_ctx *c, const ucov_options &o) {
+  if (o.flags == 0) return UCOV_OK;
+  return c->fail(UCOV_EINVAL, "this entry point takes device pointers only (flags must be 0)");
 }
 
 // Mixed-precision inverse of A_s (Np x Np in c->amat): FP32 MFMA Cholesky
@@ -627,7 +636,8 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->cam_keys, &c->cam_slots, &c->cam_ptr, &c->cam_tmp,
                  &c->zdiag, &c->hc, &c->q, &c->s, &c->alpha, &c->amat, &c->tmat,
                  &c->m_a32, &c->m_x32, &c->m_r32, &c->m_d32, &c->m_tmp32, &c->m_x64, &c->m_r64,
-                 &c->m_sum, &c->m_split, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
+                 &c->m_sum, &c->m_split, &c->hp_cams, &c->hp_pts, &c->hp_oc, &c->hp_op,
+                 &c->hp_info, &c->hp_out, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
                  &c->mlp_ws, &c->mlp_grad, &c->f_lab, &c->f_zero, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
                  &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
@@ -696,14 +706,58 @@ int ucov_gauge_basis(ucov_ctx *c, const ucov_scene *scene, double *hc, double *q
 
 namespace {
 
+int camera_covariance_dev(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
+                          double *cov_out, ucov_report *rep);
+
+// UCOV_HOST_PTRS: the scene and the output staged through device buffers.
 int camera_covariance_impl(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
                            double *cov_out, ucov_report *rep) {
+  if (!c) return UCOV_EINVAL;
+  if (!opt || !(opt->flags & UCOV_HOST_PTRS))
+    return camera_covariance_dev(c, scene, opt, cov_out, rep);
+  if (opt->flags & ~UCOV_HOST_PTRS) return c->fail(UCOV_EINVAL, "unknown flags");
+  UCOV_TRY(check_scene(c, scene));
+  if (!cov_out) return c->fail(UCOV_EINVAL, "NULL output");
+  hipSetDevice(c->device);
+  const int64_t n = scene->n_cams, m = scene->n_pts, t = scene->n_obs;
+  UCOV_TRY(ensure(c, c->hp_cams, 8 * 9 * (size_t)n));
+  UCOV_TRY(ensure(c, c->hp_pts, 8 * 3 * (size_t)m));
+  UCOV_TRY(ensure(c, c->hp_oc, 4 * (size_t)t));
+  UCOV_TRY(ensure(c, c->hp_op, 4 * (size_t)t));
+  if (scene->obs_info) UCOV_TRY(ensure(c, c->hp_info, 8 * 3 * (size_t)t));
+  UCOV_TRY(ensure(c, c->hp_out, 8 * 81 * (size_t)n));
+  hipStream_t st = c->stream;
+  if (hipMemcpyAsync(c->hp_cams.p, scene->cams, 8 * 9 * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->hp_pts.p, scene->pts, 8 * 3 * m, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->hp_oc.p, scene->obs_cam, 4 * t, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->hp_op.p, scene->obs_pt, 4 * t, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (scene->obs_info &&
+       hipMemcpyAsync(c->hp_info.p, scene->obs_info, 8 * 3 * t, hipMemcpyHostToDevice, st) != hipSuccess))
+    return check_hip(c, "copying the scene to the device");
+  ucov_scene d = *scene;
+  d.cams = as<double>(c->hp_cams);
+  d.pts = as<double>(c->hp_pts);
+  d.obs_cam = as<int32_t>(c->hp_oc);
+  d.obs_pt = as<int32_t>(c->hp_op);
+  d.obs_info = scene->obs_info ? as<double>(c->hp_info) : nullptr;
+  ucov_options o = *opt;
+  o.flags = 0;
+  UCOV_TRY(camera_covariance_dev(c, &d, &o, as<double>(c->hp_out), rep));
+  if (hipMemcpyAsync(cov_out, c->hp_out.p, 8 * 81 * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_hip(c, "copying the blocks to the host");
+  return UCOV_OK;
+}
+
+int camera_covariance_dev(ucov_ctx *c, const ucov_scene *scene, const ucov_options *opt,
+                          double *cov_out, ucov_report *rep) {
   if (!c) return UCOV_EINVAL;
   UCOV_TRY(check_scene(c, scene));
   UCOV_TRY(check_fits(c, scene));
   if (!cov_out) return c->fail(UCOV_EINVAL, "NULL output");
   ucov_options o;
   fill_defaults(opt, o);
+  UCOV_TRY(device_only(c, o));
   if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS && o.precision != UCOV_BF16X_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   if (o.gauge != UCOV_GAUGE_CAMERA && o.gauge != UCOV_GAUGE_PAPER)
@@ -765,6 +819,7 @@ int ucov_pinv_blocks(ucov_ctx *c, int64_t n, const double *z, int64_t ldz, const
     return c->fail(UCOV_EINVAL, "bad dense arguments");
   ucov_options o;
   fill_defaults(opt, o);
+  UCOV_TRY(device_only(c, o));
   if (o.precision != UCOV_FP64 && o.precision != UCOV_FP32_NS && o.precision != UCOV_BF16X_NS)
     return c->fail(UCOV_EINVAL, "unknown precision");
   hipSetDevice(c->device);
@@ -804,6 +859,7 @@ int ucov_full_covariance(ucov_ctx *c, const ucov_scene *scene, const ucov_option
   if (cam_cov && ldc < N) return c->fail(UCOV_EINVAL, "bad leading dimension of cam_cov");
   ucov_options o;
   fill_defaults(opt, o);
+  UCOV_TRY(device_only(c, o));
   if (o.precision != UCOV_FP64)
     return c->fail(UCOV_EINVAL, "the whole covariance supports UCOV_FP64 only");
   if (o.gauge != UCOV_GAUGE_CAMERA && o.gauge != UCOV_GAUGE_PAPER)
@@ -1185,6 +1241,7 @@ int ucov_camera_covariance_batched(ucov_ctx *c, int32_t n_scenes, const ucov_sce
   if (n_scenes < 1 || !scenes || !cov_out) return c->fail(UCOV_EINVAL, "bad batch arguments");
   ucov_options o;
   fill_defaults(opt, o);
+  UCOV_TRY(device_only(c, o));
   if (o.precision != UCOV_FP64 || o.gauge != UCOV_GAUGE_CAMERA)
     return c->fail(UCOV_EINVAL, "batched calls support UCOV_FP64 with UCOV_GAUGE_CAMERA only");
   const int S = n_scenes;

@@ -214,6 +214,30 @@ def test_covariance_full_medium_scene(ucov):
 
 
 @pytest.mark.parametrize("gauge", ["camera", "paper"])
+def test_host_pointers(ucov):
+    """UCOV_HOST_PTRS: a scene in host memory and host output give the device
+    path's blocks bit for bit; the flag is refused where only device pointers
+    are taken."""
+    import ctypes
+    import torch
+    u, ctx = ucov
+    s = sg.spiral_slab(15, n=70, m=4000, with_info=True)
+    host, rep = ctx.camera_covariance_host(s)
+    dev_out, _ = ctx.camera_covariance(dev(u, s))
+    assert np.array_equal(host, dev_out.cpu().numpy())
+    assert block_errors(host, oracle_cov(s)["blocks"])[0] < 1e-6
+    from paper_1808_02414_amd import _binding as b
+    d = dev(u, sg.tiny_circle(3))
+    arr = (b.Scene * 1)(d.struct())
+    out = torch.empty((10, 9, 9), dtype=torch.float64, device="cuda")
+    opt = b.Options(b.FP64, 0, 0.0, 0.0, b.GAUGE_CAMERA, b.HOST_PTRS)
+    rep = b.Report()
+    rc = ctx.lib.ucov_camera_covariance_batched(ctx.h, 1, arr, ctypes.byref(opt), out.data_ptr(),
+                                                None, ctypes.byref(rep))
+    assert rc == b.EINVAL
+
+
+@pytest.mark.parametrize("gauge", ["camera", "paper"])
 def test_repeat_calls_bitwise_equal(ucov, gauge):
     """Repeated calls give the same bits: the camera-pair bins are filled in a
     fixed order and every floating-point sum runs in a fixed order."""
