@@ -213,7 +213,6 @@ def test_covariance_full_medium_scene(ucov):
     assert fro < 1e-6, (fro, scaled)
 
 
-@pytest.mark.parametrize("gauge", ["camera", "paper"])
 def test_host_pointers(ucov):
     """UCOV_HOST_PTRS: a scene in host memory and host output give the device
     path's blocks bit for bit; the flag is refused where only device pointers
