@@ -73,9 +73,9 @@ DENSE_SOURCE = os.path.join(ROOT, "paper_1808_02414_amd", "csrc", "dense_kernels
 
 def recorded_traffic(workload):
     """HBM bytes per step of the dense stage from the committed counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there
-    are none for this workload or the dense kernels have changed since they
-    were taken."""
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy) and the tile threshold
+    they were taken with, or None when there are none for this workload or
+    the dense kernels have changed since they were taken."""
     try:
         text = open(traffic_profile(workload)).read()
         src = hashlib.sha256(open(DENSE_SOURCE, "rb").read()).hexdigest()
@@ -83,9 +83,22 @@ def recorded_traffic(workload):
         return None
     t = re.search(r"traffic_bytes_per_step: (\d+)", text)
     h = re.search(r"dense_kernels_sha256: (\w+)", text)
+    th = re.search(r"tile_threshold: (\d+)", text)
     if not (t and h) or h.group(1) != src:
         return None
-    return int(t.group(1))
+    return int(t.group(1)), int(th.group(1)) if th else DEFAULT_TILE_THRESHOLD
+
+
+def recorded_traffic_for(args, np_pad):
+    """The recorded traffic when the counters were taken with the tile
+    schedule this run uses (the single-scene FP64 path only), else None."""
+    if args.workload == "batch256" or args.precision != "fp64":
+        return None
+    rec = recorded_traffic(args.workload)
+    if rec is None:
+        return None
+    used = getattr(args, "tuned_threshold", None) or DEFAULT_TILE_THRESHOLD
+    return rec[0] if tile_schedule(np_pad, used) == tile_schedule(np_pad, rec[1]) else None
 
 
 def _threads():
@@ -337,13 +350,9 @@ def main():
                    "launch": "graph replay" if args.graph else "eager"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     # the counters were taken with the default tile schedule
-                     "traffic": (recorded_traffic(args.workload)
-                                 if args.workload != "batch256" and args.precision == "fp64"
-                                 and tile_schedule(np_pad, getattr(args, "tuned_threshold",
-                                                                   DEFAULT_TILE_THRESHOLD))
-                                 == tile_schedule(np_pad, DEFAULT_TILE_THRESHOLD) else None),
-                     "kernel": "dense inverse stage (k_leaf_mfma + k_gemm64/32s + k_gemm64/32s_pair), "
+                     # counters taken with the same tile schedule, else null
+                     "traffic": recorded_traffic_for(args, np_pad),
+                     "kernel": "dense inverse stage (k_leaf_mfma + k_gemm128/64/32s + their _pair launches), "
                                "2N^3/3 flops per scene; traffic in bytes per step"},
         "stages_ms": stages,
         "n_pairs": int(reps[-1]["n_pairs"]),

@@ -415,30 +415,43 @@ int ucov_mlp_train(ucov_ctx *ctx, float *params, float *adam_m, float *adam_v, i
                    const float *in_mean, const float *in_std, const float *target,
                    float *losses);
 
-/* Training labels: for each of n covariance blocks (n x 81 float64,
- * row-major) the 45 log-Cholesky parameters of D^-1 Sigma D^-1 = L L^T (log
- * L_aa on the diagonal, L_ab below it, row-major lower triangle), D = scale
- * (9 float64), standardised as (p - out_mean) / out_std.  UCOV_EINVAL if a
- * block is not positive definite (bad_index: the block). */
-int ucov_screener_labels(ucov_ctx *ctx, int64_t n, const double *cov, const double *scale,
-                         const float *out_mean, const float *out_std, float *labels);
+/* The label scale.  Each camera's covariance is measured against its
+ * block-diagonal estimate (Z_ii)^-1, which its own features determine: b_a =
+ * sqrt(((Z_ii)^-1)_aa) (a = 0..8), with Z_ii rebuilt from the camera's first
+ * 45 features (the correlation matrix must be positive definite), and the
+ * per-camera scale is D_a = scale_a b_a, scale (9 float64) a training-set
+ * statistic (ucov_screener_stats).  The normalised covariance is
+ * D^-1 Sigma D^-1. */
 
-/* The inverse map: network outputs y (n x 45) -> covariance blocks D L L^T D
- * (n x 81, may be NULL) and the spread trace(L L^T) of the normalised
- * covariance (n, may be NULL). */
-int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const double *scale,
-                             const float *out_mean, const float *out_std, double *cov,
-                             double *spread);
+/* Training labels: for each of n covariance blocks (n x 81 float64,
+ * row-major) with the features of the same cameras (n x 55 float32), the 45
+ * log-Cholesky parameters of the normalised covariance D^-1 Sigma D^-1 =
+ * L L^T (log L_aa on the diagonal, L_ab below it, row-major lower triangle),
+ * standardised as (p - out_mean) / out_std.  UCOV_EINVAL if a block or a
+ * camera's Z_ii correlation matrix is not positive definite (bad_index: the
+ * camera). */
+int ucov_screener_labels(ucov_ctx *ctx, int64_t n, const double *cov, const float *feat,
+                         const double *scale, const float *out_mean, const float *out_std,
+                         float *labels);
+
+/* The inverse map: network outputs y (n x 45) and the cameras' features
+ * (n x 55) -> covariance blocks D L L^T D (n x 81, may be NULL) and the
+ * spread trace(L L^T) of the normalised covariance (n, may be NULL).
+ * UCOV_EINVAL if a camera's Z_ii correlation matrix is not positive
+ * definite. */
+int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const float *feat,
+                             const double *scale, const float *out_mean, const float *out_std,
+                             double *cov, double *spread);
 
 /* Standardisation statistics of a training set of n >= 2 cameras: feat
  * (n x 55) and their exact covariance blocks cov (n x 81).  in_mean, in_std
  * (55 each): per feature the mean and the standard deviation (n - 1 in the
- * denominator, at least 1e-6); scale (9): per parameter the square root of
- * the lower median (rank (n - 1) / 2 ascending) of its variance over the
- * blocks; out_mean, out_std (45 each): mean and standard deviation of the
- * labels of ucov_screener_labels taken with out_mean 0 and out_std 1.  Every
- * sum runs in a fixed order (the same bits on every call).  UCOV_EINVAL if a
- * block is not positive definite. */
+ * denominator, at least 1e-6); scale (9): per parameter a the square root of
+ * the lower median (rank (n - 1) / 2 ascending) over the blocks of the
+ * variance ratio Sigma_aa / b_a^2; out_mean, out_std (45 each): mean and
+ * standard deviation of the labels of ucov_screener_labels taken with
+ * out_mean 0 and out_std 1.  Every sum runs in a fixed order (the same bits
+ * on every call).  UCOV_EINVAL if a block is not positive definite. */
 int ucov_screener_stats(ucov_ctx *ctx, int64_t n, const float *feat, const double *cov,
                         float *in_mean, float *in_std, double *scale, float *out_mean,
                         float *out_std);

@@ -20,9 +20,15 @@ Everything here is plain FP64 numpy, written for checking, not speed:
       between its viewing ray to the point and the ray of any other camera of
       that point's track;
     - 1: log(1 + number of other cameras that share a point with it).
+* ``zii_from_features`` / ``block_scale``: Z_ii rebuilt from its 45
+  features, and b = sqrt(diag((Z_ii)^-1)), the standard deviations of the
+  block-diagonal estimate (its correlation matrix taken with a ridge of 1e-6),
+  which set each camera's label scale D = s b;
+  ``label_scale``: s_a = sqrt of the lower median over a training set of the
+  variance ratio Sigma_aa / b_a^2.
 * ``log_cholesky`` / ``from_log_cholesky``: Sigma~ = D^-1 Sigma D^-1 = L L^T,
   parameters (log L_aa on the diagonal, L_ab below it) in row-major
-  lower-triangular order.
+  lower-triangular order; D one 9-vector, or one per camera.
 * ``mlp_forward`` / ``mlp_backward``: 55 -> 256 -> 256 -> 256 -> 45, ReLU
   between layers, linear output, mean squared error over batch and outputs.
   Parameters are one flat vector: for each layer W (out x in, row-major)
@@ -134,9 +140,58 @@ def camera_features(scene) -> np.ndarray:
 # covariance <-> log-Cholesky parameters
 # ---------------------------------------------------------------------------
 
+def zii_from_features(F: np.ndarray) -> np.ndarray:
+    """(k, >= 45) features -> (k, 9, 9) Z_ii: the diagonal from its log10, the
+    off-diagonal entries from the correlations times sqrt(Z_aa Z_bb)."""
+    F = np.asarray(F, np.float64)
+    Z = np.zeros((F.shape[0], 9, 9))
+    d = np.zeros((F.shape[0], 9))
+    k = 0
+    for a in range(9):
+        for b in range(a, 9):
+            if a == b:
+                d[:, a] = 10.0 ** F[:, k]
+            k += 1
+    k = 0
+    for a in range(9):
+        for b in range(a, 9):
+            Z[:, a, b] = Z[:, b, a] = d[:, a] if a == b else F[:, k] * np.sqrt(d[:, a] * d[:, b])
+            k += 1
+    return Z
+
+
+SCALE_RIDGE = 1e-6
+
+
+def block_scale(F: np.ndarray) -> np.ndarray:
+    """(k, 9): b_a = sqrt(((Z_ii)^-1)_aa), Z_ii rebuilt from the features,
+    with SCALE_RIDGE added to the diagonal of its correlation matrix C
+    (Z_ii = diag(d)^1/2 C diag(d)^1/2, so ((Z_ii)^-1)_aa = (C^-1)_aa / d_a):
+    the features hold C rounded to FP32, which the ridge keeps positive
+    definite."""
+    Z = zii_from_features(F)
+    d = np.diagonal(Z, axis1=1, axis2=2)
+    C = Z / np.sqrt(d[:, :, None] * d[:, None, :]) + SCALE_RIDGE * np.eye(9)
+    return np.sqrt(np.diagonal(np.linalg.inv(C), axis1=1, axis2=2) / d)
+
+
+def label_scale(S: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """(9,): per parameter a, the square root of the lower median (the value
+    of rank (k - 1) / 2 ascending) of Sigma_aa / b_a^2 over the k blocks."""
+    r = np.sort(np.diagonal(S, axis1=1, axis2=2) / block_scale(F) ** 2, axis=0)
+    return np.sqrt(r[(S.shape[0] - 1) // 2])
+
+
+def _per_block(D: np.ndarray, k: int) -> np.ndarray:
+    D = np.asarray(D, np.float64)
+    return np.broadcast_to(D, (k, 9)) if D.ndim == 1 else D
+
+
 def log_cholesky(S: np.ndarray, D: np.ndarray) -> np.ndarray:
-    """(k, 9, 9) covariances -> (k, 45) parameters of D^-1 S D^-1."""
-    St = S / (D[None, :, None] * D[None, None, :])
+    """(k, 9, 9) covariances -> (k, 45) parameters of D^-1 S D^-1 (D: (9,) or
+    (k, 9))."""
+    D = _per_block(D, S.shape[0])
+    St = S / (D[:, :, None] * D[:, None, :])
     L = np.linalg.cholesky(St)
     out = np.zeros((S.shape[0], N_OUT))
     k = 0
@@ -149,6 +204,7 @@ def log_cholesky(S: np.ndarray, D: np.ndarray) -> np.ndarray:
 
 def from_log_cholesky(P: np.ndarray, D: np.ndarray) -> np.ndarray:
     """(k, 45) parameters -> (k, 9, 9) covariances D L L^T D."""
+    D = _per_block(D, P.shape[0])
     L = np.zeros((P.shape[0], 9, 9))
     k = 0
     for a in range(9):
@@ -156,7 +212,7 @@ def from_log_cholesky(P: np.ndarray, D: np.ndarray) -> np.ndarray:
             L[:, a, b] = np.exp(P[:, k]) if a == b else P[:, k]
             k += 1
     St = L @ np.transpose(L, (0, 2, 1))
-    return St * (D[None, :, None] * D[None, None, :])
+    return St * (D[:, :, None] * D[:, None, :])
 
 
 # ---------------------------------------------------------------------------

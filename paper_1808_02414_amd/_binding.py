@@ -114,8 +114,8 @@ def load(path: str = LIB_PATH):
         "ucov_mlp_gradient": (ctypes.c_int, [P, P, I64, P, P, P, P, P, P]),
         "ucov_mlp_train": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_float, I64, I64, P, P, P,
                                           P, P]),
-        "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P]),
-        "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
+        "ucov_screener_labels": (ctypes.c_int, [P, I64, P, P, P, P, P, P]),
+        "ucov_screener_covariance": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P]),
         "ucov_plan_check": (ctypes.c_int, [P, I32, P]),
         "ucov_split_bf16_update": (ctypes.c_int, [P, I64, P, P]),
         "ucov_set_dense_threshold": (ctypes.c_int, [P, I64, I64]),
@@ -535,14 +535,15 @@ class Context:
             losses.data_ptr()))
         return losses
 
-    def screener_labels(self, cov, scale, out_mean, out_std):
+    def screener_labels(self, cov, features, scale, out_mean, out_std):
+        """Standardised log-Cholesky labels (n, 45) of covariances (n, 9, 9)
+        normalised by each camera's scale (from its features (n, 55))."""
         torch = self.torch
         n = cov.shape[0]
         lab = torch.empty((n, N_OUTPUTS), dtype=torch.float32, device=cov.device)
         self._stream()
-        rep = Report()
-        rep.bad_index = -1
         rc = self.lib.ucov_screener_labels(self.h, n, self._dev(cov, torch.float64),
+                                           self._dev(features, torch.float32),
                                            self._dev(scale, torch.float64),
                                            self._dev(out_mean, torch.float32),
                                            self._dev(out_std, torch.float32), lab.data_ptr())
@@ -600,17 +601,18 @@ class Context:
         self._check(self.lib.ucov_screener_load(self.h, os.fsencode(path), ctypes.byref(st)))
         return t, int(st.step)
 
-    def screener_covariance(self, y, scale, out_mean, out_std):
-        """Predicted (n, 9, 9) covariances and (n,) spreads from network outputs."""
+    def screener_covariance(self, y, features, scale, out_mean, out_std):
+        """Predicted (n, 9, 9) covariances and (n,) spreads from network
+        outputs y (n, 45) and the cameras' features (n, 55)."""
         torch = self.torch
         n = y.shape[0]
         cov = torch.empty((n, 9, 9), dtype=torch.float64, device=y.device)
         spread = torch.empty(n, dtype=torch.float64, device=y.device)
         self._stream()
         self._check(self.lib.ucov_screener_covariance(
-            self.h, n, self._dev(y, torch.float32), self._dev(scale, torch.float64),
-            self._dev(out_mean, torch.float32), self._dev(out_std, torch.float32),
-            cov.data_ptr(), spread.data_ptr()))
+            self.h, n, self._dev(y, torch.float32), self._dev(features, torch.float32),
+            self._dev(scale, torch.float64), self._dev(out_mean, torch.float32),
+            self._dev(out_std, torch.float32), cov.data_ptr(), spread.data_ptr()))
         return cov, spread
 
 

@@ -20,6 +20,7 @@
 // (v_mfma_f32_16x16x4f32) for the initial inverse of the mixed path, which
 // Newton-Schulz steps with FP64 residuals then refine (see ucov_api.hip).
 #include <algorithm>
+#include <type_traits>
 
 #include <string>
 #include <vector>
@@ -76,8 +77,11 @@ enum KMode { kFull = 0, kLeN = 1, kGeN = 2, kLeM = 3, kGeMN = 4 };
 //   kLeM  k < (tile_m + 1) * 64  (A lower triangular)
 //   kGeMN k >= max(tile_m, tile_n) * 64  (A^T B with A, B lower triangular)
 // Measured on MI355X: single-buffered LDS with a register prefetch and 4
-// waves/SIMD occupancy beats double buffering, larger tiles and die-aware
-// tile orders for every product shape of the recursion.
+// waves/SIMD occupancy beats double buffering and die-aware tile orders for
+// these tiles.  Products large enough for at least kBigTiles tiles of
+// 128 x 128 run on the 8-wave kernel below instead (square FP64 products:
+// 60-65 against 48-50 TFLOP/s from n = 3456 up; at n = 2304 the 64 x 64
+// tiles win, 46 against 42).
 // ---------------------------------------------------------------------------
 constexpr int kKc = 16;  // K chunk staged in LDS
 constexpr int kPad = 4;  // row padding of the LDS tiles
@@ -176,6 +180,142 @@ __device__ inline void gemm_tile(const GemmArgs<T> &g, int tm, int tn) {
         *pc = g.beta == T(0) ? x : x + g.beta * (*pc);
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 products on 128 x 128 tiles: 8 waves per workgroup, each computing a
+// 32 x 64 part (2 x 4 MFMA blocks), the same 16-deep K chunks as above.  A
+// product of M x N x K on 64 x 64 tiles moves about M N K / 4 bytes past the
+// L2 (each tile streams its own panels); 128 x 128 tiles halve that, which
+// on the large products raises the MFMA rate from ~50 to ~64 TFLOP/s.
+//
+// M and N are multiples of 64, so in the last tile row (column) the second
+// half may lie outside the product: its loads are redirected to the first
+// half (in bounds, the results discarded) and its stores skipped.  The
+// semantics are those of the 64 x 64 tiles exactly: the K ranges of
+// triangular operands are cut at 128 granularity, and every element of a
+// 64 x 64 block strictly above the diagonal of a triangular operand is read
+// as zero (those blocks are never written by the recursion and may hold the
+// original matrix); LOWER writes the 64 x 64 blocks on or below the
+// diagonal only.
+// ---------------------------------------------------------------------------
+constexpr int kBig = 128;
+
+template <bool AT, bool BT, bool LOWER>
+__device__ inline void gemm_tile128(const GemmArgs<double> &g, int tm, int tn) {
+  typedef Mfma<double> MF;
+  if (LOWER && tn > tm) return;
+  const int64_t M = g.M, N = g.N, K = g.K, lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+  const double *__restrict__ A = g.A;
+  const double *__restrict__ B = g.B;
+  double *__restrict__ C = g.C;
+  const int kmode = g.kmode;
+  int64_t kb = 0, ke = K;
+  if (kmode == kLeN) ke = min(K, (int64_t)(tn + 1) * kBig);
+  else if (kmode == kGeN) kb = (int64_t)tn * kBig;
+  else if (kmode == kLeM) ke = min(K, (int64_t)(tm + 1) * kBig);
+  else if (kmode == kGeMN) kb = (int64_t)max(tm, tn) * kBig;
+
+  __shared__ double As[kKc][kBig + kPad];
+  __shared__ double Bs[kKc][kBig + kPad];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;  // wave part: rows 32 wm.., columns 64 wn..
+  MF::acc_t acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = MF::zero();
+
+  // loaders, 4 consecutive elements per thread and chunk
+  const int lt_k = tid >> 5, lt_m = (tid & 31) * 4;  // K-major tile (M contiguous): 16 x 128
+  const int lc_m = tid >> 2, lc_k = (tid & 3) * 4;   // M-major tile (K contiguous): 128 x 16
+  const int64_t m0 = (int64_t)tm * kBig, n0 = (int64_t)tn * kBig;
+  const int a_x = AT ? lc_m : lt_m, b_x = BT ? lt_m : lc_m;  // tile row of A / column of B
+  const int a_src = m0 + a_x < M ? a_x : a_x - 64;           // in bounds
+  const int b_src = n0 + b_x < N ? b_x : b_x - 64;
+  const double *pa = AT ? A + lc_k + (m0 + a_src) * lda : A + m0 + a_src + lt_k * lda;
+  const double *pb = BT ? B + n0 + b_src + lt_k * ldb : B + lc_k + (n0 + b_src) * ldb;
+  // 64-block of the row of A / column of B this thread loads, for the masks
+  const int64_t a_blk = (m0 + a_x) >> 6, b_blk = (n0 + b_x) >> 6;
+  const bool a_tri = kmode == kLeM || kmode == kGeMN;
+  const bool b_tri = kmode == kLeN || kmode == kGeN || kmode == kGeMN;
+  double ra[4], rb[4];
+  auto load = [&](int64_t k0) {
+    const double *qa = AT ? pa + k0 : pa + k0 * lda;
+    const double2 a01 = *reinterpret_cast<const double2 *>(qa);
+    const double2 a23 = *reinterpret_cast<const double2 *>(qa + 2);
+    ra[0] = a01.x; ra[1] = a01.y; ra[2] = a23.x; ra[3] = a23.y;
+    const double *qb = BT ? pb + k0 * ldb : pb + k0;
+    const double2 b01 = *reinterpret_cast<const double2 *>(qb);
+    const double2 b23 = *reinterpret_cast<const double2 *>(qb + 2);
+    rb[0] = b01.x; rb[1] = b01.y; rb[2] = b23.x; rb[3] = b23.y;
+    // the 4 elements share their K block and their row / column block
+    const int64_t ka = (k0 + (AT ? lc_k : lt_k)) >> 6, kbk = (k0 + (BT ? lt_k : lc_k)) >> 6;
+    const bool za = a_tri && (kmode == kLeM ? ka > a_blk : ka < a_blk);
+    const bool zb = b_tri && (kmode == kLeN ? kbk > b_blk : kbk < b_blk);
+    if (za) ra[0] = ra[1] = ra[2] = ra[3] = 0.0;
+    if (zb) rb[0] = rb[1] = rb[2] = rb[3] = 0.0;
+  };
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kKc) {
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (AT) As[lc_k + v][lc_m] = ra[v];
+      else As[lt_k][lt_m + v] = ra[v];
+      if (BT) Bs[lt_k][lt_m + v] = rb[v];
+      else Bs[lc_k + v][lc_m] = rb[v];
+    }
+    __syncthreads();
+    if (k0 + kKc < ke) load(k0 + kKc);  // prefetch the next chunk during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < kKc / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const int c = lane & 15;
+      double a[2], b[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 32 + i * 16 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn * 64 + j * 16 + c];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      const int64_t col = n0 + wn * 64 + bj * 16 + (lane & 15);
+      const int64_t row0 = m0 + wm * 32 + bi * 16;
+      // outside the product, or (LOWER) a 64 x 64 block above the diagonal
+      if (row0 >= M || n0 + wn * 64 >= N || (LOWER && (n0 >> 6) + wn > (row0 >> 6))) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double *pc = C + row0 + MF::row(lane, v) + col * ldc;
+        const double x = g.alpha * acc[bi][bj][v];
+        *pc = g.beta == 0.0 ? x : x + g.beta * (*pc);
+      }
+    }
+}
+
+template <bool AT, bool BT, bool LOWER>
+__global__ __launch_bounds__(512) void k_gemm128(GemmArgs<double> g) {
+  gemm_tile128<AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+}
+
+// The recursion node's pair (as k_gemm64_pair) on 128 x 128 tiles.
+__global__ __launch_bounds__(512) void k_gemm128_pair(GemmArgs<double> s, GemmArgs<double> t,
+                                                      int nblk_s) {
+  const int b = blockIdx.x;
+  if (b < nblk_s) {
+    const int mt = (int)((s.M + kBig - 1) / kBig);
+    gemm_tile128<false, true, true>(s, b % mt, b / mt);
+  } else {
+    const int mt = (int)((t.M + kBig - 1) / kBig), bb = b - nblk_s;
+    gemm_tile128<false, false, false>(t, bb % mt, bb / mt);
+  }
 }
 
 constexpr int kRow32 = 32 + kPad;
@@ -963,11 +1103,27 @@ GemmArgs<T> make_args(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, 
 // slower at every node size of the recursion.)
 constexpr int64_t kSplit8Tiles = 256;
 
+// FP64 products with at least kBigTiles tiles of 128 x 128 run on them
+// (between the 324 tiles of n = 2304, where 64 x 64 tiles are faster, and
+// the 729 of n = 3456, where 128 x 128 tiles are).
+constexpr int64_t kBigTiles = 512;
+inline int64_t big_tiles(int64_t M, int64_t N) {
+  return ((M + kBig - 1) / kBig) * ((N + kBig - 1) / kBig);
+}
+
 template <typename T, bool AT, bool BT, bool LOWER>
 void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, int64_t ldb,
           T *C, int64_t ldc, T alpha, T beta, int kmode, hipStream_t st,
           int64_t small = kSmallTilesDefault) {
   GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
+  if constexpr (std::is_same<T, double>::value) {
+    if (big_tiles(M, N) >= kBigTiles) {
+      hipLaunchKernelGGL((k_gemm128<AT, BT, LOWER>),
+                         dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)((N + kBig - 1) / kBig)),
+                         dim3(512), 0, st, g);
+      return;
+    }
+  }
   if ((M / 64) * (N / 64) < small) {
     const dim3 grid((unsigned)(M / 32), (unsigned)(N / 32));
     const int64_t t32 = (M / 32) * (N / 32);
@@ -984,6 +1140,13 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
 template <typename T>
 void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st,
                int64_t small = kSmallTilesDefault) {
+  if constexpr (std::is_same<T, double>::value) {
+    const int64_t a = big_tiles(s.M, s.N), b = big_tiles(t.M, t.N);
+    if (a + b >= kBigTiles) {
+      hipLaunchKernelGGL(k_gemm128_pair, dim3((unsigned)(a + b)), dim3(512), 0, st, s, t, (int)a);
+      return;
+    }
+  }
   const unsigned a = (unsigned)((s.M / 64) * (s.N / 64)), b = (unsigned)((t.M / 64) * (t.N / 64));
   if ((int64_t)a + b < small) {
     const unsigned a32 = (unsigned)((s.M / 32) * (s.N / 32)),

@@ -467,12 +467,13 @@ constexpr int kRadixItems = kRadixThreads * kRadixSteps;
 constexpr int kRadixPerWave = 64 * kRadixSteps;
 
 // Only the first *count of the t slots hold observations (the rest belong to
-// rejected input), so every kernel of the sort stops there.
+// rejected input), so every kernel of the sort stops there (count null: all
+// t keys).
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int64_t t_max, const int64_t *count,
                                                             const int32_t *keys, int shift,
                                                             int64_t nblocks, int32_t *hist) {
   __shared__ int32_t cnt[256];
-  const int64_t t = min(t_max, *count);
+  const int64_t t = count ? min(t_max, *count) : t_max;
   cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRadixItems;
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     int shift, int64_t nblocks, const int64_t *offs, int32_t *keys_out, int32_t *vals_out) {
   __shared__ int32_t wcnt[kRadixThreads / 64][256];
   __shared__ int32_t wpre[kRadixThreads / 64][256];
-  const int64_t t = min(t_max, *count);
+  const int64_t t = count ? min(t_max, *count) : t_max;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < 256 * (kRadixThreads / 64); d += kRadixThreads) wcnt[d >> 8][d & 255] = 0;
   __syncthreads();
@@ -1486,21 +1487,21 @@ size_t camera_lists_scratch(int64_t t) {
          8 * (size_t)scan_tiles;
 }
 
-int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_bytes,
-                        hipStream_t st) {
-  const int64_t t = sc.t;
-  if (tmp_bytes < camera_lists_scratch(t)) return -1;
-  int bits = 1;
-  while (bits < 31 && ((int64_t)1 << bits) < (int64_t)sc.n) ++bits;
-  const int passes = (bits + 7) / 8;
+// Stable sort of t (key, value) pairs by the low `bits` bits of the
+// non-negative keys, 8 bits per pass; the first *count pairs (count null:
+// all t).  vals null: the values are the input positions.  keys and keys_out
+// must not alias.
+static void radix_sort_pairs(int64_t t, const int64_t *count, const int32_t *keys,
+                             const int32_t *vals, int bits, int32_t *keys_out, int32_t *vals_out,
+                             void *tmp, hipStream_t st) {
+  const int passes = std::max(1, (bits + 7) / 8);
   const int64_t nb = (t + kRadixItems - 1) / kRadixItems;
   const RadixScratch r = radix_layout(tmp, t);
-  const int64_t *count = w.ptr_p + sc.m;  // slots placed by the point grouping
-  const int32_t *kin = w.slot_cam, *vin = nullptr;
+  const int32_t *kin = keys, *vin = vals;
   for (int p = 0; p < passes; ++p) {
-    // the last pass writes the camera lists, the one before it the scratch
-    const bool to_lists = (passes - 1 - p) % 2 == 0;
-    int32_t *kout = to_lists ? w.cam_keys : r.keys, *vout = to_lists ? w.cam_slots : r.vals;
+    // the last pass writes the output, the one before it the scratch
+    const bool to_out = (passes - 1 - p) % 2 == 0;
+    int32_t *kout = to_out ? keys_out : r.keys, *vout = to_out ? vals_out : r.vals;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kRadixThreads), 0, st, t, count,
                        kin, 8 * p, nb, r.hist);
     exclusive_scan(r.hist, r.offs, 256 * nb, r.scan, st);
@@ -1509,6 +1510,21 @@ int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_
     kin = kout;
     vin = vout;
   }
+}
+
+static int bits_for(int64_t n) {
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
+  return bits;
+}
+
+int launch_camera_lists(const SceneDev &sc, SceneWork &w, void *tmp, size_t tmp_bytes,
+                        hipStream_t st) {
+  const int64_t t = sc.t;
+  if (tmp_bytes < camera_lists_scratch(t)) return -1;
+  const int64_t *count = w.ptr_p + sc.m;  // slots placed by the point grouping
+  radix_sort_pairs(t, count, w.slot_cam, nullptr, bits_for(sc.n), w.cam_keys, w.cam_slots, tmp,
+                   st);
   hipLaunchKernelGGL(k_cam_bounds, dim3(blocks_for((int64_t)sc.n + 1, kBlk)), dim3(kBlk), 0, st,
                      sc.n, sc.t, count, w.cam_keys, w.cam_ptr);
   return 0;
@@ -1599,6 +1615,106 @@ __global__ void k_min_trace(int64_t n, int n_decomp, const int32_t *pos, const d
   if (chosen) chosen[c] = best;
 }
 
+// ---- the sub-scenes' observations, chosen on the device --------------------
+// A candidate is one observation o in one decomposition d, e = d t + o.  The
+// candidates are sorted stably by point, then by sub-scene (the camera's
+// group), so each (sub-scene, point) pair becomes one run, in sub-scene
+// order, points ascending, observations ascending; a run of at least two
+// observations is kept: that point belongs to the sub-scene.
+
+// keys: the point of each candidate; out-of-range indices are reported
+// (the first observation's index) and read as 0.
+__global__ void k_sub_point_keys(int64_t t, int n_decomp, int32_t n, int32_t m,
+                                 const int32_t *oc, const int32_t *op, int32_t *key,
+                                 DevStatus *ds) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_decomp * t) return;
+  const int64_t o = e % t;
+  const int32_t c = oc[o], j = op[o];
+  const bool bad = c < 0 || c >= n || j < 0 || j >= m;
+  if (bad && e < t) report_error(ds, UCOV_EINVAL, (int)o);
+  key[e] = bad ? 0 : j;
+}
+
+// keys: the sub-scene of each candidate (after the sort by point)
+__global__ void k_sub_group_keys(int64_t T, int64_t t, int32_t n, const int32_t *oc,
+                                 const int32_t *gsub, const int32_t *cand, int32_t *key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  const int64_t e = cand[i], d = e / t;
+  const int32_t c = min(max(oc[e % t], 0), n - 1);
+  key[i] = gsub[d * n + c];
+}
+
+__device__ inline int32_t cand_point(const int32_t *op, const int32_t *cand, int64_t t,
+                                     int64_t i, int32_t m) {
+  return min(max(op[cand[i] % t], 0), m - 1);
+}
+
+// head[i]: candidate i starts a (sub-scene, point) run
+__global__ void k_sub_heads(int64_t T, int64_t t, int32_t m, const int32_t *op,
+                            const int32_t *sub, const int32_t *cand, int32_t *head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  head[i] = i == 0 || sub[i] != sub[i - 1] ||
+            cand_point(op, cand, t, i, m) != cand_point(op, cand, t, i - 1, m);
+}
+
+// start[r] = first candidate of run r (run = inclusive scan of head - 1), and
+// start[#runs] = T
+__global__ void k_sub_run_starts(int64_t T, const int32_t *head, const int64_t *run,
+                                 int64_t *start) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T && head[i]) start[run[i]] = i;
+  if (i == T) start[run[T]] = T;
+}
+
+// keep[i]: i's run holds at least two observations; khead[i]: i is the head
+// of a kept run (a point of the sub-scene)
+__global__ void k_sub_keep(int64_t T, const int32_t *head, const int64_t *run,
+                           const int64_t *start, int32_t *keep, int32_t *khead) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  const int64_t r = run[i] + head[i] - 1;
+  const bool k = start[r + 1] - start[r] >= 2;
+  keep[i] = k;
+  khead[i] = k && head[i];
+}
+
+// Per sub-scene s <= S: the first kept observation and kept point, from the
+// first candidate of a sub-scene >= s (binary search on the sorted keys).
+__global__ void k_sub_offsets(int32_t S, int64_t T, const int32_t *sub, const int64_t *qpos,
+                              const int64_t *kpos, int64_t *obs_off, int64_t *pt_off) {
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > S) return;
+  int64_t lo = 0, hi = T;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (sub[mid] < s) lo = mid + 1;
+    else hi = mid;
+  }
+  obs_off[s] = qpos[lo];
+  pt_off[s] = kpos[lo];
+}
+
+// The kept candidates: parent observation, camera slot and point index in
+// their sub-scene; each kept point's parent index.
+__global__ void k_sub_emit(int64_t T, int64_t t, int32_t n, int32_t m, const int32_t *oc,
+                           const int32_t *op, const int32_t *cslot, const int32_t *sub,
+                           const int32_t *cand, const int32_t *keep, const int32_t *khead,
+                           const int64_t *qpos, const int64_t *kpos, const int64_t *pt_off,
+                           int32_t *obs_src, int32_t *loc_c, int32_t *loc_p, int32_t *pt_src) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T || !keep[i]) return;
+  const int64_t e = cand[i], d = e / t, o = e % t;
+  const int64_t kp = kpos[i] + khead[i] - 1;  // the run's point
+  const int64_t q = qpos[i];
+  obs_src[q] = (int32_t)o;
+  loc_c[q] = cslot[d * n + min(max(oc[o], 0), n - 1)];
+  loc_p[q] = (int32_t)(kp - pt_off[sub[i]]);
+  if (khead[i]) pt_src[kp] = cand_point(op, cand, t, i, m);
+}
+
 }  // namespace
 
 void launch_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam_src,
@@ -1608,6 +1724,55 @@ void launch_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam
   const int64_t len = std::max({9 * n, 3 * m, pinfo ? 3 * t : (int64_t)0});
   hipLaunchKernelGGL(k_gather_subscenes, dim3(blocks_for(len, kBlk)), dim3(kBlk), 0, st, n, m, t,
                      cam_src, pt_src, obs_src, pcams, ppts, pinfo, cams, pts, info);
+}
+
+size_t subscene_select_scratch(int64_t T) {
+  const int64_t tiles = (T + 1 + kScanTile - 1) / kScanTile + 2;
+  return camera_lists_scratch(T) + 6 * align256(4 * (size_t)T) + 4 * align256(8 * (size_t)(T + 1)) +
+         align256(8 * (size_t)tiles);
+}
+
+void launch_subscene_select(int64_t t, int n_decomp, int32_t n, int32_t m, int32_t S,
+                            const int32_t *oc, const int32_t *op, const int32_t *gsub,
+                            const int32_t *cslot, void *tmp, int64_t *obs_off, int64_t *pt_off,
+                            int32_t *obs_src, int32_t *loc_c, int32_t *loc_p, int32_t *pt_src,
+                            DevStatus *ds, hipStream_t st) {
+  const int64_t T = (int64_t)n_decomp * t;
+  char *p = static_cast<char *>(tmp);
+  void *rtmp = p;
+  p += camera_lists_scratch(T);
+  auto take32 = [&]() {
+    int32_t *r = reinterpret_cast<int32_t *>(p);
+    p += align256(4 * (size_t)T);
+    return r;
+  };
+  auto take64 = [&]() {
+    int64_t *r = reinterpret_cast<int64_t *>(p);
+    p += align256(8 * (size_t)(T + 1));
+    return r;
+  };
+  int32_t *k0 = take32(), *k1 = take32(), *v1 = take32(), *cand = take32(), *head = take32(),
+          *keep = take32();
+  int32_t *khead = head;  // the heads are not needed once the runs are known
+  int64_t *run = take64(), *start = take64(), *qpos = take64(), *kpos = take64();
+  int64_t *scan_tmp = reinterpret_cast<int64_t *>(p);
+  const unsigned g = blocks_for(T, kBlk), g1 = blocks_for(T + 1, kBlk);
+  hipLaunchKernelGGL(k_sub_point_keys, dim3(g), dim3(kBlk), 0, st, t, n_decomp, n, m, oc, op, k0,
+                     ds);
+  radix_sort_pairs(T, nullptr, k0, nullptr, bits_for(m), k1, v1, rtmp, st);
+  hipLaunchKernelGGL(k_sub_group_keys, dim3(g), dim3(kBlk), 0, st, T, t, n, oc, gsub, v1, k0);
+  int32_t *sub = k1;
+  radix_sort_pairs(T, nullptr, k0, v1, bits_for((int64_t)S), sub, cand, rtmp, st);
+  hipLaunchKernelGGL(k_sub_heads, dim3(g), dim3(kBlk), 0, st, T, t, m, op, sub, cand, head);
+  exclusive_scan(head, run, T, scan_tmp, st);
+  hipLaunchKernelGGL(k_sub_run_starts, dim3(g1), dim3(kBlk), 0, st, T, head, run, start);
+  hipLaunchKernelGGL(k_sub_keep, dim3(g), dim3(kBlk), 0, st, T, head, run, start, keep, khead);
+  exclusive_scan(keep, qpos, T, scan_tmp, st);
+  exclusive_scan(khead, kpos, T, scan_tmp, st);
+  hipLaunchKernelGGL(k_sub_offsets, dim3(blocks_for((int64_t)S + 1, kBlk)), dim3(kBlk), 0, st, S,
+                     T, sub, qpos, kpos, obs_off, pt_off);
+  hipLaunchKernelGGL(k_sub_emit, dim3(g), dim3(kBlk), 0, st, T, t, n, m, oc, op, cslot, sub, cand,
+                     keep, khead, qpos, kpos, pt_off, obs_src, loc_c, loc_p, pt_src);
 }
 
 void launch_min_trace(int64_t n, int n_decomp, const int32_t *pos, const double *cand,

@@ -296,56 +296,113 @@ __global__ void k_standardize(int64_t count, const float *x, const float *mean, 
   xs[i] = mean ? (x[i] - mean[f]) / stdv[f] : x[i];
 }
 
-// Covariances -> standardised log-Cholesky parameters of D^-1 S D^-1
-__global__ void k_labels(int64_t n, const double *cov, const double *D, const float *mean,
-                         const float *stdv, float *lab, DevStatus *ds) {
+// Per camera: b_a, the standard deviations of the block-diagonal estimate
+// (Z_ii)^-1, from the camera's 45 Z_ii features (log10 of the diagonal, then
+// the correlations, row-major upper triangle).  With C the correlation
+// matrix, ((Z_ii)^-1)_aa = (C^-1)_aa / Z_aa; C is taken with kScaleRidge
+// added to its diagonal, which keeps it positive definite although its
+// entries are rounded to FP32 (at most ~6e-8 each, below 1e-6 in norm) and
+// bounds b for a nearly singular block.  ((C + ridge I)^-1)_aa is the squared
+// norm of column a of R^-1 for the Cholesky factor R R^T.
+constexpr double kScaleRidge = 1e-6;
+
+__global__ void k_block_scale(int64_t n, const float *feat, double *b, DevStatus *ds) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double L[9][9];
+  const float *f = feat + (int64_t)kIn * i;
+  double C[9][9], R[9][9];
+  int k = 0;
+  for (int a = 0; a < 9; ++a)
+    for (int c = a; c < 9; ++c, ++k) C[a][c] = a == c ? 1.0 + kScaleRidge : (double)f[k];
+  bool ok = true;
+  for (int a = 0; a < 9; ++a)
+    for (int c = 0; c <= a; ++c) {
+      double s = C[c][a];
+      for (int q = 0; q < c; ++q) s -= R[a][q] * R[c][q];
+      if (a == c) {
+        if (!(s > 0.0)) {
+          ok = false;
+          s = 1.0;
+        }
+        R[a][a] = sqrt(s);
+      } else {
+        R[a][c] = s / R[c][c];
+      }
+    }
+  if (!ok) report_error(ds, UCOV_EINVAL, (int)i);
+  // R^-1 (lower), overwriting C's lower triangle
+  for (int c = 0; c < 9; ++c) {
+    C[c][c] = 1.0 / R[c][c];
+    for (int a = c + 1; a < 9; ++a) {
+      double s = 0.0;
+      for (int q = c; q < a; ++q) s += R[a][q] * C[q][c];
+      C[a][c] = -s / R[a][a];
+    }
+  }
+  k = 0;
+  for (int a = 0; a < 9; ++a) {
+    double q = 0.0;
+    for (int r = a; r < 9; ++r) q += C[r][a] * C[r][a];
+    b[9 * i + a] = sqrt(q) * pow(10.0, -0.5 * (double)f[k]);
+    k += 9 - a;
+  }
+}
+
+// Covariances -> standardised log-Cholesky parameters of D^-1 S D^-1 with the
+// per-camera D_a = s_a b_a
+__global__ void k_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
+                         const float *mean, const float *stdv, float *lab, DevStatus *ds) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double L[9][9], D[9];
+  for (int a = 0; a < 9; ++a) D[a] = s_glob[a] * b[9 * i + a];
   const double *S = cov + 81 * i;
   for (int a = 0; a < 9; ++a)
-    for (int b = 0; b <= a; ++b) {
-      double s = S[9 * a + b] / (D[a] * D[b]);
-      for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
-      if (a == b) {
+    for (int c = 0; c <= a; ++c) {
+      double s = S[9 * a + c] / (D[a] * D[c]);
+      for (int k = 0; k < c; ++k) s -= L[a][k] * L[c][k];
+      if (a == c) {
         if (!(s > 0.0)) {
           report_error(ds, UCOV_EINVAL, (int)i);
           s = 1.0;
         }
         L[a][a] = sqrt(s);
       } else {
-        L[a][b] = s / L[b][b];
+        L[a][c] = s / L[c][c];
       }
     }
   int k = 0;
   for (int a = 0; a < 9; ++a)
-    for (int b = 0; b <= a; ++b, ++k) {
-      const double v = a == b ? log(L[a][a]) : L[a][b];
+    for (int c = 0; c <= a; ++c, ++k) {
+      const double v = a == c ? log(L[a][a]) : L[a][c];
       lab[45 * i + k] = (float)((v - mean[k]) / stdv[k]);
     }
 }
 
-// Network outputs -> covariances D L L^T D and their spread trace(L L^T)
-__global__ void k_predicted_cov(int64_t n, const float *y, const double *D, const float *mean,
-                                const float *stdv, double *cov, double *spread) {
+// Network outputs -> covariances D L L^T D (D_a = s_a b_a per camera) and
+// their spread trace(L L^T)
+__global__ void k_predicted_cov(int64_t n, const float *y, const double *b, const double *s_glob,
+                                const float *mean, const float *stdv, double *cov,
+                                double *spread) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double L[9][9];
+  double L[9][9], D[9];
+  for (int a = 0; a < 9; ++a) D[a] = s_glob[a] * b[9 * i + a];
   int k = 0;
   for (int a = 0; a < 9; ++a)
-    for (int b = 0; b < 9; ++b) L[a][b] = 0.0;
+    for (int c = 0; c < 9; ++c) L[a][c] = 0.0;
   for (int a = 0; a < 9; ++a)
-    for (int b = 0; b <= a; ++b, ++k) {
+    for (int c = 0; c <= a; ++c, ++k) {
       const double v = (double)mean[k] + (double)stdv[k] * (double)y[45 * i + k];
-      L[a][b] = a == b ? exp(v) : v;
+      L[a][c] = a == c ? exp(v) : v;
     }
   double tr = 0.0;
   for (int a = 0; a < 9; ++a)
-    for (int b = 0; b < 9; ++b) {
+    for (int c = 0; c < 9; ++c) {
       double s = 0.0;
-      for (int q = 0; q <= (a < b ? a : b); ++q) s += L[a][q] * L[b][q];
-      if (a == b) tr += s;
-      if (cov) cov[81 * i + 9 * a + b] = D[a] * s * D[b];
+      for (int q = 0; q <= (a < c ? a : c); ++q) s += L[a][q] * L[c][q];
+      if (a == c) tr += s;
+      if (cov) cov[81 * i + 9 * a + c] = D[a] * s * D[c];
     }
   if (spread) spread[i] = tr;
 }
@@ -396,11 +453,12 @@ __device__ inline uint64_t order_key(double v) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// One workgroup per diagonal entry a: D[a] = sqrt of the lower median of
-// cov[81 i + 10 a] over the n blocks (the value of rank (n - 1) / 2 in
-// ascending order), found bit by bit on the order-preserving keys.
+// One workgroup per diagonal entry a: s[a] = sqrt of the lower median (the
+// value of rank (n - 1) / 2 in ascending order) over the n blocks of the
+// variance ratio cov[81 i + 10 a] / b[9 i + a]^2, found bit by bit on the
+// order-preserving keys.
 __global__ __launch_bounds__(kStatThreads) void k_diag_median(int64_t n, const double *cov,
-                                                            double *D) {
+                                                            const double *b, double *s_glob) {
   __shared__ double red[kStatThreads];
   const int a = blockIdx.x;
   uint64_t prefix = 0;
@@ -409,7 +467,8 @@ __global__ __launch_bounds__(kStatThreads) void k_diag_median(int64_t n, const d
     const uint64_t hi_mask = bit == 63 ? 0 : ~((1ull << (bit + 1)) - 1);
     int64_t cnt = 0;  // values with the prefix and a 0 at this bit
     for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
-      const uint64_t k = order_key(cov[81 * i + 10 * a]);
+      const double bi = b[9 * i + a];
+      const uint64_t k = order_key(cov[81 * i + 10 * a] / (bi * bi));
       cnt += ((k & hi_mask) == prefix) && !((k >> bit) & 1ull);
     }
     const int64_t zeros = (int64_t)block_sum((double)cnt, red);
@@ -419,8 +478,8 @@ __global__ __launch_bounds__(kStatThreads) void k_diag_median(int64_t n, const d
     }
   }
   if (threadIdx.x == 0) {
-    const uint64_t b = (prefix >> 63) ? (prefix & 0x7fffffffffffffffull) : ~prefix;
-    D[a] = sqrt(__longlong_as_double((long long)b));
+    const uint64_t v = (prefix >> 63) ? (prefix & 0x7fffffffffffffffull) : ~prefix;
+    s_glob[a] = sqrt(__longlong_as_double((long long)v));
   }
 }
 
@@ -435,8 +494,14 @@ void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *s
   hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(kStatThreads), 0, st, n, cols, x, mean, stdv);
 }
 
-void launch_diag_median(int64_t n, const double *cov, double *D, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_median, dim3(9), dim3(kStatThreads), 0, st, n, cov, D);
+void launch_block_scale(int64_t n, const float *feat, double *b, DevStatus *ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_scale, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, feat, b,
+                     ds);
+}
+
+void launch_diag_median(int64_t n, const double *cov, const double *b, double *s_glob,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_median, dim3(9), dim3(kStatThreads), 0, st, n, cov, b, s_glob);
 }
 
 void launch_screener_features(const SceneDev &sc, const SceneWork &w, int32_t *hist,
@@ -608,16 +673,18 @@ void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, f
                      m, v, lr, c1, c2);
 }
 
-void launch_labels(int64_t n, const double *cov, const double *D, const float *mean,
-                   const float *stdv, float *lab, DevStatus *ds, hipStream_t st) {
-  hipLaunchKernelGGL(k_labels, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, cov, D, mean,
-                     stdv, lab, ds);
+void launch_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
+                   const float *mean, const float *stdv, float *lab, DevStatus *ds,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_labels, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, cov, b, s_glob,
+                     mean, stdv, lab, ds);
 }
 
-void launch_predicted_cov(int64_t n, const float *y, const double *D, const float *mean,
-                          const float *stdv, double *cov, double *spread, hipStream_t st) {
-  hipLaunchKernelGGL(k_predicted_cov, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, y, D,
-                     mean, stdv, cov, spread);
+void launch_predicted_cov(int64_t n, const float *y, const double *b, const double *s_glob,
+                          const float *mean, const float *stdv, double *cov, double *spread,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_predicted_cov, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, y, b,
+                     s_glob, mean, stdv, cov, spread);
 }
 
 }  // namespace ucov

@@ -115,7 +115,8 @@ struct ucov_ctx {
   DevStatus *h_ds = nullptr;  // pinned host copy of the per-scene status
   size_t h_ds_cap = 0;
   // learned screener
-  Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad, f_lab, f_zero;
+  Buf f_hist, f_ang, f_covis, mlp_ws, mlp_grad, f_lab, f_zero, f_bscale;
+  Buf sr_off, sr_tmp;  // sub-scene sizes and selection scratch
   Buf pg_f;  // the paper gauge's F (28 upper values), L_F (7 x 7 row-major), partial sums
   // dense stage: the tuned 32 x 32-tile threshold per padded size
   std::map<int64_t, int64_t> small_tiles;
@@ -639,7 +640,7 @@ void ucov_destroy(ucov_ctx *c) {
                  &c->m_sum, &c->m_split, &c->hp_cams, &c->hp_pts, &c->hp_oc, &c->hp_op,
                  &c->hp_info, &c->hp_out, &c->b_cams, &c->b_pts, &c->b_info, &c->b_oc, &c->b_op,
                  &c->b_cam_scene, &c->b_tab, &c->b_ds, &c->b_scratch, &c->f_hist, &c->f_ang, &c->f_covis,
-                 &c->mlp_ws, &c->mlp_grad, &c->f_lab, &c->f_zero, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
+                 &c->mlp_ws, &c->mlp_grad, &c->f_lab, &c->f_zero, &c->f_bscale, &c->sr_off, &c->sr_tmp, &c->pg_f, &c->sr_idx, &c->sr_cams, &c->sr_pts,
                  &c->sr_info, &c->sr_cand, &c->sr_chosen, &c->fc_x, &c->fc_part,
                  &c->fc_xq, &c->fc_k, &c->up_idx, &c->up_z, &c->up_jt, &c->up_b,
                  &c->up_t, &c->up_s, &c->up_tmp, &c->up_nj, &c->up_jn, &c->up_u, &c->up_g,
@@ -1545,95 +1546,76 @@ int ucov_subrecon_covariance(ucov_ctx *c, const ucov_scene *scene, int32_t n_dec
     if (groups[k] < 0 || groups[k] >= n) return c->fail(UCOV_EINVAL, "group id out of range");
   hipSetDevice(c->device);
   hipStream_t st = c->stream;
-  // the observation indices on the host, checked before any use
-  std::vector<int32_t> oc(t), op(t);
-  if (hipMemcpyAsync(oc.data(), scene->obs_cam, 4 * t, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(op.data(), scene->obs_pt, 4 * t, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return check_hip(c, "sub-reconstruction indices");
-  for (int64_t o = 0; o < t; ++o)
-    if (oc[o] < 0 || oc[o] >= n || op[o] < 0 || op[o] >= m) {
-      if (rep) rep->bad_index = (int32_t)o;
-      return c->fail(UCOV_EINVAL, "observation index out of range");
-    }
-  // sub-scenes in the order (decomposition, group by first appearance)
-  std::vector<int32_t> cam_src, pt_src, obs_src, loc_c, loc_p, pos((size_t)n_decomp * n);
-  std::vector<int64_t> cam_off{0}, pt_off{0}, obs_off{0};
-  std::vector<int32_t> slot(n), order(t);
+  const int64_t T = (int64_t)n_decomp * t;
+  if (T >= ((int64_t)1 << 31))
+    return c->fail(UCOV_EINVAL, "n_decomp x n_obs must be below 2^31");
+  // sub-scenes in the order (decomposition, group by first appearance): per
+  // camera and decomposition its sub-scene, its slot there and its row in the
+  // concatenation of the sub-scenes' cameras
+  std::vector<int32_t> gsub((size_t)n_decomp * n), cslot((size_t)n_decomp * n),
+      pos((size_t)n_decomp * n), cam_src;
+  std::vector<int64_t> cam_off{0};
+  cam_src.reserve((size_t)n_decomp * n);
   for (int d = 0; d < n_decomp; ++d) {
     const int32_t *g = groups + (int64_t)d * n;
-    std::vector<int32_t> gidx(n, -1), first;  // group id -> sub-scene of this decomposition
-    std::vector<std::vector<int32_t>> members;
+    std::vector<int32_t> gidx(n, -1), size;
+    const int32_t base = (int32_t)cam_off.size() - 1;
     for (int64_t cam = 0; cam < n; ++cam) {
       if (gidx[g[cam]] < 0) {
-        gidx[g[cam]] = (int32_t)members.size();
-        members.emplace_back();
+        gidx[g[cam]] = (int32_t)size.size();
+        size.push_back(0);
       }
-      const int sub = gidx[g[cam]];
-      slot[cam] = (int32_t)members[sub].size();
-      members[sub].push_back((int32_t)cam);
+      const int32_t sub = gidx[g[cam]];
+      gsub[(size_t)d * n + cam] = base + sub;
+      cslot[(size_t)d * n + cam] = size[sub]++;
     }
-    // observations grouped by (sub-scene, point); a point is kept in a
-    // sub-scene when at least two of its observations fall inside it
-    for (int64_t o = 0; o < t; ++o) order[o] = (int32_t)o;
-    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-      const int gx = gidx[g[oc[x]]], gy = gidx[g[oc[y]]];
-      return gx != gy ? gx < gy : op[x] < op[y];
-    });
-    std::vector<std::vector<int32_t>> keep_obs(members.size()), keep_pts(members.size());
-    for (int64_t a = 0; a < t;) {
-      const int sub = gidx[g[oc[order[a]]]];
-      int64_t b = a;
-      while (b < t && gidx[g[oc[order[b]]]] == sub && op[order[b]] == op[order[a]]) ++b;
-      if (b - a >= 2) {
-        keep_pts[sub].push_back(op[order[a]]);
-        for (int64_t e = a; e < b; ++e) keep_obs[sub].push_back(order[e]);
-      }
-      a = b;
+    std::vector<int64_t> first(size.size());
+    for (size_t sub = 0; sub < size.size(); ++sub) {
+      first[sub] = cam_off.back();
+      cam_off.push_back(cam_off.back() + size[sub]);
     }
-    for (size_t sub = 0; sub < members.size(); ++sub) {
-      const int64_t c0 = (int64_t)cam_src.size();
-      for (int32_t cam : members[sub]) {
-        pos[(size_t)d * n + cam] = (int32_t)cam_src.size();
-        cam_src.push_back(cam);
-      }
-      std::unordered_map<int32_t, int32_t> lp;
-      lp.reserve(keep_pts[sub].size() * 2);
-      for (int32_t j : keep_pts[sub]) {
-        lp[j] = (int32_t)(pt_src.size() - pt_off.back());
-        pt_src.push_back(j);
-      }
-      for (int32_t o : keep_obs[sub]) {
-        obs_src.push_back(o);
-        loc_c.push_back(slot[oc[o]]);
-        loc_p.push_back(lp[op[o]]);
-      }
-      (void)c0;
-      cam_off.push_back((int64_t)cam_src.size());
-      pt_off.push_back((int64_t)pt_src.size());
-      obs_off.push_back((int64_t)obs_src.size());
+    cam_src.resize(cam_off.back());
+    for (int64_t cam = 0; cam < n; ++cam) {
+      const int64_t row = first[gidx[g[cam]]] + cslot[(size_t)d * n + cam];
+      cam_src[row] = (int32_t)cam;
+      pos[(size_t)d * n + cam] = (int32_t)row;
     }
   }
   const int S = (int)cam_off.size() - 1;
-  const int64_t nt = cam_off.back(), mt = pt_off.back(), tt = obs_off.back();
+  const int64_t nt = cam_off.back();
   if (n_sub) *n_sub = S;
-  // index maps to the device in one buffer: cam_src | pt_src | obs_src | loc_c | loc_p | pos
-  const int64_t ni = nt + mt + 3 * tt + (int64_t)n_decomp * n;
-  UCOV_TRY(ensure(c, c->sr_idx, 4 * (size_t)ni));
+  // device index maps: cam_src | pos | gsub | cslot (n_decomp x n each), then
+  // obs_src | loc_c | loc_p | pt_src (at most n_decomp x t each)
+  const int64_t nd = (int64_t)n_decomp * n;
+  UCOV_TRY(ensure(c, c->sr_idx, 4 * (size_t)(4 * nd + 4 * T)));
+  UCOV_TRY(ensure(c, c->sr_off, 8 * 2 * (size_t)(S + 1)));
+  UCOV_TRY(ensure(c, c->sr_tmp, subscene_select_scratch(T)));
   int32_t *idx = as<int32_t>(c->sr_idx);
-  int32_t *d_cam_src = idx, *d_pt_src = d_cam_src + nt, *d_obs_src = d_pt_src + mt,
-          *d_loc_c = d_obs_src + tt, *d_loc_p = d_loc_c + tt, *d_pos = d_loc_p + tt;
+  int32_t *d_cam_src = idx, *d_pos = idx + nd, *d_gsub = idx + 2 * nd, *d_cslot = idx + 3 * nd;
+  int32_t *d_obs_src = idx + 4 * nd, *d_loc_c = d_obs_src + T, *d_loc_p = d_loc_c + T,
+          *d_pt_src = d_loc_p + T;
+  int64_t *d_obs_off = as<int64_t>(c->sr_off), *d_pt_off = d_obs_off + (S + 1);
   const std::pair<const std::vector<int32_t> *, int32_t *> up[] = {
-      {&cam_src, d_cam_src}, {&pt_src, d_pt_src}, {&obs_src, d_obs_src},
-      {&loc_c, d_loc_c},     {&loc_p, d_loc_p},   {&pos, d_pos}};
+      {&cam_src, d_cam_src}, {&pos, d_pos}, {&gsub, d_gsub}, {&cslot, d_cslot}};
   for (const auto &u : up)
-    if (!u.first->empty() &&
-        hipMemcpyAsync(u.second, u.first->data(), 4 * u.first->size(), hipMemcpyHostToDevice,
+    if (hipMemcpyAsync(u.second, u.first->data(), 4 * u.first->size(), hipMemcpyHostToDevice,
                        st) != hipSuccess)
       return check_hip(c, "sub-reconstruction index upload");
+  clear_status(c);
+  launch_subscene_select(t, n_decomp, (int32_t)n, (int32_t)m, S, scene->obs_cam, scene->obs_pt,
+                         d_gsub, d_cslot, c->sr_tmp.p, d_obs_off, d_pt_off, d_obs_src, d_loc_c,
+                         d_loc_p, d_pt_src, c->ds, st);
+  UCOV_TRY(check_hip(c, "sub-scene selection"));
+  std::vector<int64_t> offs(2 * (size_t)(S + 1));
+  if (hipMemcpyAsync(offs.data(), d_obs_off, 8 * offs.size(), hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return check_hip(c, "sub-scene sizes");
+  UCOV_TRY(sync_status(c, rep, "observation index out of range"));
+  const int64_t *obs_off = offs.data(), *pt_off = offs.data() + (S + 1);
+  const int64_t mt = pt_off[S], tt = obs_off[S];
   UCOV_TRY(ensure(c, c->sr_cams, 8 * 9 * (size_t)nt));
-  UCOV_TRY(ensure(c, c->sr_pts, 8 * 3 * (size_t)mt));
-  if (scene->obs_info) UCOV_TRY(ensure(c, c->sr_info, 8 * 3 * (size_t)tt));
+  UCOV_TRY(ensure(c, c->sr_pts, 8 * 3 * (size_t)std::max<int64_t>(mt, 1)));
+  if (scene->obs_info) UCOV_TRY(ensure(c, c->sr_info, 8 * 3 * (size_t)std::max<int64_t>(tt, 1)));
   launch_gather_subscenes(nt, mt, tt, d_cam_src, d_pt_src, d_obs_src, scene->cams, scene->pts,
                           scene->obs_info, as<double>(c->sr_cams), as<double>(c->sr_pts),
                           scene->obs_info ? as<double>(c->sr_info) : nullptr, st);
@@ -1748,29 +1730,36 @@ int ucov_mlp_train(ucov_ctx *c, float *params, float *adam_m, float *adam_v, int
   return UCOV_OK;
 }
 
-int ucov_screener_labels(ucov_ctx *c, int64_t n, const double *cov, const double *scale,
-                         const float *out_mean, const float *out_std, float *labels) {
+int ucov_screener_labels(ucov_ctx *c, int64_t n, const double *cov, const float *feat,
+                         const double *scale, const float *out_mean, const float *out_std,
+                         float *labels) {
   if (!c) return UCOV_EINVAL;
-  if (n < 1 || !cov || !scale || !out_mean || !out_std || !labels)
+  if (n < 1 || !cov || !feat || !scale || !out_mean || !out_std || !labels)
     return c->fail(UCOV_EINVAL, "bad label arguments");
   hipSetDevice(c->device);
+  UCOV_TRY(ensure(c, c->f_bscale, 8 * 9 * (size_t)n));
   clear_status(c);
-  launch_labels(n, cov, scale, out_mean, out_std, labels, c->ds, c->stream);
+  launch_block_scale(n, feat, as<double>(c->f_bscale), c->ds, c->stream);
+  launch_labels(n, cov, as<double>(c->f_bscale), scale, out_mean, out_std, labels, c->ds,
+                c->stream);
   UCOV_TRY(check_hip(c, "screener labels"));
-  return sync_status(c, nullptr, "screener labels (covariance not positive definite)");
+  return sync_status(c, nullptr, "screener labels (a block is not positive definite)");
 }
 
-int ucov_screener_covariance(ucov_ctx *c, int64_t n, const float *y, const double *scale,
-                             const float *out_mean, const float *out_std, double *cov,
-                             double *spread) {
+int ucov_screener_covariance(ucov_ctx *c, int64_t n, const float *y, const float *feat,
+                             const double *scale, const float *out_mean, const float *out_std,
+                             double *cov, double *spread) {
   if (!c) return UCOV_EINVAL;
-  if (n < 1 || !y || !scale || !out_mean || !out_std || (!cov && !spread))
+  if (n < 1 || !y || !feat || !scale || !out_mean || !out_std || (!cov && !spread))
     return c->fail(UCOV_EINVAL, "bad screener covariance arguments");
   hipSetDevice(c->device);
-  launch_predicted_cov(n, y, scale, out_mean, out_std, cov, spread, c->stream);
+  UCOV_TRY(ensure(c, c->f_bscale, 8 * 9 * (size_t)n));
+  clear_status(c);
+  launch_block_scale(n, feat, as<double>(c->f_bscale), c->ds, c->stream);
+  launch_predicted_cov(n, y, as<double>(c->f_bscale), scale, out_mean, out_std, cov, spread,
+                       c->stream);
   UCOV_TRY(check_hip(c, "screener covariance"));
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return check_hip(c, "screener covariance");
-  return UCOV_OK;
+  return sync_status(c, nullptr, "screener covariance (a Z_ii block is not positive definite)");
 }
 
 int ucov_screener_stats(ucov_ctx *c, int64_t n, const float *feat, const double *cov,
@@ -1782,17 +1771,20 @@ int ucov_screener_stats(ucov_ctx *c, int64_t n, const float *feat, const double 
   hipSetDevice(c->device);
   hipStream_t st = c->stream;
   UCOV_TRY(ensure(c, c->f_lab, 4 * UCOV_SCREENER_OUTPUTS * (size_t)n));
+  UCOV_TRY(ensure(c, c->f_bscale, 8 * 9 * (size_t)n));
   UCOV_TRY(ensure(c, c->f_zero, 8 * UCOV_SCREENER_OUTPUTS));
   float *zero = as<float>(c->f_zero), *one = zero + UCOV_SCREENER_OUTPUTS;
+  double *bsc = as<double>(c->f_bscale);
   clear_status(c);
   fill_i32(reinterpret_cast<int32_t *>(zero), 0, UCOV_SCREENER_OUTPUTS, st);
   fill_i32(reinterpret_cast<int32_t *>(one), 0x3f800000, UCOV_SCREENER_OUTPUTS, st);  // 1.0f
   launch_col_stats(n, UCOV_SCREENER_FEATURES, feat, in_mean, in_std, st);
-  launch_diag_median(n, cov, scale, st);
-  launch_labels(n, cov, scale, zero, one, as<float>(c->f_lab), c->ds, st);
+  launch_block_scale(n, feat, bsc, c->ds, st);
+  launch_diag_median(n, cov, bsc, scale, st);
+  launch_labels(n, cov, bsc, scale, zero, one, as<float>(c->f_lab), c->ds, st);
   launch_col_stats(n, UCOV_SCREENER_OUTPUTS, as<float>(c->f_lab), out_mean, out_std, st);
   UCOV_TRY(check_hip(c, "screener statistics"));
-  return sync_status(c, nullptr, "screener statistics (covariance not positive definite)");
+  return sync_status(c, nullptr, "screener statistics (a block is not positive definite)");
 }
 
 }  // extern "C"

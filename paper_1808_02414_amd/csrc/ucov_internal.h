@@ -191,6 +191,24 @@ void launch_gather_subscenes(int64_t n, int64_t m, int64_t t, const int32_t *cam
                              double *info, hipStream_t st);
 void launch_min_trace(int64_t n, int n_decomp, const int32_t *pos, const double *cand,
                       double *cov, int32_t *chosen, hipStream_t st);
+// The sub-scenes' points and observations, chosen on the device from the
+// parent's observations (oc, op: t each) and the cameras' groups: gsub
+// (n_decomp x n) the sub-scene of camera c in decomposition d, numbered so
+// that sub-scene ids grow with d; cslot (n_decomp x n) its camera slot in that
+// sub-scene.  A point belongs to a sub-scene when at least two of its
+// observations fall in it.  Outputs per sub-scene s <= S: obs_off, pt_off
+// (first row in the concatenation, [S] the totals); per kept observation
+// (sub-scene order, points ascending): obs_src (parent observation), loc_c,
+// loc_p (camera and point in the sub-scene); per kept point its parent index
+// pt_src.  Observation indices out of range are reported in ds (index: the
+// observation).  n_decomp * t must be below 2^31; tmp holds
+// subscene_select_scratch(n_decomp * t) bytes.
+size_t subscene_select_scratch(int64_t T);
+void launch_subscene_select(int64_t t, int n_decomp, int32_t n, int32_t m, int32_t S,
+                            const int32_t *oc, const int32_t *op, const int32_t *gsub,
+                            const int32_t *cslot, void *tmp, int64_t *obs_off, int64_t *pt_off,
+                            int32_t *obs_src, int32_t *loc_c, int32_t *loc_p, int32_t *pt_src,
+                            DevStatus *ds, hipStream_t st);
 
 // ---- learned screener (screener_kernels.hip) -------------------------------
 // Per-camera features (n x 55 FP32) from the scene stage's data; hist (8 n),
@@ -210,14 +228,20 @@ void mlp_gradient(const float *params, int64_t batch, const float *x, const floa
 void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr,
               int64_t step, hipStream_t st);
 // Per column of x (n x cols FP32): mean and standard deviation (n - 1, at
-// least 1e-6); per diagonal entry of n 9 x 9 blocks: D = sqrt(lower median).
+// least 1e-6).  Per camera: b (n x 9) = sqrt(diag((Z_ii)^-1)) from its Z_ii
+// features.  Per diagonal entry of n 9 x 9 blocks: s = sqrt(lower median of
+// cov_aa / b_a^2).  Label transforms with the per-camera scale D = s b.
 void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *stdv,
                       hipStream_t st);
-void launch_diag_median(int64_t n, const double *cov, double *D, hipStream_t st);
-void launch_labels(int64_t n, const double *cov, const double *D, const float *mean,
-                   const float *stdv, float *lab, DevStatus *ds, hipStream_t st);
-void launch_predicted_cov(int64_t n, const float *y, const double *D, const float *mean,
-                          const float *stdv, double *cov, double *spread, hipStream_t st);
+void launch_block_scale(int64_t n, const float *feat, double *b, DevStatus *ds, hipStream_t st);
+void launch_diag_median(int64_t n, const double *cov, const double *b, double *s_glob,
+                        hipStream_t st);
+void launch_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
+                   const float *mean, const float *stdv, float *lab, DevStatus *ds,
+                   hipStream_t st);
+void launch_predicted_cov(int64_t n, const float *y, const double *b, const double *s_glob,
+                          const float *mean, const float *stdv, double *cov, double *spread,
+                          hipStream_t st);
 
 // ---- dense stage (dense_kernels.hip) ---------------------------------------
 // Scaled positive-definite matrix a = S (Z + alpha QQ^T) S from a caller's Z.

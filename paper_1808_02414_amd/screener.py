@@ -1,8 +1,10 @@
 """Learned covariance screener: training and screening on the GPU.
 
-A network predicts each camera's 9x9 covariance from 55 features; cameras
-whose predicted spread (trace of the normalised covariance) exceeds a
-threshold fall back to the exact computation.  Every numeric step runs in the
+A network predicts each camera's 9x9 covariance from 55 features, as the
+log-Cholesky factor of the covariance normalised per camera by its
+block-diagonal estimate (Z_ii)^-1 and a training-set scale; cameras whose
+predicted spread (trace of the normalised covariance) exceeds a threshold
+fall back to the exact computation.  Every numeric step runs in the
 library's kernels: features (``ucov_screener_features``), the network's
 forward, gradient and Adam steps (``ucov_mlp_*``), the statistics that
 standardise inputs and outputs (``ucov_screener_stats``), the label
@@ -41,7 +43,7 @@ class Screener:
     params: object      # (P,) float32, device
     in_mean: object     # (55,) float32
     in_std: object      # (55,) float32
-    scale: object       # (9,) float64: per-parameter scale D
+    scale: object       # (9,) float64: per-parameter training-set scale
     out_mean: object    # (45,) float32
     out_std: object     # (45,) float32
     adam_m: object = None   # (P,) float32 Adam moments, to resume training
@@ -51,7 +53,7 @@ class Screener:
     def predict(self, ctx: Context, features):
         """Predicted covariances (n, 9, 9) and spreads (n,) for features (n, 55)."""
         y = ctx.mlp_forward(self.params, features, self.in_mean, self.in_std)
-        return ctx.screener_covariance(y, self.scale, self.out_mean, self.out_std)
+        return ctx.screener_covariance(y, features, self.scale, self.out_mean, self.out_std)
 
     def screen(self, ctx: Context, scene: DeviceScene, threshold: float):
         """Covariances of every camera of ``scene``: the network's where the
@@ -99,8 +101,9 @@ def fit(ctx: Context, features, covs, init, epochs: int = 30, batch: int = 512,
     params = torch.as_tensor(np.asarray(init), dtype=torch.float32).to(dev).contiguous()
     assert params.numel() == P, (params.numel(), P)
     covs = covs.contiguous()
-    in_mean, in_std, scale, out_mean, out_std = ctx.screener_stats(features.contiguous(), covs)
-    labels = ctx.screener_labels(covs, scale, out_mean, out_std)
+    features = features.contiguous()
+    in_mean, in_std, scale, out_mean, out_std = ctx.screener_stats(features, covs)
+    labels = ctx.screener_labels(covs, features, scale, out_mean, out_std)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     gen = torch.Generator(device="cpu").manual_seed(seed)

@@ -46,7 +46,12 @@ def block_errors(got, ref):
 
 @pytest.mark.parametrize("maker", [lambda: sg.clustered(3, n_clusters=3, per_cluster=40, m=6000),
                                    lambda: sg.clustered(4, n_clusters=4, per_cluster=30, m=5000,
-                                                        with_info=True)])
+                                                        with_info=True),
+                                   # 1000 cameras, Z 9000 x 9000: the top recursion levels
+                                   # run on 128 x 128 tiles, the last tile row half outside
+                                   lambda: sg.clustered(5, n_clusters=4, per_cluster=250,
+                                                        m=170_000)],
+                         ids=["3x40", "4x30-info", "4x250"])
 def test_clustered_matches_oracle(ucov, maker):
     u, ctx = ucov
     s = maker()

@@ -122,49 +122,55 @@ def test_train_step_is_gradient_plus_adam(ucov):
 
 
 def test_label_transforms_match_oracle(ucov):
+    """Labels and their inverse with the per-camera scale D = s b (b from the
+    cameras' Z_ii features) against the oracle's transforms."""
     import torch
     u, ctx = ucov
     from oracle.pipeline import camera_covariance as oracle_cov
-    S = oracle_cov(sg.tiny_circle(7))["blocks"]
-    D = np.sqrt(np.median(np.diagonal(S, axis1=1, axis2=2), axis=0))
+    sc = sg.tiny_circle(7)
+    S = oracle_cov(sc)["blocks"]
+    F = osc.camera_features(sc).astype(np.float32)
+    s = osc.label_scale(S, F)
+    D = s * osc.block_scale(F)
     raw = osc.log_cholesky(S, D)
     mean, std = raw.mean(0).astype(np.float32), raw.std(0).astype(np.float32) + 0.1
-    lab = ctx.screener_labels(cuda(S, torch.float64), cuda(D, torch.float64),
+    lab = ctx.screener_labels(cuda(S, torch.float64), cuda(F, torch.float32), cuda(s, torch.float64),
                               cuda(mean, torch.float32), cuda(std, torch.float32)).cpu().numpy()
     ref = (raw - mean) / std
     assert np.abs(lab - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
-    cov, spread = ctx.screener_covariance(cuda(lab, torch.float32), cuda(D, torch.float64),
-                                          cuda(mean, torch.float32), cuda(std, torch.float32))
+    cov, spread = ctx.screener_covariance(cuda(lab, torch.float32), cuda(F, torch.float32),
+                                          cuda(s, torch.float64), cuda(mean, torch.float32),
+                                          cuda(std, torch.float32))
     back = osc.from_log_cholesky(mean + std * lab.astype(np.float64), D)
-    assert rel(cov.cpu().numpy(), back) < 1e-12
+    assert rel(cov.cpu().numpy(), back) < 1e-10
     assert rel(cov.cpu().numpy(), S) < 1e-4
-    Dm = D[None, :, None] * D[None, None, :]
+    Dm = D[:, :, None] * D[:, None, :]
     assert np.allclose(spread.cpu().numpy(), np.trace(S / Dm, axis1=1, axis2=2), rtol=1e-4)
 
 
 def test_screener_stats_match_numpy(ucov):
     """The library's standardisation statistics against plain numpy on the
-    oracle's covariances: feature means and deviations (n - 1), the square
-    root of the lower median of every variance, and the moments of the
-    log-Cholesky labels (the oracle's transform)."""
+    oracle's covariances: feature means and deviations (n - 1), the label
+    scale (square root of the lower median of every variance ratio to the
+    block-diagonal estimate), and the moments of the log-Cholesky labels (the
+    oracle's transform)."""
     import torch
     u, ctx = ucov
     from oracle.pipeline import camera_covariance as oracle_cov
     scenes = [sg.tiny_circle(70 + k) for k in range(7)]  # 70 cameras: an even count
     S = np.concatenate([oracle_cov(s)["blocks"] for s in scenes])
     F = np.concatenate([osc.camera_features(s) for s in scenes]).astype(np.float32)
-    im, isd, D, om, osd = ctx.screener_stats(cuda(F, torch.float32), cuda(S, torch.float64))
+    im, isd, sc, om, osd = ctx.screener_stats(cuda(F, torch.float32), cuda(S, torch.float64))
     F64 = F.astype(np.float64)
     assert np.allclose(im.cpu().numpy(), F64.mean(0), rtol=1e-6, atol=1e-6)
     assert np.allclose(isd.cpu().numpy(), np.maximum(F64.std(0, ddof=1), 1e-6), rtol=1e-5, atol=1e-6)
-    diag = np.sort(np.diagonal(S, axis1=1, axis2=2), axis=0)
-    Dref = np.sqrt(diag[(S.shape[0] - 1) // 2])
-    assert np.array_equal(D.cpu().numpy(), Dref)
-    raw = osc.log_cholesky(S, Dref)
+    sref = osc.label_scale(S, F)
+    assert np.allclose(sc.cpu().numpy(), sref, rtol=1e-12)
+    raw = osc.log_cholesky(S, sref * osc.block_scale(F))
     assert np.allclose(om.cpu().numpy(), raw.mean(0), rtol=1e-5, atol=1e-5)
     assert np.allclose(osd.cpu().numpy(), raw.std(0, ddof=1), rtol=1e-5, atol=1e-5)
     again = ctx.screener_stats(cuda(F, torch.float32), cuda(S, torch.float64))
-    for a, b in zip(again, (im, isd, D, om, osd)):
+    for a, b in zip(again, (im, isd, sc, om, osd)):
         assert torch.equal(a, b)
 
 
@@ -293,7 +299,10 @@ def test_trained_screener_gains_over_screening_without_it(ucov, tmp_path):
     torch.cuda.synchronize()
     print(f"  trained in {time.time() - t0:.1f} s: loss first {hist[0]:.4f} last {hist[-1]:.4f}",
           flush=True)
-    assert hist[-1] < 0.5 * hist[0]
+    # the labels are standardised, so predicting their training mean (output
+    # 0) scores a loss of 1: the network must explain at least half of their
+    # variance on the training set
+    loss_ok = hist[-1] < 0.5
 
     pred, spread = model.predict(ctx, Fh)
     pred_all = pred.clone()
@@ -301,17 +310,22 @@ def test_trained_screener_gains_over_screening_without_it(ucov, tmp_path):
     err_net = block_rel_errors(pred.cpu().numpy(), ref)
     # network output 0 is the training mean of every standardised parameter
     zero = torch.zeros((Fh.shape[0], 45), dtype=torch.float32, device="cuda")
-    mcov, _ = ctx.screener_covariance(zero, model.scale, model.out_mean, model.out_std)
+    mcov, _ = ctx.screener_covariance(zero, Fh, model.scale, model.out_mean, model.out_std)
     err_mean = block_rel_errors(mcov.cpu().numpy(), ref)
     err_zii = block_rel_errors(np.linalg.inv(zii_from_features(Fh.cpu().numpy().astype(np.float64))), ref)
     med = {k: float(np.median(e)) for k, e in (("net", err_net), ("mean", err_mean), ("zii", err_zii))}
     print(f"  held-out median relative error {med}", flush=True)
 
-    D = model.scale.cpu().numpy()
-    true_spread = np.trace(ref / (D[None, :, None] * D[None, None, :]), axis1=1, axis2=2)
+    D = model.scale.cpu().numpy() * osc.block_scale(Fh.cpu().numpy())
+    true_spread = np.trace(ref / (D[:, :, None] * D[:, None, :]), axis1=1, axis2=2)
     from scipy.stats import spearmanr
     rho = spearmanr(spread.cpu().numpy(), true_spread).correlation
     print(f"  spread rank correlation {rho:.3f}", flush=True)
+    for name, sel in (("tiny", slice(7000, 10000)), ("spiral", slice(1000, 7000)),
+                      ("clustered", slice(0, 1000))):
+        print(f"  {name}: median errors net {np.median(err_net[sel]):.3f} "
+              f"mean {np.median(err_mean[sel]):.3f} zii {np.median(err_zii[sel]):.3f}", flush=True)
+    assert loss_ok, hist
     assert med["net"] < 0.35 * min(med["mean"], med["zii"]), med
     assert rho > 0.9
 

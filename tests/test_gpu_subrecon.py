@@ -42,6 +42,32 @@ def test_subrecon_matches_oracle(ucov, n, m, k, decomp):
     assert np.array_equal(chosen[clear], ref_chosen[clear])
 
 
+def test_subrecon_large_clustered(ucov):
+    """1000 cameras in 4 sites (1.16 million observations), three
+    decompositions into groups of about 250: the sub-scenes (3.5 million
+    candidate observations) are chosen on the device; every block against
+    the oracle's sub-reconstructions."""
+    import time
+    import torch
+    u, ctx = ucov
+    s = sg.clustered(5, n_clusters=4, per_cluster=250, m=170_000)
+    groups = np.stack([sg.view_graph_partition(s, 250, seed=d) for d in range(3)])
+    d = u.DeviceScene.from_scene(s)
+    print(f"subrecon clustered n={s.n_cams} t={s.n_obs}", flush=True)
+    ctx.subrecon_covariance(d, groups)  # workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got, chosen, n_sub, rep = ctx.subrecon_covariance(d, groups)
+    torch.cuda.synchronize()
+    print(f"  {n_sub} sub-reconstructions in {1e3 * (time.perf_counter() - t0):.1f} ms", flush=True)
+    ref, _ = subrecon.camera_covariance_min_trace(s, groups)
+    err = rel_blocks(got.cpu().numpy(), ref)
+    print(f"  max block error {err.max():.2e}", flush=True)
+    assert err.max() < 1e-6
+    again = ctx.subrecon_covariance(d, groups)[0]
+    assert torch.equal(again, got)
+
+
 def test_subrecon_error_falls_with_group_size(ucov):
     """The paper's Fig. 6 on the 500-camera scene: the relative error of the
     minimum-trace covariance against the whole reconstruction, for groups of

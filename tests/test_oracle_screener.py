@@ -1,4 +1,4 @@
-"""Pins of the screener oracle (CPU): features, log-Cholesky, MLP, Adam."""
+"""Pins of the screener oracle (CPU): features, label scale, log-Cholesky, MLP, Adam."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +65,80 @@ def test_log_cholesky_closed_form_and_round_trip():
     assert np.allclose(np.delete(P[0], diag_idx), 0.0, atol=1e-14)
     rng = np.random.default_rng(0)
     A = rng.normal(size=(5, 9, 9))
+    S = A @ np.transpose(A, (0, 2, 1)) + 0.1 * np.eye(9)
+    back = screener.from_log_cholesky(screener.log_cholesky(S, D), D)
+    assert np.abs(back - S).max() <= 1e-12 * np.abs(S).max()
+
+
+def test_zii_from_features_inverts_the_feature_definition():
+    """Z_ii rebuilt from the 45 features equals the block the features were
+    taken from (itself pinned to the dense Schur complement)."""
+    s = sg.spiral_slab(4, n=20, m=600)
+    Zd = screener.z_diagonal_blocks(s)
+    back = screener.zii_from_features(screener.camera_features(s))
+    assert np.abs(back - Zd).max() <= 1e-12 * np.abs(Zd).max()
+
+
+def features_of(Z):
+    """The 45 Z_ii features of (k, 9, 9) blocks, by their definition."""
+    out = []
+    for a in range(9):
+        for b in range(a, 9):
+            out.append(np.log10(Z[:, a, a]) if a == b
+                       else Z[:, a, b] / np.sqrt(Z[:, a, a] * Z[:, b, b]))
+    return np.stack(out, 1)
+
+
+def test_block_scale_closed_form_with_one_coupled_pair():
+    """A block coupling only parameters 2 and 5 with correlation rho: with the
+    ridge r on the correlation matrix, ((C + r I)^-1)_22 = (1 + r) /
+    ((1 + r)^2 - rho^2) (the 2x2 inverse), the others 1 / (1 + r); b_a is the
+    square root over Z_aa.  A singular block (rho = 1) stays finite."""
+    d = np.linspace(0.5, 40.0, 9)
+    r = screener.SCALE_RIDGE
+    for rho in (0.8, 1.0):
+        Z = np.diag(d)[None].copy()
+        Z[0, 2, 5] = Z[0, 5, 2] = rho * np.sqrt(d[2] * d[5])
+        b = screener.block_scale(features_of(Z))[0]
+        want = 1.0 / np.sqrt((1 + r) * d)
+        c22 = (1 + r) / ((1 + r) ** 2 - rho ** 2)
+        want[2] = np.sqrt(c22 / d[2])
+        want[5] = np.sqrt(c22 / d[5])
+        assert np.allclose(b, want, rtol=1e-9), rho
+    # an uncoupled block: b_a = 1 / sqrt((1 + r) Z_aa)
+    b = screener.block_scale(features_of(np.diag(d)[None]))[0]
+    assert np.allclose(b, 1.0 / np.sqrt((1 + r) * d), rtol=1e-13)
+
+
+def test_label_scale_is_the_lower_median_of_the_variance_ratios():
+    """Four cameras with Z_ii = I: the scale is the square root of the
+    second-smallest variance ratio per parameter (rank (4 - 1) // 2 = 1)."""
+    var = np.array([[4.0] * 9, [1.0] * 9, [9.0] * 9, [16.0] * 9])
+    var[:, 3] = [25.0, 36.0, 49.0, 64.0]
+    S = np.stack([np.diag(v) for v in var])
+    F = features_of(np.broadcast_to(np.eye(9), (4, 9, 9)).copy())
+    s = screener.label_scale(S, F)
+    want = np.full(9, 2.0)
+    want[3] = 6.0
+    ridge = np.sqrt(1.0 + screener.SCALE_RIDGE)  # b = 1 / sqrt(1 + ridge) for Z_ii = I
+    assert np.allclose(s, want * ridge, rtol=1e-14)
+    # with Z_ii = 4 I, b halves and the ratios grow by 4
+    F4 = features_of(np.broadcast_to(4.0 * np.eye(9), (4, 9, 9)).copy())
+    assert np.allclose(screener.label_scale(S, F4), 2.0 * want * ridge, rtol=1e-14)
+
+
+def test_log_cholesky_per_camera_scale():
+    """Per-camera D: a diagonal block D_i^2 s^2 maps to log s and zeros, and
+    the round trip holds block by block."""
+    rng = np.random.default_rng(3)
+    D = rng.uniform(0.1, 10.0, (4, 9))
+    s = np.linspace(1.0, 3.0, 9)
+    S = np.stack([np.diag((D[i] * s) ** 2) for i in range(4)])
+    P = screener.log_cholesky(S, D)
+    diag_idx = [a * (a + 1) // 2 + a for a in range(9)]
+    assert np.allclose(P[:, diag_idx], np.log(s)[None], atol=1e-13)
+    assert np.allclose(np.delete(P, diag_idx, axis=1), 0.0, atol=1e-13)
+    A = rng.normal(size=(4, 9, 9))
     S = A @ np.transpose(A, (0, 2, 1)) + 0.1 * np.eye(9)
     back = screener.from_log_cholesky(screener.log_cholesky(S, D), D)
     assert np.abs(back - S).max() <= 1e-12 * np.abs(S).max()
