@@ -49,12 +49,21 @@ def traffic_profile(workload):
 DEFAULT_TILE_THRESHOLD = 4096  # the library's untuned 32 x 32-tile threshold
 
 
+BIG_TILES = 512  # FP64 products with this many 128 x 128 tiles run on them
+
+
 def tile_schedule(n, small):
     """For each product of the dense recursion on an n x n matrix (n a
-    multiple of 64), whether it runs on 64 x 64 tiles under the tile
-    threshold `small` (the splits and tile counts of the library's host
-    code): two thresholds with the same schedule launch the same kernels."""
+    multiple of 64), the tile size it runs on under the tile threshold
+    `small` (the splits and tile counts of the library's host code): 128 when
+    it has at least BIG_TILES tiles of 128 x 128 (a node's paired launch
+    twice that), else 64 when it has at least `small` tiles of 64 x 64, else
+    32.  Two thresholds with the same schedule
+    launch the same kernels."""
     out = []
+
+    def kind(t64, t128, products=1):
+        return 128 if t128 >= products * BIG_TILES else (64 if t64 >= small else 32)
 
     def node(n):
         if n <= 128:
@@ -63,11 +72,15 @@ def tile_schedule(n, small):
         n2 = n - n1
         node(n1)
         lower, square = (n2 // 64) * (n1 // 64), (n2 // 64) ** 2
-        out.extend([lower >= small, square + lower >= small, lower >= small])
+        b1, b2 = -(-n1 // 128), -(-n2 // 128)
+        out.extend([kind(lower, b2 * b1), kind(square + lower, b2 * b2 + b2 * b1, 2),
+                    kind(lower, b2 * b1)])
         node(n2)
 
     node(n)
     return tuple(out)
+
+
 DENSE_SOURCE = os.path.join(ROOT, "paper_1808_02414_amd", "csrc", "dense_kernels.hip")
 
 

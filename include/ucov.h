@@ -427,9 +427,11 @@ int ucov_mlp_train(ucov_ctx *ctx, float *params, float *adam_m, float *adam_v, i
  * row-major) with the features of the same cameras (n x 55 float32), the 45
  * log-Cholesky parameters of the normalised covariance D^-1 Sigma D^-1 =
  * L L^T (log L_aa on the diagonal, L_ab below it, row-major lower triangle),
- * standardised as (p - out_mean) / out_std.  UCOV_EINVAL if a block or a
- * camera's Z_ii correlation matrix is not positive definite (bad_index: the
- * camera). */
+ * standardised as (p - out_mean) / out_std and clipped to [-6, 6] (a camera
+ * that the other cameras barely constrain has parameters far outside the
+ * rest, which would otherwise dominate the training loss).  UCOV_EINVAL if a
+ * block or a camera's Z_ii correlation matrix is not positive definite
+ * (bad_index: the camera). */
 int ucov_screener_labels(ucov_ctx *ctx, int64_t n, const double *cov, const float *feat,
                          const double *scale, const float *out_mean, const float *out_std,
                          float *labels);
@@ -448,10 +450,13 @@ int ucov_screener_covariance(ucov_ctx *ctx, int64_t n, const float *y, const flo
  * (55 each): per feature the mean and the standard deviation (n - 1 in the
  * denominator, at least 1e-6); scale (9): per parameter a the square root of
  * the lower median (rank (n - 1) / 2 ascending) over the blocks of the
- * variance ratio Sigma_aa / b_a^2; out_mean, out_std (45 each): mean and
- * standard deviation of the labels of ucov_screener_labels taken with
- * out_mean 0 and out_std 1.  Every sum runs in a fixed order (the same bits
- * on every call).  UCOV_EINVAL if a block is not positive definite. */
+ * variance ratio Sigma_aa / b_a^2; out_mean, out_std (45 each): per
+ * log-Cholesky parameter p of the normalised covariances (as FP32) its lower
+ * median m and 1.4826 times the lower median of |p - m| (the median absolute
+ * deviation, scaled to a normal distribution's standard deviation; at least
+ * 1e-6).  Every sum runs in a fixed order and the medians are exact order
+ * statistics (the same bits on every call).  UCOV_EINVAL if a block is not
+ * positive definite. */
 int ucov_screener_stats(ucov_ctx *ctx, int64_t n, const float *feat, const double *cov,
                         float *in_mean, float *in_std, double *scale, float *out_mean,
                         float *out_std);

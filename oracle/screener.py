@@ -24,6 +24,9 @@ Everything here is plain FP64 numpy, written for checking, not speed:
   features, and b = sqrt(diag((Z_ii)^-1)), the standard deviations of the
   block-diagonal estimate (its correlation matrix taken with a ridge of 1e-6),
   which set each camera's label scale D = s b;
+* ``label_moments`` / ``standardise``: the labels' robust location and
+  spread (median, scaled median absolute deviation) and the clipped
+  standardised labels;
   ``label_scale``: s_a = sqrt of the lower median over a training set of the
   variance ratio Sigma_aa / b_a^2.
 * ``log_cholesky`` / ``from_log_cholesky``: Sigma~ = D^-1 Sigma D^-1 = L L^T,
@@ -180,6 +183,25 @@ def label_scale(S: np.ndarray, F: np.ndarray) -> np.ndarray:
     of rank (k - 1) / 2 ascending) of Sigma_aa / b_a^2 over the k blocks."""
     r = np.sort(np.diagonal(S, axis1=1, axis2=2) / block_scale(F) ** 2, axis=0)
     return np.sqrt(r[(S.shape[0] - 1) // 2])
+
+
+LABEL_CLIP = 6.0
+
+
+def label_moments(P: np.ndarray):
+    """Per column of the (k, 45) label parameters: the lower median m (rank
+    (k - 1) / 2) and 1.4826 times the lower median of |P - m| (the median
+    absolute deviation scaled to a normal distribution's standard deviation),
+    at least 1e-6."""
+    r = (P.shape[0] - 1) // 2
+    m = np.sort(P, axis=0)[r]
+    mad = np.sort(np.abs(P - m), axis=0)[r]
+    return m, np.maximum(1.4826 * mad, 1e-6)
+
+
+def standardise(P: np.ndarray, center, spread) -> np.ndarray:
+    """Training labels: (P - center) / spread clipped to +-LABEL_CLIP."""
+    return np.clip((P - center) / spread, -LABEL_CLIP, LABEL_CLIP)
 
 
 def _per_block(D: np.ndarray, k: int) -> np.ndarray:

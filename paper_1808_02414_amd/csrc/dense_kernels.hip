@@ -839,6 +839,28 @@ __global__ __launch_bounds__(64 * S) void k_gemm32s_pair_b(const GemmArgs<T> *st
   }
 }
 
+// Batched 128 x 128 tiles (FP64): blockIdx.z picks the product of a scene.
+template <bool AT, bool BT, bool LOWER>
+__global__ __launch_bounds__(512) void k_gemm128_b(const GemmArgs<double> *tab) {
+  const GemmArgs<double> g = tab[blockIdx.z];
+  if ((int64_t)blockIdx.x * kBig >= g.M || (int64_t)blockIdx.y * kBig >= g.N) return;
+  gemm_tile128<AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(512) void k_gemm128_pair_b(const GemmArgs<double> *stab,
+                                                        const GemmArgs<double> *ttab) {
+  const GemmArgs<double> sg = stab[blockIdx.z];
+  const int ms = (int)((sg.M + kBig - 1) / kBig), nblk_s = ms * ms, b = blockIdx.x;
+  if (b < nblk_s) {
+    gemm_tile128<false, true, true>(sg, b % ms, b / ms);
+  } else {
+    const GemmArgs<double> tg = ttab[blockIdx.z];
+    const int mt = (int)((tg.M + kBig - 1) / kBig), bb = b - nblk_s;
+    if (bb >= mt * (int)((tg.N + kBig - 1) / kBig)) return;
+    gemm_tile128<false, false, false>(tg, bb % mt, bb / mt);
+  }
+}
+
 // Strict upper triangle of an n x n matrix (n a multiple of 32) set from its
 // lower triangle through 32 x 32 LDS tiles: workgroup (tm, tn), tm >= tn,
 // reads tile (tm, tn) with coalesced column loads and writes its transpose
@@ -1142,7 +1164,7 @@ void gemm_pair(const GemmArgs<T> &s, const GemmArgs<T> &t, hipStream_t st,
                int64_t small = kSmallTilesDefault) {
   if constexpr (std::is_same<T, double>::value) {
     const int64_t a = big_tiles(s.M, s.N), b = big_tiles(t.M, t.N);
-    if (a + b >= kBigTiles) {
+    if (a + b >= 2 * kBigTiles) {  // as for two products of kBigTiles tiles
       hipLaunchKernelGGL(k_gemm128_pair, dim3((unsigned)(a + b)), dim3(512), 0, st, s, t, (int)a);
       return;
     }
@@ -1223,7 +1245,7 @@ namespace {
 
 enum PlanKind { kPlanLeaf64 = 0, kPlanLeaf128 = 1, kPlanGemmT = 2, kPlanPair = 3, kPlanFinal = 4 };
 // Tile shape of a product launch: 64 x 64, or split 32 x 32 over 4 or 8 waves.
-enum PlanTiles { kTiles64 = 0, kTiles32x4 = 1, kTiles32x8 = 2 };
+enum PlanTiles { kTiles64 = 0, kTiles32x4 = 1, kTiles32x8 = 2, kTiles128 = 3 };
 
 struct PlanLaunch {
   int kind;
@@ -1300,7 +1322,27 @@ struct PlanBuilder {
       t_gemm += (x / 64) * (n1 / 64);
       t_pair += (x / 64) * (x / 64 + 1) / 2 + (x / 64) * (n1 / 64);
     }
+    // 128 x 128 tiles when the launch has enough of them (as for single
+    // products) and the scenes' products fill them: at least 3/4 of the
+    // launched tile area lies inside the products
+    int64_t b_gemm = 0, b_pair = 0, used = 0, area = 0;
+    const int64_t bn1 = (n1 + kBig - 1) / kBig;
+    for (int64_t x : m) {
+      const int64_t bx = (x + kBig - 1) / kBig;
+      b_gemm += bx * bn1;
+      b_pair += bx * bx + bx * bn1;
+      used += x * n1;
+      area += bx * bn1 * kBig * kBig;
+    }
+    const bool fill = 4 * used >= 3 * area && std::is_same<T, double>::value;
     auto shape = [&](PlanLaunch &L, int64_t tiles64, bool pair) {
+      if (fill && (pair ? b_pair >= 2 * kBigTiles : b_gemm >= kBigTiles)) {
+        L.tiles = kTiles128;
+        const unsigned m128 = (unsigned)((mmax + kBig - 1) / kBig), n128 = (unsigned)bn1;
+        L.gx = pair ? m128 * m128 + m128 * n128 : m128;
+        L.gy = pair ? 1 : n128;
+        return;
+      }
       if (tiles64 >= small) return;
       L.tiles = 4 * tiles64 < 256 ? kTiles32x8 : kTiles32x4;
       const unsigned m32 = (unsigned)(mmax / 32), n32 = (unsigned)(n1 / 32);
@@ -1524,7 +1566,10 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                            lv + L.first);
         break;
       case kPlanGemmT:
-        if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles128)
+          hipLaunchKernelGGL((k_gemm128_b<false, true, false>), dim3(L.gx, L.gy, L.count),
+                             dim3(512), 0, st, g + L.first);
+        else if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_b<double, false, true, false, 8>),
                              dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
         else if (L.tiles == kTiles32x4)
@@ -1535,7 +1580,10 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                              dim3(256), 0, st, g + L.first);
         break;
       case kPlanPair:
-        if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles128)
+          hipLaunchKernelGGL(k_gemm128_pair_b, dim3(L.gx, 1, L.count), dim3(512), 0, st,
+                             g + L.first, g + L.second);
+        else if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_pair_b<double, 8>), dim3(L.gx, 1, L.count), dim3(512), 0,
                              st, g + L.first, g + L.second);
         else if (L.tiles == kTiles32x4)
@@ -1546,7 +1594,10 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                              g + L.first, g + L.second);
         break;
       case kPlanFinal:
-        if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles128)
+          hipLaunchKernelGGL((k_gemm128_b<false, false, false>), dim3(L.gx, L.gy, L.count),
+                             dim3(512), 0, st, g + L.first);
+        else if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_b<double, false, false, false, 8>),
                              dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
         else if (L.tiles == kTiles32x4)

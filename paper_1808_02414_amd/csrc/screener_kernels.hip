@@ -349,9 +349,15 @@ __global__ void k_block_scale(int64_t n, const float *feat, double *b, DevStatus
 }
 
 // Covariances -> standardised log-Cholesky parameters of D^-1 S D^-1 with the
-// per-camera D_a = s_a b_a
+// per-camera D_a = s_a b_a, standardised and (clip) clipped to +-kLabelClip:
+// a camera that the other cameras barely constrain has a normalised
+// covariance many orders of magnitude above the rest, whose raw parameters
+// would dominate the loss.
+constexpr double kLabelClip = 6.0;
+
 __global__ void k_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
-                         const float *mean, const float *stdv, float *lab, DevStatus *ds) {
+                         const float *mean, const float *stdv, bool clip, float *lab,
+                         DevStatus *ds) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double L[9][9], D[9];
@@ -375,7 +381,8 @@ __global__ void k_labels(int64_t n, const double *cov, const double *b, const do
   for (int a = 0; a < 9; ++a)
     for (int c = 0; c <= a; ++c, ++k) {
       const double v = a == c ? log(L[a][a]) : L[a][c];
-      lab[45 * i + k] = (float)((v - mean[k]) / stdv[k]);
+      const double z = (v - mean[k]) / stdv[k];
+      lab[45 * i + k] = (float)(clip ? fmin(fmax(z, -kLabelClip), kLabelClip) : z);
     }
 }
 
@@ -453,6 +460,61 @@ __device__ inline uint64_t order_key(double v) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// The value of rank `rank` (0-based, ascending) among n keys, found digit by
+// digit (8 bits at a time, from the top) with LDS histograms: the counts, and
+// so the result, do not depend on the order of the atomic increments.
+template <typename KeyFn>
+__device__ uint64_t select_key(int64_t n, int64_t rank, KeyFn key, int32_t *hist, uint64_t *sh) {
+  uint64_t prefix = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    const uint64_t hi_mask = shift == 56 ? 0 : ~((1ull << (shift + 8)) - 1);
+    for (int d = threadIdx.x; d < 256; d += blockDim.x) hist[d] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint64_t k = key(i);
+      if ((k & hi_mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int d = 0;
+      while (d < 255 && rank >= hist[d]) rank -= hist[d++];
+      sh[0] = prefix | ((uint64_t)d << shift);
+      sh[1] = (uint64_t)rank;
+    }
+    __syncthreads();
+    prefix = sh[0];
+    rank = (int64_t)sh[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+__device__ inline double key_value(uint64_t k) {
+  const uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+// One workgroup per column c of x (n x cols, row-major FP32): the lower
+// median m (rank (n - 1) / 2) and 1.4826 times the lower median of |x - m|
+// (the median absolute deviation, scaled to a normal distribution's
+// standard deviation), at least 1e-6.
+__global__ __launch_bounds__(kStatThreads) void k_col_robust(int64_t n, int cols, const float *x,
+                                                           float *center, float *spread) {
+  __shared__ int32_t hist[256];
+  __shared__ uint64_t sh[2];
+  const int c = blockIdx.x;
+  const int64_t rank = (n - 1) / 2;
+  const double m = key_value(select_key(
+      n, rank, [&](int64_t i) { return order_key((double)x[i * cols + c]); }, hist, sh));
+  const double mad = key_value(select_key(
+      n, rank, [&](int64_t i) { return order_key(fabs((double)x[i * cols + c] - m)); }, hist,
+      sh));
+  if (threadIdx.x == 0) {
+    center[c] = (float)m;
+    spread[c] = fmaxf((float)(1.4826 * mad), 1e-6f);
+  }
+}
+
 // One workgroup per diagonal entry a: s[a] = sqrt of the lower median (the
 // value of rank (n - 1) / 2 in ascending order) over the n blocks of the
 // variance ratio cov[81 i + 10 a] / b[9 i + a]^2, found bit by bit on the
@@ -492,6 +554,12 @@ __global__ __launch_bounds__(kStatThreads) void k_diag_median(int64_t n, const d
 void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *stdv,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_col_stats, dim3(cols), dim3(kStatThreads), 0, st, n, cols, x, mean, stdv);
+}
+
+void launch_col_robust(int64_t n, int cols, const float *x, float *center, float *spread,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_col_robust, dim3(cols), dim3(kStatThreads), 0, st, n, cols, x, center,
+                     spread);
 }
 
 void launch_block_scale(int64_t n, const float *feat, double *b, DevStatus *ds, hipStream_t st) {
@@ -674,10 +742,10 @@ void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, f
 }
 
 void launch_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
-                   const float *mean, const float *stdv, float *lab, DevStatus *ds,
+                   const float *mean, const float *stdv, bool clip, float *lab, DevStatus *ds,
                    hipStream_t st) {
   hipLaunchKernelGGL(k_labels, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n, cov, b, s_glob,
-                     mean, stdv, lab, ds);
+                     mean, stdv, clip, lab, ds);
 }
 
 void launch_predicted_cov(int64_t n, const float *y, const double *b, const double *s_glob,

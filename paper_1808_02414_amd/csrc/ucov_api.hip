@@ -1740,7 +1740,7 @@ int ucov_screener_labels(ucov_ctx *c, int64_t n, const double *cov, const float 
   UCOV_TRY(ensure(c, c->f_bscale, 8 * 9 * (size_t)n));
   clear_status(c);
   launch_block_scale(n, feat, as<double>(c->f_bscale), c->ds, c->stream);
-  launch_labels(n, cov, as<double>(c->f_bscale), scale, out_mean, out_std, labels, c->ds,
+  launch_labels(n, cov, as<double>(c->f_bscale), scale, out_mean, out_std, true, labels, c->ds,
                 c->stream);
   UCOV_TRY(check_hip(c, "screener labels"));
   return sync_status(c, nullptr, "screener labels (a block is not positive definite)");
@@ -1781,8 +1781,8 @@ int ucov_screener_stats(ucov_ctx *c, int64_t n, const float *feat, const double 
   launch_col_stats(n, UCOV_SCREENER_FEATURES, feat, in_mean, in_std, st);
   launch_block_scale(n, feat, bsc, c->ds, st);
   launch_diag_median(n, cov, bsc, scale, st);
-  launch_labels(n, cov, bsc, scale, zero, one, as<float>(c->f_lab), c->ds, st);
-  launch_col_stats(n, UCOV_SCREENER_OUTPUTS, as<float>(c->f_lab), out_mean, out_std, st);
+  launch_labels(n, cov, bsc, scale, zero, one, false, as<float>(c->f_lab), c->ds, st);
+  launch_col_robust(n, UCOV_SCREENER_OUTPUTS, as<float>(c->f_lab), out_mean, out_std, st);
   UCOV_TRY(check_hip(c, "screener statistics"));
   return sync_status(c, nullptr, "screener statistics (a block is not positive definite)");
 }

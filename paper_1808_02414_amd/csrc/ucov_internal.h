@@ -233,11 +233,15 @@ void mlp_adam(int64_t n, float *params, const float *grad, float *m, float *v, f
 // cov_aa / b_a^2).  Label transforms with the per-camera scale D = s b.
 void launch_col_stats(int64_t n, int cols, const float *x, float *mean, float *stdv,
                       hipStream_t st);
+// Per column: the lower median and 1.4826 x the lower median absolute
+// deviation (at least 1e-6).
+void launch_col_robust(int64_t n, int cols, const float *x, float *center, float *spread,
+                       hipStream_t st);
 void launch_block_scale(int64_t n, const float *feat, double *b, DevStatus *ds, hipStream_t st);
 void launch_diag_median(int64_t n, const double *cov, const double *b, double *s_glob,
                         hipStream_t st);
 void launch_labels(int64_t n, const double *cov, const double *b, const double *s_glob,
-                   const float *mean, const float *stdv, float *lab, DevStatus *ds,
+                   const float *mean, const float *stdv, bool clip, float *lab, DevStatus *ds,
                    hipStream_t st);
 void launch_predicted_cov(int64_t n, const float *y, const double *b, const double *s_glob,
                           const float *mean, const float *stdv, double *cov, double *spread,

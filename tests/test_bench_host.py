@@ -25,13 +25,16 @@ def test_schedule_has_three_products_per_node():
 
 def test_thresholds_beyond_the_largest_product_are_equivalent():
     # 4544 = 71 tiles: the root's products have 36 x 35 (and 36 x 36 + 36 x 35
-    # for the pair) tiles of 64, all below 4096
+    # for the pair) tiles of 64, all below 4096, and fewer than 512 of 128
     assert bench.tile_schedule(4544, 4096) == bench.tile_schedule(4544, 1 << 40)
-    assert not any(bench.tile_schedule(4544, 4096))
+    assert set(bench.tile_schedule(4544, 4096)) == {32}
     # threshold 1024 puts exactly the root's three products on 64 x 64 tiles
-    assert sum(bench.tile_schedule(4544, 1024)) == 3
-    # at 27008 the top levels exceed 4096 tiles
-    assert bench.tile_schedule(27008, 4096) != bench.tile_schedule(27008, 1 << 40)
+    assert bench.tile_schedule(4544, 1024).count(64) == 3
+    # at 27008 every product with 4096 tiles of 64 has over 512 of 128, so
+    # thresholds from 4096 up give the same schedule; 1024 differs
+    assert bench.tile_schedule(27008, 4096) == bench.tile_schedule(27008, 1 << 40)
+    assert bench.tile_schedule(27008, 1024) != bench.tile_schedule(27008, 4096)
+    assert bench.tile_schedule(27008, 4096).count(128) == 21  # the top three levels (1 + 2 + 4 nodes)
 
 
 def test_more_than_one_gpu_is_refused():

@@ -127,6 +127,24 @@ def test_label_scale_is_the_lower_median_of_the_variance_ratios():
     assert np.allclose(screener.label_scale(S, F4), 2.0 * want * ridge, rtol=1e-14)
 
 
+def test_label_moments_hand_values_and_a_normal_sample():
+    """Lower median and scaled median absolute deviation: hand values for odd
+    and even counts (one outlier does not move them), ~sigma on a normal
+    sample; the standardised labels are clipped at +-6."""
+    P = np.array([[1.0, 1.0], [2.0, 2.0], [3.0, 3.0], [4.0, 4.0], [100.0, -50.0]])
+    m, s = screener.label_moments(P)
+    assert np.array_equal(m, [3.0, 2.0])        # ranks (5 - 1) // 2 = 2
+    assert np.allclose(s, [1.4826, 1.4826 * 1.0])  # |P - m| sorted: [0 1 1 2 97], [0 1 1 2 52]
+    m4, s4 = screener.label_moments(P[:4])
+    assert np.array_equal(m4, [2.0, 2.0]) and np.allclose(s4, 1.4826)
+    rng = np.random.default_rng(5)
+    x = rng.normal(3.0, 2.5, size=(200_001, 1))
+    mx, sx = screener.label_moments(x)
+    assert abs(mx[0] - 3.0) < 0.02 and abs(sx[0] / 2.5 - 1.0) < 0.01
+    z = screener.standardise(np.array([[-100.0], [0.5], [100.0]]), np.array([0.0]), np.array([0.5]))
+    assert np.array_equal(z[:, 0], [-6.0, 1.0, 6.0])
+
+
 def test_log_cholesky_per_camera_scale():
     """Per-camera D: a diagonal block D_i^2 s^2 maps to log s and zeros, and
     the round trip holds block by block."""
