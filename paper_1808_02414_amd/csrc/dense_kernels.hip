@@ -300,9 +300,29 @@ __device__ inline void gemm_tile128(const GemmArgs<double> &g, int tm, int tn) {
     }
 }
 
+// Tile of workgroup (bx, by): with a triangular operand cut at the tile the
+// K range grows with the tile row (kLeM) or column (kLeN); that direction is
+// taken as the slow grid dimension (the grid of a kLeM product is launched
+// transposed, N tiles by M tiles) and reversed, so the tiles with the
+// longest K ranges are dispatched first and the short ones fill in at the
+// end.
+__device__ inline void tile_order128(const GemmArgs<double> &g, int bx, int by, int &tm,
+                                     int &tn) {
+  tm = bx;
+  tn = by;
+  if (g.kmode == kLeM) {
+    tn = bx;
+    tm = (int)((g.M + kBig - 1) / kBig) - 1 - by;
+  } else if (g.kmode == kLeN) {
+    tn = (int)((g.N + kBig - 1) / kBig) - 1 - by;
+  }
+}
+
 template <bool AT, bool BT, bool LOWER>
 __global__ __launch_bounds__(512) void k_gemm128(GemmArgs<double> g) {
-  gemm_tile128<AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+  int tm, tn;
+  tile_order128(g, blockIdx.x, blockIdx.y, tm, tn);
+  gemm_tile128<AT, BT, LOWER>(g, tm, tn);
 }
 
 // The recursion node's pair (as k_gemm64_pair) on 128 x 128 tiles.
@@ -839,28 +859,6 @@ __global__ __launch_bounds__(64 * S) void k_gemm32s_pair_b(const GemmArgs<T> *st
   }
 }
 
-// Batched 128 x 128 tiles (FP64): blockIdx.z picks the product of a scene.
-template <bool AT, bool BT, bool LOWER>
-__global__ __launch_bounds__(512) void k_gemm128_b(const GemmArgs<double> *tab) {
-  const GemmArgs<double> g = tab[blockIdx.z];
-  if ((int64_t)blockIdx.x * kBig >= g.M || (int64_t)blockIdx.y * kBig >= g.N) return;
-  gemm_tile128<AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
-}
-
-__global__ __launch_bounds__(512) void k_gemm128_pair_b(const GemmArgs<double> *stab,
-                                                        const GemmArgs<double> *ttab) {
-  const GemmArgs<double> sg = stab[blockIdx.z];
-  const int ms = (int)((sg.M + kBig - 1) / kBig), nblk_s = ms * ms, b = blockIdx.x;
-  if (b < nblk_s) {
-    gemm_tile128<false, true, true>(sg, b % ms, b / ms);
-  } else {
-    const GemmArgs<double> tg = ttab[blockIdx.z];
-    const int mt = (int)((tg.M + kBig - 1) / kBig), bb = b - nblk_s;
-    if (bb >= mt * (int)((tg.N + kBig - 1) / kBig)) return;
-    gemm_tile128<false, false, false>(tg, bb % mt, bb / mt);
-  }
-}
-
 // Strict upper triangle of an n x n matrix (n a multiple of 32) set from its
 // lower triangle through 32 x 32 LDS tiles: workgroup (tm, tn), tm >= tn,
 // reads tile (tm, tn) with coalesced column loads and writes its transpose
@@ -1140,9 +1138,9 @@ void gemm(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda, const T *B, 
   GemmArgs<T> g = make_args<T>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kmode);
   if constexpr (std::is_same<T, double>::value) {
     if (big_tiles(M, N) >= kBigTiles) {
-      hipLaunchKernelGGL((k_gemm128<AT, BT, LOWER>),
-                         dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)((N + kBig - 1) / kBig)),
-                         dim3(512), 0, st, g);
+      const unsigned mt = (unsigned)((M + kBig - 1) / kBig), nt = (unsigned)((N + kBig - 1) / kBig);
+      const dim3 grid = kmode == kLeM ? dim3(nt, mt) : dim3(mt, nt);  // see tile_order128
+      hipLaunchKernelGGL((k_gemm128<AT, BT, LOWER>), grid, dim3(512), 0, st, g);
       return;
     }
   }
@@ -1245,7 +1243,7 @@ namespace {
 
 enum PlanKind { kPlanLeaf64 = 0, kPlanLeaf128 = 1, kPlanGemmT = 2, kPlanPair = 3, kPlanFinal = 4 };
 // Tile shape of a product launch: 64 x 64, or split 32 x 32 over 4 or 8 waves.
-enum PlanTiles { kTiles64 = 0, kTiles32x4 = 1, kTiles32x8 = 2, kTiles128 = 3 };
+enum PlanTiles { kTiles64 = 0, kTiles32x4 = 1, kTiles32x8 = 2 };
 
 struct PlanLaunch {
   int kind;
@@ -1322,27 +1320,7 @@ struct PlanBuilder {
       t_gemm += (x / 64) * (n1 / 64);
       t_pair += (x / 64) * (x / 64 + 1) / 2 + (x / 64) * (n1 / 64);
     }
-    // 128 x 128 tiles when the launch has enough of them (as for single
-    // products) and the scenes' products fill them: at least 3/4 of the
-    // launched tile area lies inside the products
-    int64_t b_gemm = 0, b_pair = 0, used = 0, area = 0;
-    const int64_t bn1 = (n1 + kBig - 1) / kBig;
-    for (int64_t x : m) {
-      const int64_t bx = (x + kBig - 1) / kBig;
-      b_gemm += bx * bn1;
-      b_pair += bx * bx + bx * bn1;
-      used += x * n1;
-      area += bx * bn1 * kBig * kBig;
-    }
-    const bool fill = 4 * used >= 3 * area && std::is_same<T, double>::value;
     auto shape = [&](PlanLaunch &L, int64_t tiles64, bool pair) {
-      if (fill && (pair ? b_pair >= 2 * kBigTiles : b_gemm >= kBigTiles)) {
-        L.tiles = kTiles128;
-        const unsigned m128 = (unsigned)((mmax + kBig - 1) / kBig), n128 = (unsigned)bn1;
-        L.gx = pair ? m128 * m128 + m128 * n128 : m128;
-        L.gy = pair ? 1 : n128;
-        return;
-      }
       if (tiles64 >= small) return;
       L.tiles = 4 * tiles64 < 256 ? kTiles32x8 : kTiles32x4;
       const unsigned m32 = (unsigned)(mmax / 32), n32 = (unsigned)(n1 / 32);
@@ -1566,10 +1544,7 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                            lv + L.first);
         break;
       case kPlanGemmT:
-        if (L.tiles == kTiles128)
-          hipLaunchKernelGGL((k_gemm128_b<false, true, false>), dim3(L.gx, L.gy, L.count),
-                             dim3(512), 0, st, g + L.first);
-        else if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_b<double, false, true, false, 8>),
                              dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
         else if (L.tiles == kTiles32x4)
@@ -1580,10 +1555,7 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                              dim3(256), 0, st, g + L.first);
         break;
       case kPlanPair:
-        if (L.tiles == kTiles128)
-          hipLaunchKernelGGL(k_gemm128_pair_b, dim3(L.gx, 1, L.count), dim3(512), 0, st,
-                             g + L.first, g + L.second);
-        else if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_pair_b<double, 8>), dim3(L.gx, 1, L.count), dim3(512), 0,
                              st, g + L.first, g + L.second);
         else if (L.tiles == kTiles32x4)
@@ -1594,10 +1566,7 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
                              g + L.first, g + L.second);
         break;
       case kPlanFinal:
-        if (L.tiles == kTiles128)
-          hipLaunchKernelGGL((k_gemm128_b<false, false, false>), dim3(L.gx, L.gy, L.count),
-                             dim3(512), 0, st, g + L.first);
-        else if (L.tiles == kTiles32x8)
+        if (L.tiles == kTiles32x8)
           hipLaunchKernelGGL((k_gemm32s_b<double, false, false, false, 8>),
                              dim3(L.gx, L.gy, L.count), dim3(512), 0, st, g + L.first);
         else if (L.tiles == kTiles32x4)
