@@ -1254,6 +1254,15 @@ __global__ __launch_bounds__(256) void k_concat(const BatchEntry *tab, double *c
 // Lane l supplies A[kk][l%16] and B[kk][l%16] with kk = l/16 = 2 (pair) + row.
 // (6 waves per SIMD: 80 registers without spills; more waves in flight
 // beat deeper loads per wave here, and 8 waves spill)
+// LDS writes of a wave visible to its own later reads (and its reads done
+// before later writes): a wave's LDS accesses run in issue order, so a
+// fence and a wave barrier suffice, no workgroup barrier.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(256, 6) void k_bin_blocks(SceneDev sc, const int2 *nzlist,
                                                    const int64_t *nzcount, const int64_t *bin_ptr,
                                                    const int2 *pairs, const double *rec,
@@ -1263,6 +1272,7 @@ __global__ __launch_bounds__(256, 6) void k_bin_blocks(SceneDev sc, const int2 *
   // Workgroups go round-robin to the 8 dies (XCDs); give each die a
   // contiguous run of the bin-ordered list (the grid is a multiple of 8), so
   // one die's L2 keeps a camera's records while its bins are reduced.
+  __shared__ double lrec[4][8][2][kRec];  // per wave: 8 pairs x (record a, record b)
   const unsigned per = gridDim.x / 8;
   const unsigned logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int64_t w = (int64_t)logical * 4 + (threadIdx.x >> 6);
@@ -1276,25 +1286,37 @@ __global__ __launch_bounds__(256, 6) void k_bin_blocks(SceneDev sc, const int2 *
   if (i != k) {
     const int64_t bin = bin_of(sc, i, k);
     const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
-    // 8 pairs (4 MFMAs) per iteration; all loads are issued before the MFMAs
-    // (16 or 4 pairs per iteration measured slower: fewer waves in flight,
-    // or fewer loads per wave)
+    // 8 pairs (4 MFMAs) per iteration.  The wave first copies the 8 pairs'
+    // two slot records into its LDS slot with 16-byte loads (8 lanes per
+    // pair: 4 per record, 8 doubles each), then every lane reads its
+    // operands there: 4 vector loads per lane and iteration instead of 48
+    // narrow ones that mostly fetched the same values across 16 lanes.
     constexpr int U = 4;
+    double(*my)[2][kRec] = lrec[threadIdx.x >> 6];
+    const int q_ld = lane >> 3, part = lane & 7;
     for (int64_t e = e0; e < e1; e += 2 * U) {
-      int2 pr[U];
-#pragma unroll
-      for (int h = 0; h < U; ++h) {
-        const int64_t ee = e + 2 * h + (kk >> 1);
-        pr[h] = (ee < e1) ? pairs[ee] : make_int2(-1, -1);
+      if (e + q_ld < e1) {
+        const int2 pp = pairs[e + q_ld];
+        const int slot = (part >> 2) ? pp.y : pp.x;
+        const double2 *src =
+            reinterpret_cast<const double2 *>(rec + (int64_t)slot * kRec + (part & 3) * 8);
+        double2 *dst = reinterpret_cast<double2 *>(&my[q_ld][part >> 2][(part & 3) * 8]);
+        const double2 v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
+        dst[0] = v0;
+        dst[1] = v1;
+        dst[2] = v2;
+        dst[3] = v3;
       }
+      wave_lds_sync();
       double av[U], bv[U];
 #pragma unroll
       for (int h = 0; h < U; ++h) {
+        const int q = 2 * h + (kk >> 1);
         av[h] = 0.0;
         bv[h] = 0.0;
-        if (pr[h].x >= 0 && col < 9) {
-          const double *ra = rec + (int64_t)pr[h].x * kRec;
-          const double *rb = rec + (int64_t)pr[h].y * kRec;
+        if (e + q < e1 && col < 9) {
+          const double *ra = my[q][0];
+          const double *rb = my[q][1];
           av[h] = ra[kRecJP + 9 * p + col];
           const double y0 = ra[kRecY + 3 * p], y1 = ra[kRecY + 3 * p + 1], y2 = ra[kRecY + 3 * p + 2];
           const double k0 = y0 * rb[kRecJX + 0] + y1 * rb[kRecJX + 1] + y2 * rb[kRecJX + 2];
@@ -1302,6 +1324,7 @@ __global__ __launch_bounds__(256, 6) void k_bin_blocks(SceneDev sc, const int2 *
           bv[h] = k0 * rb[kRecJP + col] + k1 * rb[kRecJP + 9 + col];
         }
       }
+      wave_lds_sync();  // the operands are read before the next copy
 #pragma unroll
       for (int h = 0; h < U; h += 2) {
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[h], acc0, 0, 0, 0);
