@@ -638,16 +638,24 @@ __global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t 
                C2 = sc.cams[9 * (int64_t)i + 5];
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int a = pairs[e].x;
-    const double *r = rec + (int64_t)a * kRec;
+    // the record's first 30 values (J_P, J_X, Y) with 16-byte loads
+    const double2 *r2 = reinterpret_cast<const double2 *>(rec + (int64_t)a * kRec);
+    double rv[30];
+#pragma unroll
+    for (int h = 0; h < 15; ++h) {
+      const double2 t = r2[h];
+      rv[2 * h] = t.x;
+      rv[2 * h + 1] = t.y;
+    }
     double jp[2][9], jx[2][3], y[2][3];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) jp[p][k] = r[kRecJP + 9 * p + k];
+      for (int k = 0; k < 9; ++k) jp[p][k] = rv[kRecJP + 9 * p + k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        jx[p][k] = r[kRecJX + 3 * p + k];
-        y[p][k] = r[kRecY + 3 * p + k];
+        jx[p][k] = rv[kRecJX + 3 * p + k];
+        y[p][k] = rv[kRecY + 3 * p + k];
       }
     }
     // M = I - Y J_X^T (2x2, symmetric)
