@@ -306,23 +306,16 @@ __device__ inline void gemm_tile128(const GemmArgs<double> &g, int tm, int tn) {
 // transposed, N tiles by M tiles) and reversed, so the tiles with the
 // longest K ranges are dispatched first and the short ones fill in at the
 // end.
-__device__ inline void tile_order128(const GemmArgs<double> &g, int bx, int by, int &tm,
-                                     int &tn) {
-  tm = bx;
-  tn = by;
-  if (g.kmode == kLeM) {
-    tn = bx;
-    tm = (int)((g.M + kBig - 1) / kBig) - 1 - by;
-  } else if (g.kmode == kLeN) {
-    tn = (int)((g.N + kBig - 1) / kBig) - 1 - by;
-  }
+__device__ inline int2 tile_order128(const GemmArgs<double> &g, int bx, int by) {
+  const int mt = (int)((g.M + kBig - 1) / kBig), nt = (int)((g.N + kBig - 1) / kBig);
+  const bool lem = g.kmode == kLeM, len = g.kmode == kLeN;
+  return make_int2(lem ? mt - 1 - by : bx, lem ? bx : (len ? nt - 1 - by : by));
 }
 
 template <bool AT, bool BT, bool LOWER>
 __global__ __launch_bounds__(512) void k_gemm128(GemmArgs<double> g) {
-  int tm, tn;
-  tile_order128(g, blockIdx.x, blockIdx.y, tm, tn);
-  gemm_tile128<AT, BT, LOWER>(g, tm, tn);
+  const int2 t = tile_order128(g, blockIdx.x, blockIdx.y);
+  gemm_tile128<AT, BT, LOWER>(g, t.x, t.y);
 }
 
 // The recursion node's pair (as k_gemm64_pair) on 128 x 128 tiles.
@@ -811,11 +804,19 @@ __global__ __launch_bounds__(LeafThreads<NB>::value) void k_leaf_mfma_b(const Le
   leaf_body<T, NB, LeafThreads<NB>::value>(a.A, a.lda, a.o, a.ds);
 }
 
+// As in the single 128 x 128 products, a triangular operand cut per tile row
+// (kLeM, whose launch has its grid transposed: N tiles by M tiles) or column
+// (kLeN) makes that direction the slow one, reversed: the scene's tiles with
+// the longest K ranges go first.
 template <typename T, bool AT, bool BT, bool LOWER>
 __global__ __launch_bounds__(256) void k_gemm64_b(const GemmArgs<T> *tab) {
   const GemmArgs<T> g = tab[blockIdx.z];
-  if ((int64_t)blockIdx.x * 64 >= g.M || (int64_t)blockIdx.y * 64 >= g.N) return;
-  gemm_tile<T, AT, BT, LOWER>(g, blockIdx.x, blockIdx.y);
+  const int mt = (int)(g.M / 64), nt = (int)(g.N / 64);
+  const bool lem = g.kmode == kLeM;
+  const int bm = lem ? (int)blockIdx.y : (int)blockIdx.x;  // over the M tiles
+  const int bn = lem ? (int)blockIdx.x : (int)blockIdx.y;  // over the N tiles
+  if (bm >= mt || bn >= nt) return;
+  gemm_tile<T, AT, BT, LOWER>(g, lem ? mt - 1 - bm : bm, g.kmode == kLeN ? nt - 1 - bn : bn);
 }
 
 template <typename T>
@@ -1572,8 +1573,8 @@ void spd_plan_run(const SpdPlan *p, hipStream_t st) {
         else if (L.tiles == kTiles32x4)
           hipLaunchKernelGGL((k_gemm32s_b<double, false, false, false, 4>),
                              dim3(L.gx, L.gy, L.count), dim3(256), 0, st, g + L.first);
-        else
-          hipLaunchKernelGGL((k_gemm64_b<double, false, false, false>), dim3(L.gx, L.gy, L.count),
+        else  // A21 = -L22^-1 T2 (kLeM): grid transposed, see k_gemm64_b
+          hipLaunchKernelGGL((k_gemm64_b<double, false, false, false>), dim3(L.gy, L.gx, L.count),
                              dim3(256), 0, st, g + L.first);
         break;
     }
