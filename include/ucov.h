@@ -241,11 +241,13 @@ int ucov_update_covariance(ucov_ctx *ctx, const ucov_scene *scene, int64_t n_new
                            double *new_cross, ucov_report *rep);
 
 /* Tune the dense stage's tile schedule for matrices of size n (N = 9 n_cams
- * of a scene): the recursion's products run on 64 x 64 or 32 x 32 MFMA tiles
- * depending on their size; every candidate threshold is timed on a synthetic
- * positive definite matrix of the padded size and the fastest is kept in this
- * context for that size (used by ucov_camera_covariance and
- * ucov_full_covariance in UCOV_FP64).  Results are unchanged by the choice up
+ * of a scene): the recursion's products run on 128 x 128, 64 x 64 or 32 x 32
+ * MFMA tiles depending on their size (a product with at least 512 tiles of
+ * 128 x 128, a recursion node's paired launch with 1024, always on those; the
+ * threshold below decides between the other two); every candidate threshold
+ * is timed on a synthetic positive definite matrix of the padded size and the
+ * fastest is kept in this context for that size (used by
+ * ucov_camera_covariance and ucov_full_covariance in UCOV_FP64).  Results are unchanged by the choice up
  * to rounding order.  threshold (HOST, or NULL): the chosen number of 64 x 64
  * tiles below which products use 32 x 32 tiles; ms (HOST, or NULL): its dense
  * stage time.  Allocates the dense workspace for that size. */
