@@ -127,3 +127,26 @@ def test_whole_covariance_full_size_sampled(ucov, gauge, name):
     assert pf < 1e-6 and ps < 1e-5, (pf, ps)
     lam = np.linalg.eigvalsh(pts)
     assert lam.min() > 0.0
+
+
+def test_whole_covariance_large_tiles(ucov):
+    """1000 cameras in 4 sites (Z 9000 x 9000, padded 9024 = 70.5 tiles of
+    128): the top recursion levels and X = L^-T L^-1 (a lower product with
+    both operands triangular) run on 128 x 128 tiles whose last row and column
+    lie half outside; the whole camera matrix against the oracle's (camera
+    gauge), 100 sampled points."""
+    u, ctx = ucov
+    s = sg.clustered(5, n_clusters=4, per_cluster=250, m=170_000)
+    d = u.DeviceScene.from_scene(s)
+    print(f"whole covariance clustered n={s.n_cams} m={s.n_pts}", flush=True)
+    cam, pts, rep = ctx.full_covariance(d)
+    cam, pts = cam.cpu().numpy(), pts.cpu().numpy()
+    print(f"  ms inverse {rep['ms_inverse']:.2f} extract {rep['ms_extract']:.2f}", flush=True)
+    sel = np.random.default_rng(1).choice(s.n_pts, 100, replace=False)
+    Xr, Pr = opts.structured(s, "camera", select=sel)
+    fro, scaled = camera_errors(cam, Xr)
+    pf, ps = point_errors(pts[sel], Pr)
+    print(f"  cameras fro {fro:.2e} scaled {scaled:.2e}; points fro {pf:.2e} scaled {ps:.2e}",
+          flush=True)
+    assert fro < 1e-6 and scaled < 1e-5, (fro, scaled)
+    assert pf < 1e-6 and ps < 1e-5, (pf, ps)
