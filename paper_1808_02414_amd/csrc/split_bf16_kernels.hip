@@ -246,6 +246,121 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16x(int64_t n, const unsigned
 #undef UCOV_SPLIT_LOAD
 }
 
+// The same product on 128 x 128 tiles (three slices only): 8 waves, each a
+// 32 x 64 part as 2 x 4 MFMA tiles, which halves the slice panels each tile
+// streams past the L2 and reads a quarter fewer LDS bytes per MFMA; all A
+// fragments of a step stay in registers while the B slices go by (about 240
+// registers, two waves per SIMD, one workgroup per CU).  n is a multiple of
+// 64, so the last tile row or column may be half outside: its loads repeat
+// the first half (in bounds) and its stores are skipped.
+constexpr int kBTile = 128;
+constexpr int64_t kBigSplitN = 512;  // from this size the 128 x 128 tiles
+
+__global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_big(int64_t n, const unsigned short *as,
+                                                         const unsigned short *bs,
+                                                         const int *ex, const int *er,
+                                                         double *x, int64_t ldx) {
+  constexpr int S = 3;
+  __shared__ __attribute__((aligned(16))) unsigned short sa[S][kBTile * kLdsRow];
+  __shared__ __attribute__((aligned(16))) unsigned short sb[S][kBTile * kLdsRow];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 64;
+  const int64_t m0 = (int64_t)blockIdx.x * kBTile, n0 = (int64_t)blockIdx.y * kBTile;
+  const size_t slice = (size_t)n * n;
+  // loader: thread -> row tid / 4 of the tile, 8 k at (tid % 4) * 8
+  const int lr = tid >> 2, lk = (tid & 3) * 8;
+  const int64_t ar = m0 + lr < n ? m0 + lr : m0 + lr - 64;  // in bounds
+  const int64_t br = n0 + lr < n ? n0 + lr : n0 + lr - 64;
+  const unsigned short *pa = as + ar * n + lk;
+  const unsigned short *pb = bs + br * n + lk;
+  uint4 ra0, ra1, ra2, rb0, rb1, rb2;
+#define UCOV_SPLIT_LOAD3(k0)                                         \
+  do {                                                               \
+    ra0 = *reinterpret_cast<const uint4 *>(pa + (k0));               \
+    rb0 = *reinterpret_cast<const uint4 *>(pb + (k0));               \
+    ra1 = *reinterpret_cast<const uint4 *>(pa + slice + (k0));       \
+    rb1 = *reinterpret_cast<const uint4 *>(pb + slice + (k0));       \
+    ra2 = *reinterpret_cast<const uint4 *>(pa + 2 * slice + (k0));   \
+    rb2 = *reinterpret_cast<const uint4 *>(pb + 2 * slice + (k0));   \
+  } while (0)
+  f4 acc[S][2][4];
+  double sum[2][4][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll
+      for (int g = 0; g < S; ++g) acc[g][bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sum[bi][bj][v] = 0.0;
+    }
+  UCOV_SPLIT_LOAD3(0);
+  for (int64_t k0 = 0; k0 < n; k0 += kKs) {
+    __syncthreads();
+    {
+      const int o = lr * kLdsRow + lk;
+      *reinterpret_cast<uint4 *>(&sa[0][o]) = ra0;
+      *reinterpret_cast<uint4 *>(&sb[0][o]) = rb0;
+      *reinterpret_cast<uint4 *>(&sa[1][o]) = ra1;
+      *reinterpret_cast<uint4 *>(&sb[1][o]) = rb1;
+      *reinterpret_cast<uint4 *>(&sa[2][o]) = ra2;
+      *reinterpret_cast<uint4 *>(&sb[2][o]) = rb2;
+    }
+    __syncthreads();
+    if (k0 + kKs < n) UCOV_SPLIT_LOAD3(k0 + kKs);
+    const int kq = 8 * (lane >> 4);
+    bf16x8 fa[S][2];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        fa[i][b] = *reinterpret_cast<const bf16x8 *>(&sa[i][(wm + 16 * b + (lane & 15)) * kLdsRow + kq]);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      bf16x8 fb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        fb[b] = *reinterpret_cast<const bf16x8 *>(&sb[j][(wn + 16 * b + (lane & 15)) * kLdsRow + kq]);
+#pragma unroll
+      for (int i = 0; i + j < S; ++i)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj)
+            acc[i + j][bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i][bi], fb[bj],
+                                                                         acc[i + j][bi][bj], 0, 0, 0);
+    }
+    if ((k0 + kKs) % kFlushK == 0 || k0 + kKs >= n) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double t = 0.0;
+#pragma unroll
+            for (int g = 0; g < S; ++g) t += (double)acc[g][bi][bj][v];
+            sum[bi][bj][v] += t;
+#pragma unroll
+            for (int g = 0; g < S; ++g) acc[g][bi][bj][v] = 0.f;
+          }
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm + 16 * bi + 4 * (lane >> 4) + v;
+        const int64_t col = n0 + wn + 16 * bj + (lane & 15);
+        if (row >= n || col >= n) continue;
+        if (ex[row] == kNoExp || er[col] == kNoExp) continue;
+        x[row + col * ldx] += ldexp(sum[bi][bj][v], ex[row] + er[col]);
+      }
+#undef UCOV_SPLIT_LOAD3
+}
+
 }  // namespace
 
 int split_bf16_slices(int64_t n) { return n > kSplitSmallN ? 4 : 3; }
@@ -269,6 +384,11 @@ void update(int64_t n, double *x, const double *r, void *scratch, hipStream_t st
                      x, n, ex, as);
   hipLaunchKernelGGL((k_split_cols<S>), dim3(blocks(n, 256), (unsigned)n), dim3(256), 0, st, n,
                      r, n, er, bs);
+  if (S == 3 && n >= kBigSplitN) {
+    const unsigned t = blocks(n, kBTile);
+    hipLaunchKernelGGL(k_gemm_bf16x3_big, dim3(t, t), dim3(512), 0, st, n, as, bs, ex, er, x, n);
+    return;
+  }
   hipLaunchKernelGGL((k_gemm_bf16x<S>), dim3((unsigned)(n / kSTile), (unsigned)(n / kSTile)),
                      dim3(256), 0, st, n, as, bs, ex, er, x, n);
 }
