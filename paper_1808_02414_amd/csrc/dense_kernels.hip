@@ -21,6 +21,7 @@
 // Newton-Schulz steps with FP64 residuals then refine (see ucov_api.hip).
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include <string>
 #include <vector>
@@ -528,6 +529,75 @@ __device__ inline float rsqrt_nr(float x) {
   return y;
 }
 
+// Lane n of each row of 16 lanes, broadcast to that row (DPP row_newbcast).
+template <int N>
+__device__ inline double row_bcast(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x150 + N, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + N, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int N>
+__device__ inline float row_bcast(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + N, 0xF, 0xF, true));
+}
+// Lane src's value of x, for any src of the wave (LDS crossbar, no memory).
+__device__ inline double lane_fetch(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(4 * src, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(4 * src, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float lane_fetch(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(4 * src, __float_as_int(x)));
+}
+
+// Cholesky factor L and inverse L^-1 of a 16 x 16 diagonal block on one wave.
+// Lane 16 q + r holds a[k] = A[r][4k + q] of the symmetric trailing matrix
+// (both triangles) and t[k] = T[4k + q][r], column r of the forward
+// elimination L T = I (T = L^-1 at the end).  Column j: pivot A[j][j],
+// rs = A[j][j]^-1/2, L[i][j] = A[i][j] rs = A[j][i] rs (symmetry), so the
+// values every lane needs, row j at its own columns, come from lane j of its
+// own row of 16 lanes (one DPP broadcast each); the two values from column
+// group j % 4 (A[r][j] and T[j][r]) come over the crossbar.  Then
+//   A[r][c] -= A[r][j] A[j][c] rs^2   (c > j),
+//   T[i][r] -= A[j][i] T[j][r] rs^2   (i > j),
+// and column j is final: L[r][j] = A[r][j] rs (r >= j, zero above), and
+// T[j][r] = T[j][r] rs.
+template <typename T, int J>
+__device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, int q, bool &ok) {
+  constexpr int KJ = J / 4, QJ = J % 4;
+  const T piv = readlane(a[KJ], 16 * QJ + J);
+  ok = ok && piv > T(0);
+  const T rs = rsqrt_nr(piv);
+  const int src = 16 * QJ + r;
+  const T col = lane_fetch(a[KJ], src);  // A[r][j]
+  const T tj = lane_fetch(t[KJ], src);   // T[j][r]
+  const T rs2 = rs * rs;
+  const T w2 = col * rs2, tz = tj * rs2;
+  // column j's final values, kept by column group j % 4 (selects, no branch)
+  const T fa = r >= J ? col * rs : T(0), ft = tj * rs;
+  const bool gt = q > QJ, eq = q == QJ;
+#pragma unroll
+  for (int k = KJ; k < 4; ++k) {
+    const T bc = row_bcast<J>(a[k]);  // A[j][4k + q]
+    const T na = a[k] - w2 * bc, nt = t[k] - tz * bc;
+    if (k > KJ) {
+      a[k] = na;
+      t[k] = nt;
+    } else {
+      const T ka = gt ? na : a[k], kt = gt ? nt : t[k];
+      a[k] = eq ? fa : ka;
+      t[k] = eq ? ft : kt;
+    }
+  }
+}
+template <typename T, int... J>
+__device__ __forceinline__ void diag_steps(T (&a)[4], T (&t)[4], int r, int q, bool &ok,
+                                           std::integer_sequence<int, J...>) {
+  (diag_step<T, J>(a, t, r, q, ok), ...);
+}
+
 template <typename T, int NB, int NT>
 __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatus *ds) {
   typedef Mfma<T> MF;
@@ -563,46 +633,24 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   __syncthreads();
   const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
 
-  // Diagonal block p on wave 0: lane r < 16 holds row r; L_pp into S,
-  // L_pp^-1 into Dinv[p].
+  // Diagonal block p on wave 0: L_pp into S, L_pp^-1 into Dinv[p].  S holds
+  // the lower triangle of the block (the upper one is not kept up to date);
+  // lane 16 q + r reads both triangles from it.
   auto factor_diag = [&](int p) {
-    const int c0 = 16 * p;
-    T v[16], y[16];
+    const int c0 = 16 * p, q = lane >> 4;
+    T a[4], t[4];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      v[c] = S[(c0 + c) * LD + c0 + lr];
-      y[c] = (lr == c) ? T(1) : T(0);
+    for (int k = 0; k < 4; ++k) {
+      const int c = 4 * k + q, lo = lr < c ? lr : c, hi = lr < c ? c : lr;
+      a[k] = S[(c0 + lo) * LD + c0 + hi];
+      t[k] = c == lr ? T(1) : T(0);
     }
     bool ok = true;
-    T my_rs = T(0);
-    // Column j: w = L[lr][j] (lr >= j); the columns c > j lose w L[c][j].
-    // Beside it, the forward elimination of M Y = I with the unit lower
-    // M = L diag(L)^-1, whose column j is now known and whose row j of Y is
-    // final: row lr > j loses M[lr][j] times row j (Y[j][j] = 1).  Row lr of
-    // Y scaled by 1 / L[lr][lr] is row lr of L^-1.
+    diag_steps(a, t, lr, q, ok, std::make_integer_sequence<int, 16>());
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const T piv = readlane(v[j], j);
-      ok = ok && (piv > T(0));
-      const T rs = rsqrt_nr(piv);
-      my_rs = (lr == j) ? rs : my_rs;
-      const T w = v[j] * rs;
-#pragma unroll
-      for (int c = j + 1; c < 16; ++c) v[c] -= w * readlane(w, c);
-      v[j] = lr >= j ? w : T(0);
-      if (j < 15) {
-        const T f = lr > j ? w * rs : T(0);
-#pragma unroll
-        for (int c = 0; c < j; ++c) y[c] -= f * readlane(y[c], j);
-        y[j] -= f;
-      }
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        S[(c0 + c) * LD + c0 + lr] = v[c];
-        Dinv[p][c * kDL + lr] = y[c] * my_rs;
-      }
+    for (int k = 0; k < 4; ++k) {
+      S[(c0 + 4 * k + q) * LD + c0 + lr] = a[k];
+      Dinv[p][lr * kDL + 4 * k + q] = t[k];
     }
     if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
   };
