@@ -528,6 +528,17 @@ __device__ inline float rsqrt_nr(float x) {
   y = y * (1.5f - 0.5f * x * y * y);
   return y;
 }
+// Hardware reciprocal refined by Newton-Raphson steps (y <- y + y (1 - x y)).
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ inline float rcp_nr(float x) {
+  float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
 
 // Lane n of each row of 16 lanes, broadcast to that row (DPP row_newbcast).
 template <int N>
@@ -552,50 +563,45 @@ __device__ inline float lane_fetch(float x, int src) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(4 * src, __float_as_int(x)));
 }
 
-// Cholesky factor L and inverse L^-1 of a 16 x 16 diagonal block on one wave.
-// Lane 16 q + r holds a[k] = A[r][4k + q] of the symmetric trailing matrix
-// (both triangles) and t[k] = T[4k + q][r], column r of the forward
-// elimination L T = I (T = L^-1 at the end).  Column j: pivot A[j][j],
+// Inverse L^-1 of the Cholesky factor of a 16 x 16 diagonal block on one
+// wave (the factor L itself is not needed: the leaf uses only L^-1 of its
+// diagonal blocks).  Lane 16 q + r holds a[k] = A[r][4k + q] of the
+// symmetric trailing matrix (both triangles) and t[k] = T[4k + q][r], column
+// r of the forward elimination L T = I.  Column j: pivot A[j][j],
 // rs = A[j][j]^-1/2, L[i][j] = A[i][j] rs = A[j][i] rs (symmetry), so the
 // values every lane needs, row j at its own columns, come from lane j of its
-// own row of 16 lanes (one DPP broadcast each); the two values from column
-// group j % 4 (A[r][j] and T[j][r]) come over the crossbar.  Then
-//   A[r][c] -= A[r][j] A[j][c] rs^2   (c > j),
-//   T[i][r] -= A[j][i] T[j][r] rs^2   (i > j),
-// and column j is final: L[r][j] = A[r][j] rs (r >= j, zero above), and
-// T[j][r] = T[j][r] rs.
+// own row of 16 lanes (one DPP broadcast each); A[r][j] and T[j][r] come
+// from column group j % 4 over the crossbar.  Then
+//   A[r][c] -= A[r][j] A[j][c] / A[j][j]   (c > j),
+//   T[i][r] -= A[j][i] T[j][r] / A[j][j]   (i > j),
+// and row j of L^-1 is final, T[j][r] rs, stored at once (every column group
+// holds the same values and writes the same addresses).  The entries of
+// columns and rows already final keep being updated in registers, with
+// values nothing reads.
 template <typename T, int J>
-__device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, int q, bool &ok) {
+__device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, T *dinv, bool &ok) {
   constexpr int KJ = J / 4, QJ = J % 4;
   const T piv = readlane(a[KJ], 16 * QJ + J);
   ok = ok && piv > T(0);
-  const T rs = rsqrt_nr(piv);
+  // 1 / A[j][j] carries the updates (and so the next pivot); rs, off that
+  // chain, only the stored row
+  const T inv = rcp_nr(piv), rs = rsqrt_nr(piv);
   const int src = 16 * QJ + r;
   const T col = lane_fetch(a[KJ], src);  // A[r][j]
   const T tj = lane_fetch(t[KJ], src);   // T[j][r]
-  const T rs2 = rs * rs;
-  const T w2 = col * rs2, tz = tj * rs2;
-  // column j's final values, kept by column group j % 4 (selects, no branch)
-  const T fa = r >= J ? col * rs : T(0), ft = tj * rs;
-  const bool gt = q > QJ, eq = q == QJ;
+  const T w2 = col * inv, tz = tj * inv;
+  dinv[r * kDL + J] = tj * rs;  // (L^-1)[j][r], column-major
 #pragma unroll
   for (int k = KJ; k < 4; ++k) {
     const T bc = row_bcast<J>(a[k]);  // A[j][4k + q]
-    const T na = a[k] - w2 * bc, nt = t[k] - tz * bc;
-    if (k > KJ) {
-      a[k] = na;
-      t[k] = nt;
-    } else {
-      const T ka = gt ? na : a[k], kt = gt ? nt : t[k];
-      a[k] = eq ? fa : ka;
-      t[k] = eq ? ft : kt;
-    }
+    a[k] -= w2 * bc;
+    t[k] -= tz * bc;
   }
 }
 template <typename T, int... J>
-__device__ __forceinline__ void diag_steps(T (&a)[4], T (&t)[4], int r, int q, bool &ok,
+__device__ __forceinline__ void diag_steps(T (&a)[4], T (&t)[4], int r, T *dinv, bool &ok,
                                            std::integer_sequence<int, J...>) {
-  (diag_step<T, J>(a, t, r, q, ok), ...);
+  (diag_step<T, J>(a, t, r, dinv, ok), ...);
 }
 
 template <typename T, int NB, int NT>
@@ -633,9 +639,11 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
   __syncthreads();
   const int lr = lane & 15, lg = lane >> 4;  // row in block, column group
 
-  // Diagonal block p on wave 0: L_pp into S, L_pp^-1 into Dinv[p].  S holds
-  // the lower triangle of the block (the upper one is not kept up to date);
-  // lane 16 q + r reads both triangles from it.
+  // Diagonal block p on wave 0: L_pp^-1 into Dinv[p] (L_pp itself is never
+  // read: the panel solve and the inversion use L_pp^-1, and block (p, p) of
+  // S is overwritten by it later).  S holds the lower triangle of the block
+  // (the upper one is not kept up to date); lane 16 q + r reads both
+  // triangles from it.
   auto factor_diag = [&](int p) {
     const int c0 = 16 * p, q = lane >> 4;
     T a[4], t[4];
@@ -646,12 +654,7 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
       t[k] = c == lr ? T(1) : T(0);
     }
     bool ok = true;
-    diag_steps(a, t, lr, q, ok, std::make_integer_sequence<int, 16>());
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      S[(c0 + 4 * k + q) * LD + c0 + lr] = a[k];
-      Dinv[p][lr * kDL + 4 * k + q] = t[k];
-    }
+    diag_steps(a, t, lr, Dinv[p], ok, std::make_integer_sequence<int, 16>());
     if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
   };
   // Trailing block (i, j) -= L_ip L_jp^T (one wave, MFMA).

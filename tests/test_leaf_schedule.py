@@ -144,12 +144,14 @@ def test_every_block_of_the_inverse_is_written():
 
 
 def diag_lanes(S):
-    """Lane-level model of the 16 x 16 diagonal factorisation on one wave of
-    64 lanes, lane 16 q + r holding a[k] = A[r][4k + q] (both triangles, read
-    from the lower one) and t[k] = T[4k + q][r] of the forward elimination
-    L T = I.  Column j: the pivot from lane 16 (j % 4) + j; A[r][j] and
-    T[j][r] from lane 16 (j % 4) + r (the crossbar); row j at a lane's own
-    columns from lane j of its own row of 16 lanes (the DPP broadcast)."""
+    """Lane-level model of the 16 x 16 diagonal step on one wave of 64 lanes,
+    lane 16 q + r holding a[k] = A[r][4k + q] (both triangles, read from the
+    lower one) and t[k] = T[4k + q][r] of the forward elimination L T = I.
+    Column j: the pivot from lane 16 (j % 4) + j; A[r][j] and T[j][r] from
+    lane 16 (j % 4) + r (the crossbar); row j at a lane's own columns from
+    lane j of its own row of 16 lanes (the DPP broadcast).  Row j of L^-1 is
+    stored at step j; the registers of final rows and columns keep being
+    updated with values that are never read again."""
     lane = np.arange(64)
     r, q = lane & 15, lane >> 4
     a = np.zeros((64, 4))
@@ -158,39 +160,31 @@ def diag_lanes(S):
         c = 4 * k + q
         a[:, k] = S[np.maximum(r, c), np.minimum(r, c)]
         t[:, k] = (c == r)
+    Y = np.full((16, 16), np.nan)
     for j in range(16):
         kj, qj = j // 4, j % 4
         rs = 1.0 / np.sqrt(a[16 * qj + j, kj])
         src = 16 * qj + r
         col, tj = a[src, kj].copy(), t[src, kj].copy()
         w2, tz = col * rs * rs, tj * rs * rs
-        fa, ft = np.where(r >= j, col * rs, 0.0), tj * rs
+        Y[j, r] = tj * rs  # every column group stores the same row
         for k in range(kj, 4):
             bc = a[16 * q + j, k].copy()
-            na, nt = a[:, k] - w2 * bc, t[:, k] - tz * bc
-            if k > kj:
-                a[:, k], t[:, k] = na, nt
-            else:
-                a[:, k] = np.where(q == qj, fa, np.where(q > qj, na, a[:, k]))
-                t[:, k] = np.where(q == qj, ft, np.where(q > qj, nt, t[:, k]))
-    L, Y = np.zeros((16, 16)), np.zeros((16, 16))
-    for k in range(4):
-        c = 4 * k + q
-        L[r, c] = a[:, k]
-        Y[c, r] = t[:, k]
-    return L, Y
+            a[:, k] -= w2 * bc
+            t[:, k] -= tz * bc
+    return Y
 
 
-def test_diagonal_lane_scheme_gives_factor_and_inverse():
+def test_diagonal_lane_scheme_gives_the_inverse_factor():
     """The lane scheme reads only the lower triangle (the upper one of the
-    block in LDS is stale) and returns L with zeros above the diagonal and
-    L^-1."""
+    block in LDS is stale) and stores every entry of L^-1, zeros above the
+    diagonal included."""
     rng = np.random.default_rng(7)
     B = rng.standard_normal((16, 16))
     A = B @ B.T + 4 * np.eye(16)
     S = np.tril(A) + np.triu(rng.standard_normal((16, 16)) * 1e3, 1)
-    L, Y = diag_lanes(S)
-    ref = np.linalg.cholesky(A)
-    assert np.abs(L - ref).max() < 1e-13
-    assert np.abs(Y - np.linalg.inv(ref)).max() < 1e-13
-    assert np.all(np.triu(L, 1) == 0) and np.all(np.triu(Y, 1) == 0)
+    Y = diag_lanes(S)
+    ref = np.linalg.inv(np.linalg.cholesky(A))
+    assert not np.isnan(Y).any()
+    assert np.abs(Y - ref).max() < 1e-13
+    assert np.all(np.triu(Y, 1) == 0)
