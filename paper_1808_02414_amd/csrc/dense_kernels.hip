@@ -574,23 +574,23 @@ __device__ inline float lane_fetch(float x, int src) {
 // from column group j % 4 over the crossbar.  Then
 //   A[r][c] -= A[r][j] A[j][c] / A[j][j]   (c > j),
 //   T[i][r] -= A[j][i] T[j][r] / A[j][j]   (i > j),
-// and row j of L^-1 is final, T[j][r] rs, stored at once (every column group
-// holds the same values and writes the same addresses).  The entries of
-// columns and rows already final keep being updated in registers, with
-// values nothing reads.
+// and row j of T is final, stored at once (every column group holds the same
+// values and writes the same addresses); row j of L^-1 is T[j][.] / sqrt(A[j][j]),
+// scaled after the last column so that no square root sits in the column
+// loop.  The entries of columns and rows already final keep being updated
+// in registers, with values nothing reads.
 template <typename T, int J>
-__device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, T *dinv, bool &ok) {
+__device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, T &pv, T *dinv, bool &ok) {
   constexpr int KJ = J / 4, QJ = J % 4;
   const T piv = readlane(a[KJ], 16 * QJ + J);
   ok = ok && piv > T(0);
-  // 1 / A[j][j] carries the updates (and so the next pivot); rs, off that
-  // chain, only the stored row
-  const T inv = rcp_nr(piv), rs = rsqrt_nr(piv);
+  pv = r == J ? piv : pv;  // lane r keeps pivot r for the final scaling
+  const T inv = rcp_nr(piv);
   const int src = 16 * QJ + r;
   const T col = lane_fetch(a[KJ], src);  // A[r][j]
   const T tj = lane_fetch(t[KJ], src);   // T[j][r]
   const T w2 = col * inv, tz = tj * inv;
-  dinv[r * kDL + J] = tj * rs;  // (L^-1)[j][r], column-major
+  dinv[r * kDL + J] = tj;  // T[j][r], column-major; row j is scaled at the end
 #pragma unroll
   for (int k = KJ; k < 4; ++k) {
     const T bc = row_bcast<J>(a[k]);  // A[j][4k + q]
@@ -599,9 +599,9 @@ __device__ __forceinline__ void diag_step(T (&a)[4], T (&t)[4], int r, T *dinv, 
   }
 }
 template <typename T, int... J>
-__device__ __forceinline__ void diag_steps(T (&a)[4], T (&t)[4], int r, T *dinv, bool &ok,
+__device__ __forceinline__ void diag_steps(T (&a)[4], T (&t)[4], int r, T &pv, T *dinv, bool &ok,
                                            std::integer_sequence<int, J...>) {
-  (diag_step<T, J>(a, t, r, dinv, ok), ...);
+  (diag_step<T, J>(a, t, r, pv, dinv, ok), ...);
 }
 
 template <typename T, int NB, int NT>
@@ -654,7 +654,15 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
       t[k] = c == lr ? T(1) : T(0);
     }
     bool ok = true;
-    diag_steps(a, t, lr, Dinv[p], ok, std::make_integer_sequence<int, 16>());
+    T pv = T(1);
+    diag_steps(a, t, lr, pv, Dinv[p], ok, std::make_integer_sequence<int, 16>());
+    // row r of L^-1 = row r of T / sqrt(pivot r); lane 16 q + r scales its
+    // columns 4k + q, which other lanes of this wave stored above
+    const T rs = rsqrt_nr(pv);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Dinv[p][(4 * k + q) * kDL + lr] *= rs;
     if (!ok && lane == 0) report_error(ds, UCOV_EGAUGE, (int)((o + c0) / 9));
   };
   // Trailing block (i, j) -= L_ip L_jp^T (one wave, MFMA).

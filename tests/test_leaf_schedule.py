@@ -149,9 +149,10 @@ def diag_lanes(S):
     lower one) and t[k] = T[4k + q][r] of the forward elimination L T = I.
     Column j: the pivot from lane 16 (j % 4) + j; A[r][j] and T[j][r] from
     lane 16 (j % 4) + r (the crossbar); row j at a lane's own columns from
-    lane j of its own row of 16 lanes (the DPP broadcast).  Row j of L^-1 is
-    stored at step j; the registers of final rows and columns keep being
-    updated with values that are never read again."""
+    lane j of its own row of 16 lanes (the DPP broadcast).  Row j of T is
+    stored at step j and scaled by the pivot's inverse square root after the
+    last column; the registers of final rows and columns keep being updated
+    with values that are never read again."""
     lane = np.arange(64)
     r, q = lane & 15, lane >> 4
     a = np.zeros((64, 4))
@@ -160,18 +161,23 @@ def diag_lanes(S):
         c = 4 * k + q
         a[:, k] = S[np.maximum(r, c), np.minimum(r, c)]
         t[:, k] = (c == r)
-    Y = np.full((16, 16), np.nan)
+    T = np.full((16, 16), np.nan)  # rows of T as stored, before their scaling
+    pv = np.ones(64)
     for j in range(16):
         kj, qj = j // 4, j % 4
-        rs = 1.0 / np.sqrt(a[16 * qj + j, kj])
+        piv = a[16 * qj + j, kj]
+        pv = np.where(r == j, piv, pv)
         src = 16 * qj + r
         col, tj = a[src, kj].copy(), t[src, kj].copy()
-        w2, tz = col * rs * rs, tj * rs * rs
-        Y[j, r] = tj * rs  # every column group stores the same row
+        w2, tz = col / piv, tj / piv
+        T[j, r] = tj  # every column group stores the same row
         for k in range(kj, 4):
             bc = a[16 * q + j, k].copy()
             a[:, k] -= w2 * bc
             t[:, k] -= tz * bc
+    Y = T.copy()
+    for k in range(4):  # lane 16 q + r scales row r at its columns 4k + q
+        Y[r, 4 * k + q] = T[r, 4 * k + q] / np.sqrt(pv)
     return Y
 
 
