@@ -612,6 +612,7 @@ __global__ __launch_bounds__(kFillThreads) void k_pair_fill_cam(
 // per camera: diagonal block Z_ii and the rotation rows of the nullspace
 // ---------------------------------------------------------------------------
 constexpr int kDiagVals = 45 + 6 + 9;  // Z_ii upper triangle, J_r^T J_r, J_r^T B
+constexpr int kDiagWaves = 2;           // waves per camera in k_camera_diag
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -619,24 +620,43 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sums over the 64 lanes of a wave of 64 values per lane, lane l ending
+// with the sum of value l: at distance d = 32, 16, .., 1 every lane keeps the
+// half of its remaining values that bit d of its lane index selects and
+// adds its partner's copy of that half (63 exchanges instead of 6 per value).
+template <int V>
+__device__ inline void wave_sums_halving(double (&x)[64], int lane) {
+  if constexpr (V > 1) {
+    constexpr int H = V / 2;
+    const bool up = lane & H;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = up ? x[H + i] : x[i], send = up ? x[i] : x[H + i];
+      x[i] = keep + __shfl_xor(send, H, 64);
+    }
+    wave_sums_halving<H>(x, lane);
+  }
+}
+
 // Z_ii = sum over the observations a of camera i of J_P^T (I - Y J_X^T) J_P
 // (whitened), i.e. U_i minus the point-eliminated terms.  The rotation
 // nullspace block solves J_r H_r = B in least squares over the camera's
 // observation rows, B = -J_X [X_j - C_i]x (the known rows of H in the rotation
 // columns are [C_i]x for the centre and [X_j]x for the points, and J_C = -J_X).
-__global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t *bin_ptr,
-                                                    const int2 *pairs, const double *rec,
-                                                    const int32_t *slot_pt, double *zdiag,
-                                                    double *hc, DevStatus *ds) {
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_camera_diag(SceneDev sc, const int64_t *bin_ptr,
+                                                       const int2 *pairs, const double *rec,
+                                                       const int32_t *slot_pt, double *zdiag,
+                                                       double *hc, DevStatus *ds) {
   const int i = blockIdx.x;
   const int64_t bin = bin_of(sc, i, i);
   const int64_t e0 = bin_ptr[bin], e1 = bin_ptr[bin + 1];
-  double acc[kDiagVals];
+  double acc[64];  // kDiagVals sums, padded for the halving exchange
 #pragma unroll
-  for (int k = 0; k < kDiagVals; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 64; ++k) acc[k] = 0.0;
   const double C0 = sc.cams[9 * (int64_t)i + 3], C1 = sc.cams[9 * (int64_t)i + 4],
                C2 = sc.cams[9 * (int64_t)i + 5];
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 64 * W) {
     const int a = pairs[e].x;
     // the record's first 30 values (J_P, J_X, Y) with 16-byte loads
     const double2 *r2 = reinterpret_cast<const double2 *>(rec + (int64_t)a * kRec);
@@ -696,26 +716,26 @@ __global__ __launch_bounds__(256) void k_camera_diag(SceneDev sc, const int64_t 
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) acc[idx++] += jp[0][rr] * B[0][cc] + jp[1][rr] * B[1][cc];
   }
-  __shared__ double part[4][kDiagVals];
+  __shared__ double part[W][64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kDiagVals; ++k) {
-    double v = wave_sum(acc[k]);
-    if (lane == 0) part[wid][k] = v;
-  }
+  wave_sums_halving<64>(acc, lane);
+  part[wid][lane] = acc[0];  // this wave's sum of value `lane`
   __syncthreads();
   __shared__ double tot[kDiagVals];
   if (threadIdx.x < kDiagVals) {
     const int k = threadIdx.x;
-    tot[k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+    double v = part[0][k];
+#pragma unroll
+    for (int w = 1; w < W; ++w) v += part[w][k];
+    tot[k] = v;
   }
   __syncthreads();
   // diagonal block, full 9x9 row-major
-  if (threadIdx.x < 81) {
-    const int rr = threadIdx.x / 9, cc = threadIdx.x % 9;
+  for (int u = threadIdx.x; u < 81; u += 64 * W) {
+    const int rr = u / 9, cc = u % 9;
     const int a = rr < cc ? rr : cc, b = rr < cc ? cc : rr;
     const int idx = a * 9 - a * (a - 1) / 2 + (b - a);
-    zdiag[81 * (int64_t)i + threadIdx.x] = tot[idx];
+    zdiag[81 * (int64_t)i + u] = tot[idx];
   }
   if (threadIdx.x == 0) {
     if (e1 == e0) report_error(ds, UCOV_EGAUGE, i);
@@ -1576,8 +1596,8 @@ void launch_pair_fill_cam(const SceneDev &sc, SceneWork &w, int max_scene_cams, 
 }
 
 void launch_camera_diag(const SceneDev &sc, SceneWork &w, DevStatus *ds, hipStream_t st) {
-  hipLaunchKernelGGL(k_camera_diag, dim3(sc.n), dim3(256), 0, st, sc, w.bin_ptr, w.pairs,
-                     w.rec, w.slot_pt, w.zdiag, w.hc, ds);
+  hipLaunchKernelGGL(k_camera_diag<kDiagWaves>, dim3(sc.n), dim3(64 * kDiagWaves), 0, st, sc,
+                     w.bin_ptr, w.pairs, w.rec, w.slot_pt, w.zdiag, w.hc, ds);
 }
 
 void launch_gauge(int64_t N, const double *hc, double *q, const double *zdiag,
