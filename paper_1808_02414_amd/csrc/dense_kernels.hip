@@ -798,23 +798,30 @@ __device__ __forceinline__ void leaf_body(T *A, int64_t lda, int64_t o, DevStatu
         const int w0 = look ? 1 : 0, nw = look ? NW - 1 : NW;
         const int first = look ? 1 : 0;      // block (p+1, p+1) is wave 0's
         const int ncol = look ? p : p + 1;   // columns c < p; the last panel adds Y(p, p)
-        for (int t = wid - w0; t < ncol + (ntr - first); t += nw) {
-          if (t < ncol) {
-            inv_y(p, t);
-            if (t < p) {
-              __builtin_amdgcn_s_waitcnt(0);  // Y(p, t) is read back by this wave
-              __builtin_amdgcn_wave_barrier();
-              for (int i = p + 1; i < NPAN; ++i) inv_col(p, i, t);
-            }
-          } else {
-            int jj = 0, rem = t - ncol + first;  // -> (ii, jj) in the lower triangle of m x m blocks
-            while (rem >= m - jj) {
-              rem -= m - jj;
-              ++jj;
-            }
-            trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
+        const int u = wid - w0;              // this wave among the nw (ncol <= nw)
+        if (u < ncol) {                      // inversion column u, a chain of NPAN - p blocks
+          inv_y(p, u);
+          if (u < p) {
+            __builtin_amdgcn_s_waitcnt(0);  // Y(p, u) is read back by this wave
+            __builtin_amdgcn_wave_barrier();
+            for (int i = p + 1; i < NPAN; ++i) inv_col(p, i, u);
           }
         }
+        auto trail = [&](int j) {
+          int jj = 0, rem = j + first;  // -> (ii, jj) in the lower triangle of m x m blocks
+          while (rem >= m - jj) {
+            rem -= m - jj;
+            ++jj;
+          }
+          trailing_block(p, p + 1 + jj + rem, p + 1 + jj);
+        };
+        // trailing blocks go to the waves without a column first, up to a
+        // column's length each, and the rest round-robin over all waves
+        const int ntrail = ntr - first, nfree = nw - ncol;
+        const int cap = min(ntrail, nfree * (NPAN - p));
+        if (u >= ncol)
+          for (int j = u - ncol; j < cap; j += nfree) trail(j);
+        for (int j = cap + u; j < ntrail; j += nw) trail(j);
       }
     }
     __syncthreads();

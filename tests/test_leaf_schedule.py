@@ -194,3 +194,32 @@ def test_diagonal_lane_scheme_gives_the_inverse_factor():
     assert not np.isnan(Y).any()
     assert np.abs(Y - ref).max() < 1e-13
     assert np.all(np.triu(Y, 1) == 0)
+
+
+@pytest.mark.parametrize("NB,NT", [(128, 512), (64, 256)])
+def test_second_phase_deals_every_trailing_block_once(NB, NT):
+    """The kernel's dealing of the second phase: inversion column u to wave
+    u (one chain of NPAN - p block products each), the trailing blocks first
+    to the waves without a column, up to a column's length each, the rest
+    round-robin.  Every block is dealt exactly once, and no wave gets more
+    than a column's chain plus its share of the remainder."""
+    P, NW = NB // 16, NT // 64
+    for p in range(P):
+        m = P - 1 - p
+        look = p + 1 < P
+        nw, first = (NW - 1, 1) if look else (NW, 0)
+        ncol = p if look else p + 1
+        assert ncol <= nw
+        ntrail = m * (m + 1) // 2 - first
+        nfree = nw - ncol
+        cap = min(ntrail, nfree * (P - p))
+        dealt, loads = [], []
+        for u in range(nw):
+            js = list(range(u - ncol, cap, nfree)) if u >= ncol else []
+            js += list(range(cap + u, ntrail, nw))
+            dealt += js
+            chain = (1 + (m if u < p else 0)) if u < ncol else 0
+            loads.append(chain + len(js))
+        assert sorted(dealt) == list(range(ntrail))
+        rest = max(0, ntrail - cap)
+        assert max(loads) <= max(P - p, -(-cap // max(nfree, 1))) + -(-rest // nw)
